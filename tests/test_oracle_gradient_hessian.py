@@ -1,0 +1,170 @@
+"""Pins of the oracle's reduced gradient (eq. e:rgrad), Gauss--Newton Hessian
+matvec (eq. e:matvec with eqs. e:incstate, e:incadj), PCG (Algorithm 2) and
+Gauss--Newton solve (Algorithm 1).
+
+Exact cases: v = 0 (the zero-velocity Hessian of Section 2.5.6 is then the
+GN Hessian exactly), constant images, the inverse-crime point (m1 = m0
+transported by v*, where lambda = 0 and g = alpha L v*), whole-voxel
+translations (every SL step is a shift, so H is exactly symmetric).
+Convergence: finite differences of J and of g. Because the method is
+optimize-then-discretize, discrete g and H are consistent with the discrete J
+only up to discretisation error (Section 2.3); the gap must shrink under
+refinement of n and n_t.
+Brute force: the 8^3 Hessian assembled column by column.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from synthetic import bandlimited_velocity, gaussian_blobs
+
+
+def _problem(n, nt, seed=1, sigma=0.6):
+    g = O.Grid((n, n, n))
+    m0 = gaussian_blobs(g.n, seed, sigma=sigma)
+    vs = bandlimited_velocity(g.n, seed + 1, 2, 0.8)
+    m1 = O.transport(g, m0, vs, nt)
+    return g, m0, m1, vs
+
+
+def test_zero_velocity_closed_forms():
+    g, m0, m1, _ = _problem(16, 4)
+    alpha, nt = 1e-2, 4
+    st = O.setup_velocity(g, m0, m1, np.zeros((3,) + g.n), alpha, nt, 1)
+    gm0 = O.spectral_gradient(g, m0)
+    # g = -(m0 - m1) grad m0 (Section 2.5.6, zero velocity approximation)
+    assert np.abs(st.g - (-(m0 - m1) * gm0)).max() <= 1e-13 * np.abs(st.g).max()
+    vt = bandlimited_velocity(g.n, 9, 3, 1.0)
+    # m~(1) = -grad m0 . v~ and H v~ = alpha L v~ + (grad m0 (x) grad m0) v~
+    mt = O.incremental_state(st, vt)
+    ref_mt = -np.sum(gm0 * vt, axis=0)
+    assert np.abs(mt - ref_mt).max() <= 1e-13 * np.abs(ref_mt).max()
+    hv = O.hessian_matvec(st, vt)
+    ref = O.regularization_operator(g, vt, alpha, 1) + np.sum(gm0 * vt, axis=0) * gm0
+    assert np.abs(hv - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_inverse_crime_point():
+    g, m0, m1, vs = _problem(16, 4)
+    for p in (1, 2):
+        st = O.setup_velocity(g, m0, m1, vs, 3e-2, 4, p)
+        assert np.abs(st.m[-1] - m1).max() == 0.0
+        assert all(np.abs(l).max() == 0.0 for l in st.lam)
+        assert np.array_equal(st.g, O.regularization_operator(g, vs, 3e-2, p))
+        assert st.J_dist == 0.0
+
+
+def test_constant_image():
+    n = (16, 16, 16)
+    g = O.Grid(n)
+    m = np.full(n, 0.4)
+    v = bandlimited_velocity(n, 5, 3, 1.0)
+    st = O.setup_velocity(g, m, m, v, 1e-2, 4, 2)
+    assert np.abs(st.g - O.regularization_operator(g, v, 1e-2, 2)).max() < 1e-12
+    vt = bandlimited_velocity(n, 6, 3, 1.0)
+    ref = O.regularization_operator(g, vt, 1e-2, 2)
+    assert np.abs(O.hessian_matvec(st, vt) - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def _fd_gaps(n, nt):
+    g, m0, m1, vs = _problem(n, nt)
+    alpha = 1e-2
+    v = 0.4 * bandlimited_velocity(g.n, 3, 2, 0.8)
+    w = bandlimited_velocity(g.n, 4, 3, 1.0)
+    eps = 1e-4
+    st = O.setup_velocity(g, m0, m1, v, alpha, nt, 1)
+    jp = O.objective(g, m0, m1, v + eps * w, alpha, nt, 1)
+    jm = O.objective(g, m0, m1, v - eps * w, alpha, nt, 1)
+    fd = (jp - jm) / (2 * eps)
+    grad_gap = abs(fd - g.inner(st.g, w)) / abs(fd)
+    st_star = O.setup_velocity(g, m0, m1, vs, alpha, nt, 1)
+    gp = O.setup_velocity(g, m0, m1, vs + eps * w, alpha, nt, 1).g
+    gm = O.setup_velocity(g, m0, m1, vs - eps * w, alpha, nt, 1).g
+    hv = O.hessian_matvec(st_star, w)
+    hess_gap = np.abs((gp - gm) / (2 * eps) - hv).max() / np.abs(hv).max()
+    return grad_gap, hess_gap
+
+
+def test_finite_difference_consistency_converges():
+    g1, h1 = _fd_gaps(16, 4)
+    g2, h2 = _fd_gaps(32, 8)
+    # a dropped term or a flipped sign leaves an O(1) gap that does not shrink
+    assert g2 < 0.03 and g1 / g2 > 4, (g1, g2)
+    assert h2 < 0.03 and h1 / h2 > 3, (h1, h2)
+
+
+def _assemble(op, shape):
+    N = int(np.prod(shape))
+    M = np.empty((N, N))
+    e = np.zeros(N)
+    for i in range(N):
+        e[:] = 0.0
+        e[i] = 1.0
+        M[:, i] = op(e.reshape(shape)).ravel()
+    return M
+
+
+def test_brute_force_8cubed_hessian():
+    g, m0, m1, vs = _problem(8, 2, sigma=0.9)
+    alpha = 1e-2
+    st = O.setup_velocity(g, m0, m1, 0.5 * vs, alpha, 2, 1)
+    shape = (3,) + g.n
+    H = _assemble(lambda e: O.hessian_matvec(st, e), shape)
+    R = _assemble(lambda e: O.regularization_operator(g, e, alpha, 1), shape)
+    D = H - R
+    ev = np.linalg.eigvalsh(0.5 * (D + D.T))
+    assert ev.min() >= -1e-4 * ev.max()                     # GN data part is PSD
+    assert np.abs(D - D.T).max() <= 0.1 * np.abs(D).max()  # symmetric up to discretisation
+    assert np.abs(R - R.T).max() <= 1e-12 * np.abs(R).max()
+
+
+def test_translation_hessian_exactly_symmetric_and_pcg():
+    n, nt = 8, 2
+    g = O.Grid((n, n, n))
+    m0 = gaussian_blobs(g.n, 3, sigma=0.9)
+    shift = np.array([1, 0, -1])
+    v = np.stack([np.full(g.n, shift[a] * g.h[a] * nt) for a in range(3)])
+    m1 = gaussian_blobs(g.n, 4, sigma=0.9)
+    alpha = 1e-2
+    st = O.setup_velocity(g, m0, m1, v, alpha, nt, 1)
+    shape = (3,) + g.n
+    H = _assemble(lambda e: O.hessian_matvec(st, e), shape)
+    assert np.abs(H - H.T).max() <= 1e-12 * np.abs(H).max()
+    # PCG (Algorithm 2) for 10 iterations against SciPy's preconditioned CG
+    Minv = spla.LinearOperator(H.shape, matvec=lambda r: O.precondition(
+        g, r.reshape(shape), alpha, 1).ravel())
+    Hop = spla.LinearOperator(H.shape, matvec=lambda x: H @ x)
+    ref, _ = spla.cg(Hop, -st.g.ravel(), x0=np.zeros(H.shape[0]), rtol=0.0, atol=0.0,
+                     maxiter=10, M=Minv)
+    vt, its, hist, _ = O.pcg(lambda s: O.hessian_matvec(st, s),
+                             lambda r: O.precondition(g, r, alpha, 1),
+                             st.g, fixed_iters=10)
+    assert its == 10
+    assert np.abs(vt.ravel() - ref).max() <= 1e-8 * np.abs(ref).max()
+    # and run to convergence: the dense solution
+    vt_full, its_full, _, _ = O.pcg(lambda s: O.hessian_matvec(st, s),
+                                    lambda r: O.precondition(g, r, alpha, 1),
+                                    st.g, fixed_iters=300)
+    dense = np.linalg.solve(H, -st.g.ravel())
+    assert np.abs(vt_full.ravel() - dense).max() <= 1e-8 * np.abs(dense).max()
+
+
+def test_forcing_rule():
+    assert O.forcing_tolerance(4.0) == 2.0                 # eta = 1/2
+    assert abs(O.forcing_tolerance(0.04) - 0.2 * 0.04) < 1e-15
+    assert abs(O.forcing_tolerance(0.04, "quadratic") - 0.04 * 0.04) < 1e-15
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_gn_solve_invariants(p):
+    n, nt = 16, 4
+    g, m0, m1, vs = _problem(n, nt)
+    alpha = 1e-2 if p == 1 else 1e-3
+    v, st, stats = O.gn_solve(g, m0, m1, nt, p, [alpha], gtol=5e-2, max_gn=20)
+    hist = [h["J"] for h in stats.history]
+    assert all(b < a for a, b in zip(hist, hist[1:]))        # Armijo: monotone
+    assert stats.rel_grad <= 5e-2 and not stats.warnings
+    assert stats.J < stats.J0 and stats.rel_mismatch < 0.5
+    assert O.deformation_determinant(g, v, nt).min() > 0
+    assert stats.pde_solves == 2 + 2 * stats.gn_iters + 2 * stats.matvecs + stats.ls_trials
