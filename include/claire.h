@@ -1,0 +1,209 @@
+/*
+ * claire.h -- C ABI of the MI355X (gfx950) Gauss--Newton--Krylov
+ * diffeomorphic registration engine.
+ *
+ * Problem (Section 2.2, eq. e:varopt-claire): given a template image m0 and a
+ * reference image m1 on the periodic domain [0, 2*pi)^3, find a stationary
+ * velocity v minimising
+ *     J(v) = 1/2 ||m(1) - m1||^2 + alpha/2 <L v, v>,
+ * where m solves the transport equation d_t m + grad m . v = 0, m(0) = m0,
+ * and L = (-Laplacian)^p is the H^p seminorm operator (p = 1 or 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid:    n1 x n2 x n3 nodes x_i = i * 2*pi / n_a (Section 2.5.1). Each n_a
+ *          must be a power of two between 8 and 1024.
+ * Layout:  scalar fields are float32, C-contiguous [n1][n2][n3] (x3 fastest);
+ *          vector fields are structure-of-arrays [3][n1][n2][n3].
+ * Memory:  every float/double array argument is a DEVICE pointer unless its
+ *          comment says "host". The caller owns all argument memory; the
+ *          library never frees it and keeps no pointer to it after a call
+ *          returns (inputs are copied into the context where needed).
+ * Streams: all device work is enqueued on the hipStream_t passed (as void*)
+ *          at context creation or to the stateless call; NULL means the
+ *          default stream. Calls that return host scalars synchronise it.
+ * Errors:  every int-returning call returns CLAIRE_OK (0) on success, a
+ *          negative CLAIRE_E* code on failure (outputs are then undefined),
+ *          or a positive CLAIRE_W* code when it finished with a warning.
+ *          claire_last_error() gives a message for the calling thread.
+ *          Nothing throws across the ABI and nothing exits the process.
+ * Threads: a context may be used by one thread at a time.
+ */
+#ifndef CLAIRE_H
+#define CLAIRE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum claire_status {
+    CLAIRE_OK = 0,
+    CLAIRE_EINVAL = -1,      /* bad argument: NULL pointer, size, nt < 1, alpha <= 0 */
+    CLAIRE_ENOMEM = -2,      /* device allocation failed */
+    CLAIRE_EDEVICE = -3,     /* HIP runtime error */
+    CLAIRE_ENONFINITE = -4,  /* a NaN/Inf appeared in the objective or gradient */
+    CLAIRE_ESTATE = -5,      /* call out of order (e.g. matvec before set_velocity) */
+    CLAIRE_WNOTCONV = 1,     /* Gauss--Newton stopped at max_gn iterations */
+    CLAIRE_WLINESEARCH = 2,  /* Armijo line search found no acceptable step */
+    CLAIRE_WPCGMAX = 3,      /* PCG hit max_pcg before its forcing tolerance */
+    CLAIRE_WDETBOUND = 4     /* det F(1) <= 0 somewhere (map not diffeomorphic) */
+};
+
+/* Options of the Gauss--Newton--Krylov solve (Section 2.5.5, Algorithms 1-2,
+ * Section 2.6). claire_opts_default() fills the paper's defaults. */
+typedef struct claire_opts {
+    int reg_order;              /* 1: H1 seminorm (symbol |k|^2); 2: H2 seminorm (|k|^4) */
+    int precision;              /* 0: float32 fields and FFTs (the only value accepted) */
+    double gtol;                /* stop when ||g||_inf <= gtol ||g_0||_inf (default 5e-2) */
+    double gabs;                /* ... or when ||g||_inf <= gabs (default 1e-6) */
+    int forcing;                /* PCG forcing: 0 superlinear eta = min(1/2, sqrt||g||_inf),
+                                   1 quadratic eta = min(1/2, ||g||_inf) */
+    int max_gn;                 /* Gauss--Newton iterations per continuation level (50) */
+    int max_pcg;                /* PCG matvecs per Newton step (100) */
+    int fixed_pcg_iters;        /* > 0: run exactly this many PCG matvecs per step */
+    int max_linesearch;         /* Armijo trials, step halved each time (16) */
+    double armijo_c1;           /* sufficient-decrease constant (1e-4) */
+    const double *alpha_levels; /* host array: continuation weights, solved in order,
+                                   each level warm-started from the previous one
+                                   (Section 2.6). NULL: the single alpha argument. */
+    int n_levels;               /* length of alpha_levels */
+    int compute_det;            /* 1: report det F(1) statistics at the end */
+} claire_opts;
+
+/* Statistics of a solve (row labels of the paper's result tables). */
+typedef struct claire_stats {
+    int gn_iters;               /* accepted Gauss--Newton steps, all levels */
+    int matvecs;                /* Hessian matvecs */
+    int pde_solves;             /* state + adjoint + incremental solves */
+    int linesearch_trials;      /* objective evaluations in the line search */
+    int pcg_max_hits;           /* Newton steps where PCG hit max_pcg */
+    double J0;                  /* objective at the initial velocity, first level */
+    double J;                   /* objective at exit */
+    double rel_mismatch;        /* ||m(1) - m1||_2 / ||m0 - m1||_2 at exit */
+    double rel_grad;            /* ||g||_inf / ||g_0||_inf at exit, last level */
+    double det_min, det_mean, det_max; /* det F(1), when compute_det = 1 */
+    long long det_nonpositive;  /* voxels with det F(1) <= 0 */
+    double seconds;             /* wall time of the solve (host clock) */
+} claire_stats;
+
+typedef struct claire_ctx claire_ctx;
+
+/* Fill *opts with the defaults listed above (reg_order 1). */
+void claire_opts_default(claire_opts *opts);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *claire_last_error(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context for an n1 x n2 x n3 grid (nx is a host array), nt time
+ * steps (h_t = 1/nt, Section 2.5.1), regularisation weight alpha > 0 and
+ * order reg_order (1 or 2). Allocates the context's device workspace on the
+ * current HIP device (about (30 + 5 nt) float32 fields). */
+int claire_ctx_create(claire_ctx **out, const int nx[3], int nt, double alpha,
+                      int reg_order, void *stream);
+int claire_ctx_destroy(claire_ctx *ctx);
+
+/* Change alpha (continuation). Invalidates the cached gradient. */
+int claire_ctx_set_alpha(claire_ctx *ctx, double alpha);
+
+/* Copy the template m0 and the reference m1 ([n] each) into the context. */
+int claire_ctx_set_images(claire_ctx *ctx, const float *m0, const float *m1);
+
+/* Per-velocity setup at v ([3][n]), Algorithm 1 lines 3-6: RK2 backtrace of
+ * the characteristics of +v and -v (Section 2.5.2), state solve
+ * (eq. e:transport) keeping m^j and grad m^j for j = 0..nt (spectral,
+ * Section 2.5.3), objective J (eq. e:varopt-claire), adjoint
+ * (eq. e:adjoint) and reduced gradient (eq. e:rgrad). */
+int claire_ctx_set_velocity(claire_ctx *ctx, const float *v);
+
+/* Results of the last set_velocity: g ([3][n], device, may be NULL) and
+ * J (host double, may be NULL). */
+int claire_ctx_gradient(claire_ctx *ctx, float *g, double *J);
+
+/* Objective J(v) alone (backtrace, state, J): one Armijo trial. J is a host
+ * double. Leaves the gradient cache invalid. */
+int claire_ctx_objective(claire_ctx *ctx, const float *v, double *J);
+
+/* Gauss--Newton Hessian matvec at the velocity of the last set_velocity,
+ * eq. (e:matvec) with the incremental state (e:incstate) and incremental
+ * adjoint (e:incadj), lambda-terms dropped (Section 2.5.5):
+ * Hvt = alpha L vt + int_0^1 lambda~ grad m dt. vt and Hvt are [3][n] and
+ * must not overlap. */
+int claire_ctx_hessian_matvec(claire_ctx *ctx, const float *vt, float *Hvt);
+
+/* Regularisation preconditioner z = (alpha L)^{-1} r, k = 0 mode passed
+ * through (Sections 2.5.5-2.5.6). r, z: [3][n]; may alias. */
+int claire_ctx_precond(claire_ctx *ctx, const float *r, float *z);
+
+/* Gauss--Newton--Krylov solve (Algorithm 1 with Algorithm 2 inside) from the
+ * initial guess in v_inout ([3][n]); the solution overwrites it. opts and
+ * stats (host) may be NULL. Returns a CLAIRE_W* code on early exit. */
+int claire_ctx_solve(claire_ctx *ctx, const claire_opts *opts, float *v_inout,
+                     claire_stats *stats);
+
+/* Deformation gradient check (appendix, eq. e:def-grad): transport F with
+ * d_t F + (v.grad) F = (grad v) F, F(0) = I, for the velocity of the last
+ * set_velocity, and evaluate det F(1) in float64. det_out ([n] float64,
+ * device) may be NULL; stats (host double[4]) receives min, mean, max and
+ * the count of non-positive values. Returns CLAIRE_WDETBOUND if any
+ * determinant is <= 0. */
+int claire_ctx_detdefgrad(claire_ctx *ctx, double *det_out, double stats[4]);
+
+/* ----------------------------------------------- building blocks (checks) */
+
+/* Spectral operators (Section 2.5.3): op selects
+ *   CLAIRE_OP_GRAD     in [n]    -> out [3][n]  grad (Nyquist of odd derivatives zero)
+ *   CLAIRE_OP_DIV      in [3][n] -> out [n]     divergence
+ *   CLAIRE_OP_REG      in [3][n] -> out [3][n]  alpha L
+ *   CLAIRE_OP_REG_INV  in [3][n] -> out [3][n]  (alpha L)^{-1}, k = 0 passed through
+ * in and out must not overlap. */
+enum { CLAIRE_OP_GRAD = 0, CLAIRE_OP_DIV = 1, CLAIRE_OP_REG = 2, CLAIRE_OP_REG_INV = 3 };
+int claire_ctx_spectral(claire_ctx *ctx, int op, const float *in, float *out);
+
+/* Tricubic Lagrange interpolation (Section 2.5.4, p = 3):
+ * out[k][x] = f[k](x + disp(x)) for nfield fields f ([nfield][n]) and a
+ * displacement disp ([3][n], in voxel units). out must not overlap f. */
+int claire_ctx_interpolate(claire_ctx *ctx, const float *f, int nfield,
+                           const float *disp, float *out);
+
+/* Copy a field cached by the last set_velocity into out:
+ *   CLAIRE_FIELD_DISP_PLUS   [3][n] departure displacement (voxels) of +v
+ *   CLAIRE_FIELD_DISP_MINUS  [3][n] departure displacement of -v
+ *   CLAIRE_FIELD_STATE       [n]    m^j, j = index in 0..nt
+ *   CLAIRE_FIELD_GRAD_STATE  [3][n] grad m^j
+ *   CLAIRE_FIELD_ADJOINT     [n]    lambda^j
+ *   CLAIRE_FIELD_DIVV        [n]    div v */
+enum { CLAIRE_FIELD_DISP_PLUS = 0, CLAIRE_FIELD_DISP_MINUS = 1, CLAIRE_FIELD_STATE = 2,
+       CLAIRE_FIELD_GRAD_STATE = 3, CLAIRE_FIELD_ADJOINT = 4, CLAIRE_FIELD_DIVV = 5 };
+int claire_ctx_get_field(claire_ctx *ctx, int which, int index, float *out);
+
+/* --------------------------------------------- stateless convenience calls
+ * Each builds a context, runs, and destroys it (setup cost paid per call). */
+
+/* m1_out = m(1): transport of m0 by the stationary v (eq. e:transport),
+ * nt semi-Lagrangian steps. */
+int claire_transport(const float *m0, const float *v, const int nx[3], int nt,
+                     float *m1_out, void *stream);
+
+/* Reduced gradient g_out ([3][n]) and objective *J_out (host) at v
+ * (eq. e:rgrad). Either output may be NULL. */
+int claire_gradient(const float *m0, const float *m1, const float *v,
+                    const int nx[3], double alpha, int nt, int reg_order,
+                    float *g_out, double *J_out, void *stream);
+
+/* Hvt_out = H(v) vt, the Gauss--Newton Hessian matvec (eq. e:matvec). */
+int claire_hessian_matvec(const float *m0, const float *m1, const float *v,
+                          const float *vt, const int nx[3], double alpha, int nt,
+                          int reg_order, float *Hvt_out, void *stream);
+
+/* Full solve (Algorithm 1); alpha is used when opts->alpha_levels is NULL.
+ * opts and stats are host pointers and may be NULL. */
+int claire_solve(const float *m0, const float *m1, const int nx[3], double alpha,
+                 int nt, const claire_opts *opts, float *v_inout,
+                 claire_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLAIRE_H */

@@ -1,0 +1,247 @@
+// Float64 reductions and float32 vector updates for PCG, the objective and
+// the line search. Reductions are deterministic: a fixed grid writes one
+// partial per block (wavefront shuffles, then LDS), and a single block folds
+// the partials in a fixed order.
+
+#include "internal.h"
+
+#include <cfloat>
+
+namespace claire {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+
+enum RedOp { OP_SUM = 0, OP_MAX = 1, OP_MIN = 2 };
+
+template <int OP>
+__device__ __forceinline__ double combine(double a, double b) {
+    if (OP == OP_SUM) return a + b;
+    if (OP == OP_MAX) return fmax(a, b);
+    return fmin(a, b);
+}
+
+template <int OP>
+__device__ __forceinline__ double identity() {
+    if (OP == OP_SUM) return 0.0;
+    if (OP == OP_MAX) return -DBL_MAX;
+    return DBL_MAX;
+}
+
+template <int OP>
+__device__ double block_reduce(double v, double* sh) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = combine<OP>(v, __shfl_down(v, o, kWave));
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int w = 1; w < kThreads / kWave; ++w) r = combine<OP>(r, sh[w]);
+        sh[0] = r;
+    }
+    __syncthreads();
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// KIND 0: sum a*b; 1: sum (a-b)^2; 2: max |a|
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_partial(const float* __restrict__ a,
+                                                      const float* __restrict__ b, long long n,
+                                                      double* __restrict__ partial) {
+    __shared__ double sh[kThreads / kWave];
+    constexpr int OP = (KIND == 2) ? OP_MAX : OP_SUM;
+    double acc = identity<OP>();
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        if (KIND == 0) acc += (double)a[i] * (double)b[i];
+        else if (KIND == 1) { const double d = (double)a[i] - (double)b[i]; acc += d * d; }
+        else acc = fmax(acc, fabs((double)a[i]));
+    }
+    acc = block_reduce<OP>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// float64 array statistics: min, sum, max, count(<= 0) -> partial[4*block + q]
+__global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __restrict__ a,
+                                                            long long n,
+                                                            double* __restrict__ partial) {
+    __shared__ double sh[kThreads / kWave];
+    double mn = DBL_MAX, mx = -DBL_MAX, sm = 0.0, cnt = 0.0;
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const double x = a[i];
+        mn = fmin(mn, x);
+        mx = fmax(mx, x);
+        sm += x;
+        cnt += (x <= 0.0) ? 1.0 : 0.0;
+    }
+    mn = block_reduce<OP_MIN>(mn, sh);
+    sm = block_reduce<OP_SUM>(sm, sh);
+    mx = block_reduce<OP_MAX>(mx, sh);
+    cnt = block_reduce<OP_SUM>(cnt, sh);
+    if (threadIdx.x == 0) {
+        partial[4 * blockIdx.x + 0] = mn;
+        partial[4 * blockIdx.x + 1] = sm;
+        partial[4 * blockIdx.x + 2] = mx;
+        partial[4 * blockIdx.x + 3] = cnt;
+    }
+}
+
+// fold nb partials (with element stride `stride`, offset `off`) into result[slot]
+template <int OP>
+__global__ __launch_bounds__(kThreads) void k_fold(const double* __restrict__ partial, int nb,
+                                                   int stride, int off,
+                                                   double* __restrict__ result, int slot) {
+    __shared__ double sh[kThreads / kWave];
+    double acc = identity<OP>();
+    for (int i = threadIdx.x; i < nb; i += kThreads) acc = combine<OP>(acc, partial[i * stride + off]);
+    acc = block_reduce<OP>(acc, sh);
+    if (threadIdx.x == 0) result[slot] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy(const float* __restrict__ x,
+                                                   float* __restrict__ y, float a, long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = fmaf(a, x[i], y[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_xpby(const float* __restrict__ x,
+                                                   float* __restrict__ y, float b, long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = fmaf(b, y[i], x[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ x,
+                                                      const float* __restrict__ z,
+                                                      float* __restrict__ y, float b,
+                                                      long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = fmaf(b, z[i], x[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ y, float v, long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_copy(const float* __restrict__ x,
+                                                         float* __restrict__ y, float a,
+                                                         long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_finite(const float* __restrict__ x, long long n,
+                                                     int* __restrict__ flag) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && !isfinite(x[i])) *flag = 1;
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+unsigned red_blocks(long long n) {
+    long long b = (n + kThreads - 1) / kThreads;
+    if (b > kRedBlocks) b = kRedBlocks;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <int KIND>
+int red_generic(Reducer& r, const float* a, const float* b, long long n, int slot, hipStream_t s) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_partial<KIND>, dim3(nb), dim3(kThreads), 0, s, a, b, n, r.partial);
+    CL_LAUNCH_CHECK();
+    constexpr int OP = (KIND == 2) ? OP_MAX : OP_SUM;
+    hipLaunchKernelGGL(k_fold<OP>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 1, 0,
+                       r.result, slot);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace
+
+int reducer_init(Reducer& r) {
+    CL_HIP(hipMalloc(&r.partial, sizeof(double) * kRedBlocks * 4));
+    CL_HIP(hipMalloc(&r.result, sizeof(double) * 8));
+    CL_HIP(hipHostMalloc(&r.host, sizeof(double) * 8, hipHostMallocDefault));
+    return 0;
+}
+
+void reducer_free(Reducer& r) {
+    if (r.partial) (void)hipFree(r.partial);
+    if (r.result) (void)hipFree(r.result);
+    if (r.host) (void)hipHostFree(r.host);
+    r = Reducer();
+}
+
+int red_dot(Reducer& r, const float* a, const float* b, long long n, int slot, hipStream_t s) {
+    return red_generic<0>(r, a, b, n, slot, s);
+}
+
+int red_sumsq_diff(Reducer& r, const float* a, const float* b, long long n, int slot,
+                   hipStream_t s) {
+    return red_generic<1>(r, a, b, n, slot, s);
+}
+
+int red_absmax(Reducer& r, const float* a, long long n, int slot, hipStream_t s) {
+    return red_generic<2>(r, a, a, n, slot, s);
+}
+
+int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_partial_stats, dim3(nb), dim3(kThreads), 0, s, a, n, r.partial);
+    CL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fold<OP_MIN>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 0, r.result, 0);
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 1, r.result, 1);
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 2, r.result, 2);
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 3, r.result, 3);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int red_fetch(Reducer& r, hipStream_t s) {
+    CL_HIP(hipMemcpyAsync(r.host, r.result, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    CL_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, a, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, b, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_lincomb(const float* x, const float* z, float* y, float b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, z, y, b, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_fill(float* y, float value, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, y, value, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_scale_copy(const float* x, float* y, float a, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, a, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_check_finite(const float* x, long long n, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_finite, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, n, flag);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace claire

@@ -1,0 +1,756 @@
+// Context, Gauss--Newton--Krylov driver and the exported C ABI.
+//
+// Per-velocity setup (Algorithm 1 lines 3-6), Hessian matvec (eq. e:matvec,
+// Gauss--Newton form), PCG (Algorithm 2) with the regularisation
+// preconditioner (Section 2.5.6), Armijo line search and parameter
+// continuation (Sections 2.5.5, 2.6). All field work runs in the HIP kernels
+// of fft.hip, sl.hip and blas.hip; this file only sequences them and makes
+// the scalar decisions (step lengths, stopping tests) in float64 on the host.
+
+#include "internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace claire {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? CLAIRE_ENOMEM
+                                                                       : CLAIRE_EDEVICE;
+}
+
+Geo make_geo(const int nx[3]) {
+    Geo g;
+    g.n1 = nx[0];
+    g.n2 = nx[1];
+    g.n3 = nx[2];
+    auto lg = [](int v) { int l = 0; while ((1 << l) < v) ++l; return l; };
+    g.l1 = lg(g.n1);
+    g.l2 = lg(g.n2);
+    g.l3 = lg(g.n3);
+    g.nh = g.n3 / 2 + 1;
+    g.n = (long long)g.n1 * g.n2 * g.n3;
+    g.nspec = (long long)g.n1 * g.n2 * g.nh;
+    return g;
+}
+
+}  // namespace claire
+
+using namespace claire;
+
+struct claire_ctx {
+    Geo g;
+    int nt = 0;
+    double alpha = 0;
+    int p = 1;
+    hipStream_t s = nullptr;
+    double cell = 0;   // h1 h2 h3
+
+    // per-velocity state
+    float* m0 = nullptr;     // [n]
+    float* m1 = nullptr;     // [n]
+    float* v = nullptr;      // [3][n]
+    float* dp = nullptr;     // [3][n] departure displacement of +v (voxels)
+    float* dm = nullptr;     // [3][n] departure displacement of -v
+    float* m = nullptr;      // [nt+1][n]   m^j
+    float* gm = nullptr;     // [nt+1][3][n] grad m^j
+    float* divv = nullptr;   // [n]
+    float* A = nullptr;      // [n] adjoint step factor
+    float* grad = nullptr;   // [3][n] reduced gradient
+    float* regv = nullptr;   // [3][n] alpha L v
+    float* lam = nullptr;    // [nt+1][n] adjoint / incremental adjoint
+    float* w0 = nullptr;     // [n] incremental-state ping-pong
+    float* w1 = nullptr;     // [n]
+    float* tmp3 = nullptr;   // [3][n]
+    SpectralWork sw;
+    Reducer red;
+    int* flag = nullptr;     // device int (non-finite check)
+
+    // solver vectors (allocated on first solve)
+    float* vt = nullptr;
+    float* r = nullptr;
+    float* z = nullptr;
+    float* sd = nullptr;
+    float* hs = nullptr;
+    float* vtrial = nullptr;
+
+    bool have_images = false;
+    bool state_valid = false;      // dp, dm, m valid for the content of v
+    bool have_velocity = false;    // full setup done: gm, A, g, J valid
+    double J = 0, Jdist = 0, Jreg = 0, gnorm = 0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T** p, long long count) {
+    CL_HIP(hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count));
+    return 0;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+bool pow2(int v) { return v >= 8 && v <= 1024 && (v & (v - 1)) == 0; }
+
+int check_args(const int nx[3], int nt, double alpha, int reg_order) {
+    if (!nx) { set_error("nx is NULL"); return CLAIRE_EINVAL; }
+    for (int a = 0; a < 3; ++a)
+        if (!pow2(nx[a])) {
+            set_error("n%d = %d: each extent must be a power of two in [8, 1024]", a + 1, nx[a]);
+            return CLAIRE_EINVAL;
+        }
+    if (nt < 1 || nt > 64) { set_error("nt = %d out of range [1, 64]", nt); return CLAIRE_EINVAL; }
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) { set_error("alpha must be positive"); return CLAIRE_EINVAL; }
+    if (reg_order != 1 && reg_order != 2) { set_error("reg_order must be 1 or 2"); return CLAIRE_EINVAL; }
+    return 0;
+}
+
+int ctx_alloc(claire_ctx* c) {
+    const long long n = c->g.n;
+    const int nt = c->nt;
+    CL_TRY(dalloc(&c->m0, n));
+    CL_TRY(dalloc(&c->m1, n));
+    CL_TRY(dalloc(&c->v, 3 * n));
+    CL_TRY(dalloc(&c->dp, 3 * n));
+    CL_TRY(dalloc(&c->dm, 3 * n));
+    CL_TRY(dalloc(&c->m, (nt + 1) * n));
+    CL_TRY(dalloc(&c->gm, 3 * (nt + 1) * n));
+    CL_TRY(dalloc(&c->divv, n));
+    CL_TRY(dalloc(&c->A, n));
+    CL_TRY(dalloc(&c->grad, 3 * n));
+    CL_TRY(dalloc(&c->regv, 3 * n));
+    CL_TRY(dalloc(&c->lam, (nt + 1) * n));
+    CL_TRY(dalloc(&c->w0, n));
+    CL_TRY(dalloc(&c->w1, n));
+    CL_TRY(dalloc(&c->tmp3, 3 * n));
+    CL_TRY(dalloc(&c->flag, 1));
+    CL_TRY(spectral_init(c->sw, c->g));
+    CL_TRY(reducer_init(c->red));
+    return 0;
+}
+
+void ctx_release(claire_ctx* c) {
+    float* bufs[] = {c->m0, c->m1, c->v, c->dp, c->dm, c->m, c->gm, c->divv, c->A, c->grad,
+                     c->regv, c->lam, c->w0, c->w1, c->tmp3, c->vt, c->r, c->z, c->sd, c->hs,
+                     c->vtrial};
+    for (float* b : bufs) dfree(b);
+    dfree(c->flag);
+    spectral_free(c->sw);
+    reducer_free(c->red);
+}
+
+int copy_d2d(float* dst, const float* src, long long count, hipStream_t s) {
+    if (dst == src) return 0;
+    CL_HIP(hipMemcpyAsync(dst, src, sizeof(float) * (size_t)count, hipMemcpyDeviceToDevice, s));
+    return 0;
+}
+
+// Backtrace and state solve for the velocity held in c->v (Section 2.5.2,
+// eq. e:transport): m^0 = m0, m^{j+1} = m^j(y+).
+int run_state(claire_ctx* c) {
+    const Geo& g = c->g;
+    const double ht = 1.0 / c->nt;
+    CL_TRY(launch_backtrace(g, c->v, c->dp, c->dm, ht, c->s));
+    CL_TRY(copy_d2d(c->m, c->m0, g.n, c->s));
+    for (int j = 0; j < c->nt; ++j)
+        CL_TRY(launch_interp(g, c->m + (long long)j * g.n, 1, c->dp, c->m + (long long)(j + 1) * g.n,
+                             c->s));
+    c->state_valid = true;
+    return 0;
+}
+
+// Full per-velocity setup; the state is reused when state_valid says the
+// backtrace and m^j already belong to c->v (accepted line-search trial).
+int run_setup(claire_ctx* c) {
+    const Geo& g = c->g;
+    const long long n = g.n;
+    const int nt = c->nt;
+    const double ht = 1.0 / nt;
+    if (!c->state_valid) CL_TRY(run_state(c));
+    // objective parts: 1/2 ||m^nt - m1||^2 and 1/2 <alpha L v, v>
+    CL_TRY(red_sumsq_diff(c->red, c->m + nt * n, c->m1, n, 0, c->s));
+    CL_TRY(spectral_apply(g, c->sw, SPEC_REG, c->v, c->regv, c->alpha, c->p, c->s));
+    CL_TRY(red_dot(c->red, c->regv, c->v, 3 * n, 1, c->s));
+    // grad m^j (Section 2.5.3; stored, not recomputed per matvec)
+    for (int j = 0; j <= nt; ++j)
+        CL_TRY(spectral_apply(g, c->sw, SPEC_GRAD, c->m + (long long)j * n,
+                              c->gm + (long long)j * 3 * n, c->alpha, c->p, c->s));
+    // div v and the adjoint step factor
+    CL_TRY(spectral_apply(g, c->sw, SPEC_DIV, c->v, c->divv, c->alpha, c->p, c->s));
+    CL_TRY(launch_make_A(g, c->divv, c->dm, c->A, ht, c->s));
+    // adjoint (eq. e:adjoint): lam^nt = -(m^nt - m1), lam^j = A lam^{j+1}(y-)
+    CL_TRY(launch_final_adjoint(g, c->m + nt * n, c->m1, c->lam + nt * n, c->s));
+    for (int j = nt - 1; j >= 0; --j)
+        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
+                                   c->lam + (long long)j * n, c->s));
+    // reduced gradient (eq. e:rgrad), trapezoid in time
+    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->regv, c->grad, c->s));
+    CL_TRY(red_absmax(c->red, c->grad, 3 * n, 2, c->s));
+    CL_TRY(red_fetch(c->red, c->s));
+    c->Jdist = 0.5 * c->cell * c->red.host[0];
+    c->Jreg = 0.5 * c->cell * c->red.host[1];
+    c->J = c->Jdist + c->Jreg;
+    c->gnorm = c->red.host[2];
+    if (!std::isfinite(c->J) || !std::isfinite(c->gnorm)) {
+        set_error("non-finite objective or gradient");
+        c->have_velocity = false;
+        return CLAIRE_ENONFINITE;
+    }
+    c->have_velocity = true;
+    return 0;
+}
+
+// Gauss--Newton Hessian matvec (eqs. e:matvec, e:incstate, e:incadj).
+int run_matvec(claire_ctx* c, const float* vt, float* out) {
+    const Geo& g = c->g;
+    const long long n = g.n;
+    const int nt = c->nt;
+    const double ht = 1.0 / nt;
+    // incremental state, forward in time; the last step writes lambda~^nt = -m~^nt
+    CL_TRY(launch_inc_state_first(g, c->gm, vt, c->w0, ht, c->s));
+    float* src = c->w0;
+    float* nxt = c->w1;
+    for (int j = 0; j < nt; ++j) {
+        const float* gnext = c->gm + (long long)(j + 1) * 3 * n;
+        if (j + 1 < nt) {
+            CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, nxt, (float)ht, 1.0f, c->s));
+            float* t = src;
+            src = nxt;
+            nxt = t;
+        } else {
+            CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, c->lam + (long long)nt * n,
+                                         (float)(0.5 * ht), -1.0f, c->s));
+        }
+    }
+    // incremental adjoint (GN), backward in time
+    for (int j = nt - 1; j >= 0; --j)
+        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
+                                   c->lam + (long long)j * n, c->s));
+    // H v~ = alpha L v~ + h_t sum_j c_j lambda~^j grad m^j
+    CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
+    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->tmp3, out, c->s));
+    return 0;
+}
+
+// Objective of a trial velocity held in c->v: backtrace, state, mismatch.
+int run_trial_mismatch(claire_ctx* c, double* half_sumsq) {
+    const long long n = c->g.n;
+    c->state_valid = false;
+    c->have_velocity = false;
+    CL_TRY(run_state(c));
+    CL_TRY(red_sumsq_diff(c->red, c->m + c->nt * n, c->m1, n, 0, c->s));
+    CL_TRY(red_fetch(c->red, c->s));
+    *half_sumsq = 0.5 * c->cell * c->red.host[0];
+    return 0;
+}
+
+int ensure_solver_buffers(claire_ctx* c) {
+    const long long n3 = 3 * c->g.n;
+    if (!c->vt) CL_TRY(dalloc(&c->vt, n3));
+    if (!c->r) CL_TRY(dalloc(&c->r, n3));
+    if (!c->z) CL_TRY(dalloc(&c->z, n3));
+    if (!c->sd) CL_TRY(dalloc(&c->sd, n3));
+    if (!c->hs) CL_TRY(dalloc(&c->hs, n3));
+    if (!c->vtrial) CL_TRY(dalloc(&c->vtrial, n3));
+    return 0;
+}
+
+struct PcgResult {
+    int its = 0;
+    bool hit_max = false;
+};
+
+// PCG (Algorithm 2) on H v~ = -g with M = alpha L; v~^0 = 0. Stopping per
+// Section 2.5.5: ||r||_inf <= eta ||g||_inf, or a fixed number of matvecs.
+int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
+    const long long n3 = 3 * c->g.n;
+    const hipStream_t s = c->s;
+    const double gn = c->gnorm;
+    const double eta = (o.forcing == 1) ? std::fmin(0.5, gn) : std::fmin(0.5, std::sqrt(gn));
+    const double tol = eta * gn;
+    const bool fixed = o.fixed_pcg_iters > 0;
+    const int limit = fixed ? o.fixed_pcg_iters : o.max_pcg;
+    CL_TRY(launch_fill(c->vt, 0.f, n3, s));
+    CL_TRY(launch_scale_copy(c->grad, c->r, -1.f, n3, s));
+    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
+    CL_TRY(copy_d2d(c->sd, c->z, n3, s));
+    CL_TRY(red_dot(c->red, c->r, c->z, n3, 0, s));
+    CL_TRY(red_fetch(c->red, s));
+    double rz = c->red.host[0];
+    res = PcgResult();
+    bool converged = false;
+    while (res.its < limit) {
+        CL_TRY(run_matvec(c, c->sd, c->hs));
+        ++res.its;
+        CL_TRY(red_dot(c->red, c->sd, c->hs, n3, 0, s));
+        CL_TRY(red_fetch(c->red, s));
+        const double shs = c->red.host[0];
+        if (!(shs > 0.0) || !std::isfinite(shs)) {
+            // zero curvature along s: the residual is already zero in that direction
+            if (shs == 0.0) break;
+            set_error("PCG curvature <s, Hs> = %g is not positive", shs);
+            return CLAIRE_ENONFINITE;
+        }
+        const double kappa = rz / shs;
+        CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
+        CL_TRY(launch_axpy(c->hs, c->r, (float)(-kappa), n3, s));
+        if (res.its == limit) break;
+        // preconditioned residual and the stopping norm in one host round trip
+        CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
+        CL_TRY(red_absmax(c->red, c->r, n3, 1, s));
+        CL_TRY(red_dot(c->red, c->z, c->r, n3, 2, s));
+        CL_TRY(red_fetch(c->red, s));
+        if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
+        const double rz_new = c->red.host[2];
+        const double mu = rz_new / rz;
+        CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
+        rz = rz_new;
+    }
+    if (!fixed && !converged && res.its >= limit) {
+        // the last residual was not tested inside the loop
+        CL_TRY(red_absmax(c->red, c->r, n3, 1, s));
+        CL_TRY(red_fetch(c->red, s));
+        res.hit_max = c->red.host[1] > tol;
+    }
+    return 0;
+}
+
+int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = c->g;
+    const long long n = g.n, n3 = 3 * n;
+    const hipStream_t s = c->s;
+    CL_TRY(ensure_solver_buffers(c));
+    std::vector<double> levels;
+    if (o.alpha_levels && o.n_levels > 0) levels.assign(o.alpha_levels, o.alpha_levels + o.n_levels);
+    else levels.push_back(c->alpha);
+    for (double a : levels)
+        if (!(a > 0.0)) { set_error("alpha levels must be positive"); return CLAIRE_EINVAL; }
+    claire_stats S;
+    std::memset(&S, 0, sizeof(S));
+    int warn = 0;
+    auto note = [&](int w) { if (!warn) warn = w; };
+    bool stop_all = false;
+    double g0 = 0.0;
+    for (size_t li = 0; li < levels.size() && !stop_all; ++li) {
+        c->alpha = levels[li];
+        CL_TRY(copy_d2d(c->v, v_io, n3, s));
+        c->state_valid = false;
+        CL_TRY(run_setup(c));
+        S.pde_solves += 2;
+        if (li == 0) S.J0 = c->J;
+        g0 = c->gnorm;
+        int k = 0;
+        while (true) {
+            if (c->gnorm <= o.gtol * g0 || c->gnorm <= o.gabs) break;
+            if (k >= o.max_gn) { note(CLAIRE_WNOTCONV); break; }
+            PcgResult pr;
+            CL_TRY(run_pcg(c, o, pr));
+            S.matvecs += pr.its;
+            S.pde_solves += 2 * pr.its;
+            if (pr.hit_max) { ++S.pcg_max_hits; note(CLAIRE_WPCGMAX); }
+            // Armijo line search on J(v + gamma v~). The regulariser is
+            // quadratic: J_reg(v + gamma v~) = J_reg + gamma <aLv, v~> + gamma^2/2 <aLv~, v~>.
+            CL_TRY(red_dot(c->red, c->grad, c->vt, n3, 3, s));
+            CL_TRY(red_dot(c->red, c->regv, c->vt, n3, 4, s));
+            CL_TRY(spectral_apply(g, c->sw, SPEC_REG, c->vt, c->tmp3, c->alpha, c->p, s));
+            CL_TRY(red_dot(c->red, c->tmp3, c->vt, n3, 5, s));
+            CL_TRY(red_fetch(c->red, s));
+            const double slope = c->cell * c->red.host[3];
+            const double ra = c->cell * c->red.host[4];
+            const double rb = c->cell * c->red.host[5];
+            const double J = c->J, Jreg = c->Jreg;
+            double gamma = 1.0;
+            bool accepted = false;
+            for (int t = 0; t < o.max_linesearch; ++t) {
+                CL_TRY(launch_lincomb(v_io, c->vt, c->v, (float)gamma, n3, s));
+                double jd = 0.0;
+                CL_TRY(run_trial_mismatch(c, &jd));
+                ++S.linesearch_trials;
+                ++S.pde_solves;
+                const double jt = jd + Jreg + gamma * ra + 0.5 * gamma * gamma * rb;
+                if (std::isfinite(jt) && jt <= J + o.armijo_c1 * gamma * slope) {
+                    accepted = true;
+                    break;
+                }
+                gamma *= 0.5;
+            }
+            if (!accepted) {
+                note(CLAIRE_WLINESEARCH);
+                // restore the setup at the last accepted iterate
+                CL_TRY(copy_d2d(c->v, v_io, n3, s));
+                c->state_valid = false;
+                CL_TRY(run_setup(c));
+                stop_all = true;
+                break;
+            }
+            CL_TRY(copy_d2d(v_io, c->v, n3, s));
+            CL_TRY(run_setup(c));   // reuses the accepted trial's state
+            ++S.pde_solves;          // adjoint solve
+            ++k;
+            ++S.gn_iters;
+        }
+        S.rel_grad = g0 > 0 ? c->gnorm / g0 : 0.0;
+    }
+    S.J = c->J;
+    CL_TRY(red_sumsq_diff(c->red, c->m + c->nt * n, c->m1, n, 0, s));
+    CL_TRY(red_sumsq_diff(c->red, c->m0, c->m1, n, 1, s));
+    CL_TRY(red_fetch(c->red, s));
+    S.rel_mismatch = c->red.host[1] > 0 ? std::sqrt(c->red.host[0] / c->red.host[1]) : 0.0;
+    S.det_min = S.det_mean = S.det_max = 0.0;
+    S.det_nonpositive = 0;
+    if (o.compute_det) {
+        double ds[4];
+        int rc = claire_ctx_detdefgrad(c, nullptr, ds);
+        if (rc < 0) return rc;
+        S.det_min = ds[0];
+        S.det_mean = ds[1];
+        S.det_max = ds[2];
+        S.det_nonpositive = (long long)ds[3];
+        if (rc > 0) note(rc);
+    }
+    CL_HIP(hipStreamSynchronize(s));
+    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = S;
+    return warn;
+}
+
+int need(claire_ctx* c, bool velocity) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    if (!c->have_images) { set_error("call claire_ctx_set_images first"); return CLAIRE_ESTATE; }
+    if (velocity && !c->have_velocity) {
+        set_error("call claire_ctx_set_velocity first");
+        return CLAIRE_ESTATE;
+    }
+    return 0;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_ptr(const void* p, const char* name) {
+    if (!p) { set_error("%s is NULL", name); return CLAIRE_EINVAL; }
+    if (!aligned(p)) { set_error("%s is not 16-byte aligned", name); return CLAIRE_EINVAL; }
+    return 0;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+void claire_opts_default(claire_opts* o) {
+    if (!o) return;
+    o->reg_order = 1;
+    o->precision = 0;
+    o->gtol = 5e-2;
+    o->gabs = 1e-6;
+    o->forcing = 0;
+    o->max_gn = 50;
+    o->max_pcg = 100;
+    o->fixed_pcg_iters = 0;
+    o->max_linesearch = 16;
+    o->armijo_c1 = 1e-4;
+    o->alpha_levels = nullptr;
+    o->n_levels = 0;
+    o->compute_det = 0;
+}
+
+const char* claire_last_error(void) { return g_err; }
+
+int claire_ctx_create(claire_ctx** out, const int nx[3], int nt, double alpha, int reg_order,
+                      void* stream) {
+    if (!out) { set_error("out is NULL"); return CLAIRE_EINVAL; }
+    *out = nullptr;
+    CL_TRY(check_args(nx, nt, alpha, reg_order));
+    claire_ctx* c = new (std::nothrow) claire_ctx();
+    if (!c) { set_error("host allocation failed"); return CLAIRE_ENOMEM; }
+    c->g = make_geo(nx);
+    c->nt = nt;
+    c->alpha = alpha;
+    c->p = reg_order;
+    c->s = reinterpret_cast<hipStream_t>(stream);
+    c->cell = (2.0 * M_PI / nx[0]) * (2.0 * M_PI / nx[1]) * (2.0 * M_PI / nx[2]);
+    int rc = ctx_alloc(c);
+    if (rc < 0) {
+        ctx_release(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return 0;
+}
+
+int claire_ctx_destroy(claire_ctx* c) {
+    if (!c) return 0;
+    if (c->s) (void)hipStreamSynchronize(c->s);
+    else (void)hipDeviceSynchronize();
+    ctx_release(c);
+    delete c;
+    return 0;
+}
+
+int claire_ctx_set_alpha(claire_ctx* c, double alpha) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    if (!(alpha > 0.0)) { set_error("alpha must be positive"); return CLAIRE_EINVAL; }
+    c->alpha = alpha;
+    c->have_velocity = false;
+    return 0;
+}
+
+int claire_ctx_set_images(claire_ctx* c, const float* m0, const float* m1) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(check_ptr(m0, "m0"));
+    CL_TRY(check_ptr(m1, "m1"));
+    CL_TRY(copy_d2d(c->m0, m0, c->g.n, c->s));
+    CL_TRY(copy_d2d(c->m1, m1, c->g.n, c->s));
+    c->have_images = true;
+    c->state_valid = false;
+    c->have_velocity = false;
+    return 0;
+}
+
+int claire_ctx_set_velocity(claire_ctx* c, const float* v) {
+    CL_TRY(need(c, false));
+    CL_TRY(check_ptr(v, "v"));
+    CL_TRY(copy_d2d(c->v, v, 3 * c->g.n, c->s));
+    c->state_valid = false;
+    return run_setup(c);
+}
+
+int claire_ctx_gradient(claire_ctx* c, float* g, double* J) {
+    CL_TRY(need(c, true));
+    if (g) {
+        CL_TRY(check_ptr(g, "g"));
+        CL_TRY(copy_d2d(g, c->grad, 3 * c->g.n, c->s));
+    }
+    if (J) *J = c->J;
+    return 0;
+}
+
+int claire_ctx_objective(claire_ctx* c, const float* v, double* J) {
+    CL_TRY(need(c, false));
+    CL_TRY(check_ptr(v, "v"));
+    if (!J) { set_error("J is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(copy_d2d(c->v, v, 3 * c->g.n, c->s));
+    double jd = 0.0;
+    CL_TRY(run_trial_mismatch(c, &jd));
+    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG, c->v, c->tmp3, c->alpha, c->p, c->s));
+    CL_TRY(red_dot(c->red, c->tmp3, c->v, 3 * c->g.n, 1, c->s));
+    CL_TRY(red_fetch(c->red, c->s));
+    *J = jd + 0.5 * c->cell * c->red.host[1];
+    return 0;
+}
+
+int claire_ctx_hessian_matvec(claire_ctx* c, const float* vt, float* Hvt) {
+    CL_TRY(need(c, true));
+    CL_TRY(check_ptr(vt, "vt"));
+    CL_TRY(check_ptr(Hvt, "Hvt"));
+    if (vt == Hvt) { set_error("vt and Hvt must not overlap"); return CLAIRE_EINVAL; }
+    return run_matvec(c, vt, Hvt);
+}
+
+int claire_ctx_precond(claire_ctx* c, const float* r, float* z) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(check_ptr(r, "r"));
+    CL_TRY(check_ptr(z, "z"));
+    return spectral_apply(c->g, c->sw, SPEC_REG_INV, r, z, c->alpha, c->p, c->s);
+}
+
+int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
+                     claire_stats* stats) {
+    CL_TRY(need(c, false));
+    CL_TRY(check_ptr(v_inout, "v_inout"));
+    claire_opts o;
+    if (opts) o = *opts;
+    else claire_opts_default(&o);
+    if (opts && o.reg_order != c->p) {
+        set_error("opts->reg_order %d differs from the context's %d", o.reg_order, c->p);
+        return CLAIRE_EINVAL;
+    }
+    if (o.precision != 0) { set_error("only precision 0 (float32) is supported"); return CLAIRE_EINVAL; }
+    if (o.max_gn < 0 || o.max_pcg < 1 || o.max_linesearch < 1 || !(o.gtol >= 0)) {
+        set_error("invalid solver limits");
+        return CLAIRE_EINVAL;
+    }
+    return run_solve(c, o, v_inout, stats);
+}
+
+int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {
+    CL_TRY(need(c, false));
+    if (!c->state_valid) {
+        set_error("no velocity set");
+        return CLAIRE_ESTATE;
+    }
+    const Geo& g = c->g;
+    const long long n = g.n;
+    float* G = nullptr;
+    float* F = nullptr;
+    float* Fo = nullptr;
+    double* det = det_out;
+    int rc = 0;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(c->s);
+        dfree(G);
+        dfree(F);
+        dfree(Fo);
+        if (!det_out) dfree(det);
+    };
+    if ((rc = dalloc(&G, 9 * n)) < 0 || (rc = dalloc(&F, 9 * n)) < 0 || (rc = dalloc(&Fo, 9 * n)) < 0 ||
+        (!det_out && (rc = dalloc(&det, n)) < 0)) {
+        cleanup();
+        return rc;
+    }
+    const double ht = 1.0 / c->nt;
+    for (int a = 0; a < 3 && rc >= 0; ++a)
+        rc = spectral_apply(g, c->sw, SPEC_GRAD, c->v + (long long)a * n, G + (long long)a * 3 * n,
+                            c->alpha, c->p, c->s);
+    for (int j = 0; j < c->nt && rc >= 0; ++j) {
+        rc = launch_defgrad_step(g, F, G, c->dp, Fo, ht, j == 0, c->s);
+        float* t = F;
+        F = Fo;
+        Fo = t;
+    }
+    if (rc >= 0) rc = launch_det(g, F, det, c->s);
+    if (rc >= 0) rc = red_stats_f64(c->red, det, n, c->s);
+    if (rc >= 0) rc = red_fetch(c->red, c->s);
+    if (rc >= 0 && stats) {
+        stats[0] = c->red.host[0];
+        stats[1] = c->red.host[1] / (double)n;
+        stats[2] = c->red.host[2];
+        stats[3] = c->red.host[3];
+    }
+    const bool bad = rc >= 0 && c->red.host[3] > 0;
+    cleanup();
+    if (rc < 0) return rc;
+    return bad ? CLAIRE_WDETBOUND : 0;
+}
+
+int claire_ctx_spectral(claire_ctx* c, int op, const float* in, float* out) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(check_ptr(in, "in"));
+    CL_TRY(check_ptr(out, "out"));
+    if (in == out) { set_error("in and out must not overlap"); return CLAIRE_EINVAL; }
+    SpecMode m;
+    switch (op) {
+    case CLAIRE_OP_GRAD: m = SPEC_GRAD; break;
+    case CLAIRE_OP_DIV: m = SPEC_DIV; break;
+    case CLAIRE_OP_REG: m = SPEC_REG; break;
+    case CLAIRE_OP_REG_INV: m = SPEC_REG_INV; break;
+    default: set_error("unknown op %d", op); return CLAIRE_EINVAL;
+    }
+    return spectral_apply(c->g, c->sw, m, in, out, c->alpha, c->p, c->s);
+}
+
+int claire_ctx_interpolate(claire_ctx* c, const float* f, int nfield, const float* disp,
+                           float* out) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(check_ptr(f, "f"));
+    CL_TRY(check_ptr(disp, "disp"));
+    CL_TRY(check_ptr(out, "out"));
+    if (nfield < 1 || nfield > 64) { set_error("nfield must be in [1, 64]"); return CLAIRE_EINVAL; }
+    if (f == out) { set_error("out must not overlap f"); return CLAIRE_EINVAL; }
+    return launch_interp(c->g, f, nfield, disp, out, c->s);
+}
+
+int claire_ctx_get_field(claire_ctx* c, int which, int index, float* out) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    CL_TRY(check_ptr(out, "out"));
+    const long long n = c->g.n;
+    const bool state_field = which == CLAIRE_FIELD_DISP_PLUS || which == CLAIRE_FIELD_DISP_MINUS ||
+                             which == CLAIRE_FIELD_STATE;
+    if (state_field ? !c->state_valid : !c->have_velocity) {
+        set_error("field %d not available: call claire_ctx_set_velocity first", which);
+        return CLAIRE_ESTATE;
+    }
+    if ((which == CLAIRE_FIELD_STATE || which == CLAIRE_FIELD_GRAD_STATE ||
+         which == CLAIRE_FIELD_ADJOINT) && (index < 0 || index > c->nt)) {
+        set_error("index %d out of range [0, %d]", index, c->nt);
+        return CLAIRE_EINVAL;
+    }
+    switch (which) {
+    case CLAIRE_FIELD_DISP_PLUS: return copy_d2d(out, c->dp, 3 * n, c->s);
+    case CLAIRE_FIELD_DISP_MINUS: return copy_d2d(out, c->dm, 3 * n, c->s);
+    case CLAIRE_FIELD_STATE: return copy_d2d(out, c->m + index * n, n, c->s);
+    case CLAIRE_FIELD_GRAD_STATE: return copy_d2d(out, c->gm + index * 3 * n, 3 * n, c->s);
+    case CLAIRE_FIELD_ADJOINT: return copy_d2d(out, c->lam + index * n, n, c->s);
+    case CLAIRE_FIELD_DIVV: return copy_d2d(out, c->divv, n, c->s);
+    default: set_error("unknown field %d", which); return CLAIRE_EINVAL;
+    }
+}
+
+// ------------------------------------------------------------- stateless
+namespace {
+struct Owned {
+    claire_ctx* c = nullptr;
+    ~Owned() { if (c) claire_ctx_destroy(c); }
+};
+}  // namespace
+
+int claire_transport(const float* m0, const float* v, const int nx[3], int nt, float* m1_out,
+                     void* stream) {
+    CL_TRY(check_ptr(m0, "m0"));
+    CL_TRY(check_ptr(v, "v"));
+    CL_TRY(check_ptr(m1_out, "m1_out"));
+    Owned o;
+    CL_TRY(claire_ctx_create(&o.c, nx, nt, 1.0, 1, stream));
+    CL_TRY(claire_ctx_set_images(o.c, m0, m0));
+    CL_TRY(copy_d2d(o.c->v, v, 3 * o.c->g.n, o.c->s));
+    CL_TRY(run_state(o.c));
+    CL_TRY(copy_d2d(m1_out, o.c->m + (long long)nt * o.c->g.n, o.c->g.n, o.c->s));
+    CL_HIP(hipStreamSynchronize(o.c->s));
+    return 0;
+}
+
+int claire_gradient(const float* m0, const float* m1, const float* v, const int nx[3],
+                    double alpha, int nt, int reg_order, float* g_out, double* J_out,
+                    void* stream) {
+    Owned o;
+    CL_TRY(claire_ctx_create(&o.c, nx, nt, alpha, reg_order, stream));
+    CL_TRY(claire_ctx_set_images(o.c, m0, m1));
+    CL_TRY(claire_ctx_set_velocity(o.c, v));
+    CL_TRY(claire_ctx_gradient(o.c, g_out, J_out));
+    CL_HIP(hipStreamSynchronize(o.c->s));
+    return 0;
+}
+
+int claire_hessian_matvec(const float* m0, const float* m1, const float* v, const float* vt,
+                          const int nx[3], double alpha, int nt, int reg_order, float* Hvt_out,
+                          void* stream) {
+    Owned o;
+    CL_TRY(claire_ctx_create(&o.c, nx, nt, alpha, reg_order, stream));
+    CL_TRY(claire_ctx_set_images(o.c, m0, m1));
+    CL_TRY(claire_ctx_set_velocity(o.c, v));
+    CL_TRY(claire_ctx_hessian_matvec(o.c, vt, Hvt_out));
+    CL_HIP(hipStreamSynchronize(o.c->s));
+    return 0;
+}
+
+int claire_solve(const float* m0, const float* m1, const int nx[3], double alpha, int nt,
+                 const claire_opts* opts, float* v_inout, claire_stats* stats, void* stream) {
+    const int reg = opts ? opts->reg_order : 1;
+    Owned o;
+    CL_TRY(claire_ctx_create(&o.c, nx, nt, alpha, reg, stream));
+    CL_TRY(claire_ctx_set_images(o.c, m0, m1));
+    return claire_ctx_solve(o.c, opts, v_inout, stats);
+}
+
+}  // extern "C"

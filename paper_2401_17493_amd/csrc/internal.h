@@ -1,0 +1,124 @@
+// Internal declarations of the gfx950 registration engine (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "claire.h"
+
+namespace claire {
+
+// Grid geometry: power-of-two extents, masks and shifts for periodic wrap.
+struct Geo {
+    int n1, n2, n3;     // extents
+    int l1, l2, l3;     // log2 of the extents
+    int nh;             // n3/2 + 1: length of a half-complex x3 row
+    long long n;        // voxels
+    long long nspec;    // half-complex spectrum length n1*n2*nh
+};
+
+Geo make_geo(const int nx[3]);
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define CL_HIP(call)                                                      \
+    do {                                                                  \
+        hipError_t _e = (call);                                           \
+        if (_e != hipSuccess) return ::claire::hip_fail(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define CL_TRY(call)                                                      \
+    do {                                                                  \
+        int _s = (call);                                                  \
+        if (_s < 0) return _s;                                            \
+    } while (0)
+
+#define CL_LAUNCH_CHECK() CL_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ spectral
+// Workspace of the FFT-based operators: three half-complex spectra and the
+// twiddle table exp(-2 pi i k / tw_n), k < tw_n, tw_n = max extent.
+struct SpectralWork {
+    float2* spec = nullptr;   // [3][nspec]
+    float2* tw = nullptr;     // [tw_n]
+    int tw_n = 0;
+};
+
+int spectral_init(SpectralWork& w, const Geo& g);
+void spectral_free(SpectralWork& w);
+
+// Multiplier applied between the forward and inverse transforms.
+enum SpecMode {
+    SPEC_GRAD = 0,     // 1 input  -> 3 outputs: i k_a (Nyquist zero)
+    SPEC_DIV = 1,      // 3 inputs -> 1 output:  sum_a i k_a u_a
+    SPEC_REG = 2,      // 3 -> 3: alpha |k|^{2p}
+    SPEC_REG_INV = 3,  // 3 -> 3: 1/(alpha |k|^{2p}), 1 at k = 0
+};
+
+// out = F^{-1}[ sigma F[in] ] for the mode above; in and out are real fields
+// (SoA). `add` (nullable, same shape as out) is added to the result and
+// `scale` multiplies the spectral part. in and out must not overlap.
+int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in,
+                   float* out, double alpha, int p, hipStream_t s,
+                   const float* add = nullptr);
+
+// ------------------------------------------------------ semi-Lagrangian
+int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus,
+                     double ht, hipStream_t s);
+int launch_interp(const Geo& g, const float* f, int nfield, const float* disp,
+                  float* out, hipStream_t s);
+int launch_make_A(const Geo& g, const float* divv, const float* dminus, float* A,
+                  double ht, hipStream_t s);
+int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* lamT,
+                         hipStream_t s);
+int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus,
+                        const float* A, float* lam, hipStream_t s);
+int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt,
+                           float* w0, double ht, hipStream_t s);
+int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
+                          const float* gradm_next, const float* vt, float* out,
+                          float coef, float sign, hipStream_t s);
+int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt,
+                    const float* add, float* out, hipStream_t s);
+int launch_defgrad_step(const Geo& g, const float* F, const float* G, const float* dplus,
+                        float* Fout, double ht, int first, hipStream_t s);
+int launch_det(const Geo& g, const float* F, double* det, hipStream_t s);
+
+// --------------------------------------------------------- reductions
+// Device partial buffer + pinned host landing zone for float64 scalars.
+struct Reducer {
+    double* partial = nullptr;   // [kBlocks * 4]
+    double* result = nullptr;    // [8] device
+    double* host = nullptr;      // [8] pinned host
+};
+constexpr int kRedBlocks = 1024;
+
+int reducer_init(Reducer& r);
+void reducer_free(Reducer& r);
+
+// Enqueue reductions; results land in r.result[slot]. fetch() copies
+// r.result to r.host and synchronises the stream.
+int red_dot(Reducer& r, const float* a, const float* b, long long n, int slot, hipStream_t s);
+int red_sumsq_diff(Reducer& r, const float* a, const float* b, long long n, int slot,
+                   hipStream_t s);
+int red_absmax(Reducer& r, const float* a, long long n, int slot, hipStream_t s);
+// min, sum, max and count of non-positive values of a float64 array -> slots 0..3
+int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
+int red_fetch(Reducer& r, hipStream_t s);
+
+// ------------------------------------------------------- vector updates
+// y = a*x + y
+int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s);
+// y = x + b*y
+int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s);
+// y = x + b*z
+int launch_lincomb(const float* x, const float* z, float* y, float b, long long n,
+                   hipStream_t s);
+int launch_fill(float* y, float value, long long n, hipStream_t s);
+int launch_scale_copy(const float* x, float* y, float a, long long n, hipStream_t s);
+int launch_check_finite(const float* x, long long n, int* flag, hipStream_t s);
+
+}  // namespace claire

@@ -1,0 +1,404 @@
+// Semi-Lagrangian kernels (Section 2.5.2) with tricubic Lagrange
+// interpolation (Section 2.5.4, p = 3).
+//
+// Departure points are stored as displacements in voxel units, d = (y - x)/h,
+// so a query is (integer grid index) + (float displacement): the stencil
+// origin floor(d) is exact and a zero displacement returns grid values
+// bit-for-bit. One thread per output voxel, x3 fastest across the wavefront;
+// the 4x4x4 stencil is read with wrapped indices (extents are powers of two,
+// so the wrap is a mask).
+
+#include "internal.h"
+
+namespace claire {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct G3 {
+    int m1, m2, m3;     // extent - 1 (masks)
+    int l2, l3;         // shifts
+    int s1;             // l2 + l3
+};
+
+G3 make_g3(const Geo& g) {
+    G3 r;
+    r.m1 = g.n1 - 1;
+    r.m2 = g.n2 - 1;
+    r.m3 = g.n3 - 1;
+    r.l2 = g.l2;
+    r.l3 = g.l3;
+    r.s1 = g.l2 + g.l3;
+    return r;
+}
+
+// Cubic Lagrange basis through nodes -1, 0, 1, 2 at fractional offset t.
+__device__ __forceinline__ void cubic_basis(float t, float w[4]) {
+    const float tp = t + 1.0f, tm = t - 1.0f, tmm = t - 2.0f;
+    const float a = t * tm;             // t (t - 1)
+    const float b = tp * tmm;           // (t + 1)(t - 2)
+    w[0] = -(1.0f / 6.0f) * a * tmm;
+    w[1] = 0.5f * b * tm;
+    w[2] = -0.5f * b * t;
+    w[3] = (1.0f / 6.0f) * a * tp;
+}
+
+// Stencil of the point (i1, i2, i3) + (d1, d2, d3).
+struct Stencil {
+    int o1[4], o2[4], o3[4];
+    float w1[4], w2[4], w3[4];
+};
+
+__device__ __forceinline__ void make_stencil(const G3& g, int i1, int i2, int i3, float d1,
+                                             float d2, float d3, Stencil& st) {
+    const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
+    const int b1 = i1 + (int)f1 - 1, b2 = i2 + (int)f2 - 1, b3 = i3 + (int)f3 - 1;
+    cubic_basis(d1 - f1, st.w1);
+    cubic_basis(d2 - f2, st.w2);
+    cubic_basis(d3 - f3, st.w3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        st.o1[q] = ((b1 + q) & g.m1) << g.s1;
+        st.o2[q] = ((b2 + q) & g.m2) << g.l3;
+        st.o3[q] = (b3 + q) & g.m3;
+    }
+}
+
+template <int NF>
+__device__ __forceinline__ void gather(const float* __restrict__ f, long long fstride,
+                                       const Stencil& st, float out[NF]) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k] = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = st.o1[a] + st.o2[b];
+            const float wab = st.w1[a] * st.w2[b];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) {
+                const float* p = f + k * fstride + row;
+                float t = st.w3[0] * p[st.o3[0]];
+                t = fmaf(st.w3[1], p[st.o3[1]], t);
+                t = fmaf(st.w3[2], p[st.o3[2]], t);
+                t = fmaf(st.w3[3], p[st.o3[3]], t);
+                out[k] = fmaf(wab, t, out[k]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void coords(const G3& g, long long idx, int& i1, int& i2, int& i3) {
+    i3 = (int)(idx & g.m3);
+    i2 = (int)((idx >> g.l3) & g.m2);
+    i1 = (int)(idx >> g.s1);
+}
+
+// RK2 backtrace for +v and -v (Section 2.5.2):
+//   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
+// c_a = h_t / h_a converts velocity to voxels per step.
+__global__ __launch_bounds__(kThreads) void k_backtrace(const float* __restrict__ v,
+                                                        float* __restrict__ dp,
+                                                        float* __restrict__ dm, G3 g, long long n,
+                                                        float c1, float c2, float c3) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    const float v1 = v[idx], v2 = v[n + idx], v3 = v[2 * n + idx];
+    Stencil st;
+    float vy[3];
+    // forward characteristics (+v)
+    make_stencil(g, i1, i2, i3, -c1 * v1, -c2 * v2, -c3 * v3, st);
+    gather<3>(v, n, st, vy);
+    dp[idx] = -0.5f * c1 * (v1 + vy[0]);
+    dp[n + idx] = -0.5f * c2 * (v2 + vy[1]);
+    dp[2 * n + idx] = -0.5f * c3 * (v3 + vy[2]);
+    // backward characteristics (-v): y~ = x + h_t v(x), y = x + (h_t/2)(v(x) + v(y~))
+    make_stencil(g, i1, i2, i3, c1 * v1, c2 * v2, c3 * v3, st);
+    gather<3>(v, n, st, vy);
+    dm[idx] = 0.5f * c1 * (v1 + vy[0]);
+    dm[n + idx] = 0.5f * c2 * (v2 + vy[1]);
+    dm[2 * n + idx] = 0.5f * c3 * (v3 + vy[2]);
+}
+
+// out[k](x) = f[k](x + d(x)), k < nf (nf <= 4 per launch chunk)
+template <int NF>
+__global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ f,
+                                                     const float* __restrict__ d,
+                                                     float* __restrict__ out, G3 g, long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    Stencil st;
+    make_stencil(g, i1, i2, i3, d[idx], d[n + idx], d[2 * n + idx], st);
+    float r[NF];
+    gather<NF>(f, n, st, r);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k * n + idx] = r[k];
+}
+
+// Factor of one RK2 step of the continuity equation along -v:
+// u^j = u^{j+1}(y-) [1 + (h_t/2)(D(y-) + D + h_t D(y-) D)], D = div v.
+__global__ __launch_bounds__(kThreads) void k_make_A(const float* __restrict__ D,
+                                                     const float* __restrict__ dm,
+                                                     float* __restrict__ A, G3 g, long long n,
+                                                     float ht) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    Stencil st;
+    make_stencil(g, i1, i2, i3, dm[idx], dm[n + idx], dm[2 * n + idx], st);
+    float Dy;
+    gather<1>(D, n, st, &Dy);
+    const float Dx = D[idx];
+    A[idx] = 1.0f + 0.5f * ht * (Dy + Dx + ht * Dy * Dx);
+}
+
+__global__ __launch_bounds__(kThreads) void k_final_adjoint(const float* __restrict__ mT,
+                                                            const float* __restrict__ m1,
+                                                            float* __restrict__ lam, long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx < n) lam[idx] = m1[idx] - mT[idx];
+}
+
+// lam^j = A * lam^{j+1}(y-)
+__global__ __launch_bounds__(kThreads) void k_adjoint_step(const float* __restrict__ ln,
+                                                           const float* __restrict__ dm,
+                                                           const float* __restrict__ A,
+                                                           float* __restrict__ l, G3 g,
+                                                           long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    Stencil st;
+    make_stencil(g, i1, i2, i3, dm[idx], dm[n + idx], dm[2 * n + idx], st);
+    float u;
+    gather<1>(ln, n, st, &u);
+    l[idx] = A[idx] * u;
+}
+
+// w^0 = (h_t/2) f^0 with f^0 = -grad m^0 . v~
+__global__ __launch_bounds__(kThreads) void k_inc_first(const float* __restrict__ gm,
+                                                        const float* __restrict__ vt,
+                                                        float* __restrict__ w, long long n,
+                                                        float half_ht) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    const float f = gm[idx] * vt[idx] + gm[n + idx] * vt[n + idx] + gm[2 * n + idx] * vt[2 * n + idx];
+    w[idx] = -half_ht * f;
+}
+
+// Incremental state step, RK2 along +v with the grid source f^j = -grad m^j . v~
+// merged into the gathered field (interpolation is linear):
+//   m~^{j+1} = (m~^j + (h_t/2) f^j)(y+) + (h_t/2) f^{j+1}.
+// The gather source w^j carries m~^j + (h_t/2) f^j; this kernel writes
+//   sign * (w^j(y+) + coef * f^{j+1}),
+// coef = h_t for an intermediate step (giving w^{j+1}), h_t/2 for the last
+// step (giving m~^{nt}; sign -1 turns it into lambda~^{nt} = -m~^{nt}).
+__global__ __launch_bounds__(kThreads) void k_inc_step(const float* __restrict__ w,
+                                                       const float* __restrict__ dp,
+                                                       const float* __restrict__ gm,
+                                                       const float* __restrict__ vt,
+                                                       float* __restrict__ out, G3 g, long long n,
+                                                       float coef, float sign) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    Stencil st;
+    make_stencil(g, i1, i2, i3, dp[idx], dp[n + idx], dp[2 * n + idx], st);
+    float u;
+    gather<1>(w, n, st, &u);
+    const float f = -(gm[idx] * vt[idx] + gm[n + idx] * vt[n + idx] + gm[2 * n + idx] * vt[2 * n + idx]);
+    out[idx] = sign * (u + coef * f);
+}
+
+// out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2)
+__global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__ lam,
+                                                       const float* __restrict__ gm, int nt,
+                                                       const float* __restrict__ add,
+                                                       float* __restrict__ out, long long n,
+                                                       float ht) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    for (int j = 0; j <= nt; ++j) {
+        const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
+        const float l = c * lam[(long long)j * n + idx];
+        const float* gj = gm + (long long)j * 3 * n;
+        acc0 = fmaf(l, gj[idx], acc0);
+        acc1 = fmaf(l, gj[n + idx], acc1);
+        acc2 = fmaf(l, gj[2 * n + idx], acc2);
+    }
+    if (add) {
+        acc0 += add[idx];
+        acc1 += add[n + idx];
+        acc2 += add[2 * n + idx];
+    }
+    out[idx] = acc0;
+    out[n + idx] = acc1;
+    out[2 * n + idx] = acc2;
+}
+
+// Deformation gradient, eq. (e:def-grad): D F/Dt = (grad v) F along +v,
+// RK2 along the characteristics: F_y = F^j(y+), f0 = G(y+) F_y,
+// F~ = F_y + h_t f0, f1 = G(x) F~, F^{j+1} = F_y + (h_t/2)(f0 + f1).
+// F, G: [9][n] row-major 3x3 (G_ab = d_b v_a). first: F^0 = I (no gather).
+__global__ __launch_bounds__(kThreads) void k_defgrad(const float* __restrict__ F,
+                                                      const float* __restrict__ G,
+                                                      const float* __restrict__ dp,
+                                                      float* __restrict__ Fo, G3 g, long long n,
+                                                      float ht, int first) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords(g, idx, i1, i2, i3);
+    Stencil st;
+    make_stencil(g, i1, i2, i3, dp[idx], dp[n + idx], dp[2 * n + idx], st);
+    float Gy[9], Fy[9], Gx[9];
+    gather<9>(G, n, st, Gy);
+    if (first) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Fy[q] = (q % 4 == 0) ? 1.f : 0.f;
+    } else {
+        gather<9>(F, n, st, Fy);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Gx[q] = G[q * n + idx];
+    float f0[9], Ft[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) s = fmaf(Gy[3 * a + b], Fy[3 * b + c], s);
+            f0[3 * a + c] = s;
+            Ft[3 * a + c] = Fy[3 * a + c] + ht * s;
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) s = fmaf(Gx[3 * a + b], Ft[3 * b + c], s);
+            Fo[(3 * a + c) * n + idx] = Fy[3 * a + c] + 0.5f * ht * (f0[3 * a + c] + s);
+        }
+}
+
+// det of the 3x3 field in float64
+__global__ __launch_bounds__(kThreads) void k_det(const float* __restrict__ F,
+                                                  double* __restrict__ det, long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    double a[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a[q] = (double)F[q * n + idx];
+    det[idx] = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+               a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus, double ht,
+                     hipStream_t s) {
+    const float c1 = (float)(ht * g.n1 / (2.0 * M_PI));
+    const float c2 = (float)(ht * g.n2 / (2.0 * M_PI));
+    const float c3 = (float)(ht * g.n3 / (2.0 * M_PI));
+    hipLaunchKernelGGL(k_backtrace, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, v, dplus, dminus,
+                       make_g3(g), g.n, c1, c2, c3);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, float* out,
+                  hipStream_t s) {
+    const G3 g3 = make_g3(g);
+    int k = 0;
+    while (k < nfield) {
+        const int chunk = (nfield - k >= 3) ? 3 : (nfield - k);
+        const float* fk = f + (long long)k * g.n;
+        float* ok = out + (long long)k * g.n;
+        if (chunk == 3)
+            hipLaunchKernelGGL(k_interp<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
+        else if (chunk == 2)
+            hipLaunchKernelGGL(k_interp<2>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
+        else
+            hipLaunchKernelGGL(k_interp<1>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
+        CL_LAUNCH_CHECK();
+        k += chunk;
+    }
+    return 0;
+}
+
+int launch_make_A(const Geo& g, const float* divv, const float* dminus, float* A, double ht,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_make_A, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, divv, dminus, A,
+                       make_g3(g), g.n, (float)ht);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* lamT,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_final_adjoint, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, mT, m1, lamT,
+                       g.n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus, const float* A,
+                        float* lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_step, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, lam_next,
+                       dminus, A, lam, make_g3(g), g.n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, float* w0,
+                           double ht, hipStream_t s) {
+    hipLaunchKernelGGL(k_inc_first, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0, vt, w0,
+                       g.n, (float)(0.5 * ht));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
+                          const float* gradm_next, const float* vt, float* out, float coef,
+                          float sign, hipStream_t s) {
+    hipLaunchKernelGGL(k_inc_step, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, w_prev, dplus,
+                       gradm_next, vt, out, make_g3(g), g.n, coef, sign);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, const float* add,
+                    float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, lam, gradm, nt, add,
+                       out, g.n, (float)(1.0 / nt));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_defgrad_step(const Geo& g, const float* F, const float* G, const float* dplus,
+                        float* Fout, double ht, int first, hipStream_t s) {
+    hipLaunchKernelGGL(k_defgrad, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, F, G, dplus, Fout,
+                       make_g3(g), g.n, (float)ht, first);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_det(const Geo& g, const float* F, double* det, hipStream_t s) {
+    hipLaunchKernelGGL(k_det, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, F, det, g.n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace claire

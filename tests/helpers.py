@@ -1,0 +1,42 @@
+"""Shared helpers of the tests: seeded workloads, float32 rounding, error norms."""
+import numpy as np
+
+import oracle as O
+from synthetic import (WORKLOADS, bandlimited_velocity, ellipsoid_phantom, gaussian_blobs,
+                       noise)
+
+
+def f32(a):
+    """Round to float32 and back: the oracle sees exactly the GPU's inputs."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def rel_err(got, ref):
+    """max |got - ref| / max |ref| (max-norm relative error)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.abs(ref).max()
+    return float(np.abs(got - ref).max() / (den if den > 0 else 1.0))
+
+
+def blob_problem(n=(32, 32, 32), nt=4, seed=1001, kmax=4, vmax=0.5, sigma=0.3):
+    """Template, reference (oracle transport by v*, inverse crime) and v*."""
+    grid = O.Grid(n)
+    m0 = f32(gaussian_blobs(n, seed, sigma=sigma))
+    vstar = f32(bandlimited_velocity(n, seed + 1000, kmax, vmax))
+    m1 = f32(O.transport(grid, m0, vstar, nt))
+    return grid, m0, m1, vstar
+
+
+def phantom_problem(name, n=None, nt=None):
+    """Ellipsoid workload of the named recipe, optionally at another size."""
+    w = dict(WORKLOADS[name])
+    n = tuple(n or w["n"])
+    nt = nt or w["nt"]
+    grid = O.Grid(n)
+    seed = w["seed"]
+    clean = ellipsoid_phantom(n, seed)
+    vstar = f32(bandlimited_velocity(n, seed + 1000, min(w["kmax"], n[0] // 2 - 1), w["vmax"]))
+    m0 = f32(clean + noise(n, seed + 2000, w["noise"]))
+    m1 = f32(O.transport(grid, clean, vstar, nt) + noise(n, seed + 3000, w["noise"]))
+    return grid, m0, m1, vstar, w

@@ -1,0 +1,231 @@
+"""Parity of the HIP path with the FP64 oracle, element by element.
+
+Float32 fields and FFTs against float64: the bar is a max-norm relative error
+of 1e-5 (|gpu - oracle|_inf <= 1e-5 |oracle|_inf) for every field the hot
+path produces. Inputs are rounded to float32 before the oracle sees them.
+Bit-exact cases: zero and whole-voxel displacements.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import blob_problem, f32, phantom_problem, rel_err
+from synthetic import bandlimited_velocity, ellipsoid_phantom, trig_field
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_17493_amd import claire
+    return claire
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+SHAPES = [(32, 32, 32), (16, 32, 64), (64, 16, 8), (8, 8, 8), (128, 64, 32)]
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_spectral_operators(C, n):
+    grid = O.Grid(n)
+    u = f32(ellipsoid_phantom(n, 3))
+    v = f32(bandlimited_velocity(n, 4, min(4, min(n) // 2 - 1), 1.0))
+    for p in (1, 2):
+        with C.Context(n, 4, 3e-2, p) as ctx:
+            g = host(ctx.spectral(C.OP_GRAD, dev(u)))
+            assert rel_err(g, O.spectral_gradient(grid, u)) < TOL
+            d = host(ctx.spectral(C.OP_DIV, dev(v)))
+            assert rel_err(d, O.spectral_divergence(grid, v)) < TOL
+            r = host(ctx.spectral(C.OP_REG, dev(v)))
+            assert rel_err(r, O.regularization_operator(grid, v, 3e-2, p)) < TOL
+            z = host(ctx.spectral(C.OP_REG_INV, dev(v)))
+            assert rel_err(z, O.precondition(grid, v, 3e-2, p)) < TOL
+            z2 = host(ctx.precond(dev(v)))
+            assert np.array_equal(z, z2)
+
+
+def test_spectral_exact_on_trig_polynomial(C):
+    n = (64, 32, 16)
+    u, terms = trig_field(n, 7, terms=5, kfrac=1.0)
+    grid = O.Grid(n)
+    with C.Context(n, 4, 1.0, 1) as ctx:
+        g = host(ctx.spectral(C.OP_GRAD, dev(u)))
+    # the oracle is exact here (pinned); float32 leaves ~1e-6
+    assert rel_err(g, O.spectral_gradient(grid, f32(u))) < TOL
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (16, 64, 8)])
+def test_interpolation(C, n):
+    rng = np.random.default_rng(5)
+    f = f32(rng.standard_normal((2,) + n))
+    d = f32(np.stack([rng.uniform(-12, 12, n) for _ in range(3)]))
+    with C.Context(n, 4, 1.0, 1) as ctx:
+        got = host(ctx.interpolate(dev(f), dev(d)))
+        ref = O.interpolate(f, d)
+        assert rel_err(got, ref) < TOL
+        # zero and whole-voxel displacements are exact copies / rolls
+        z = host(ctx.interpolate(dev(f[0]), dev(np.zeros((3,) + n))))
+        assert np.array_equal(z, f[0])
+        s = (3, -5, 2 * n[2] + 1)
+        ds = np.stack([np.full(n, float(k)) for k in s])
+        r = host(ctx.interpolate(dev(f[0]), dev(ds)))
+        assert np.array_equal(r, np.roll(f[0], tuple(-k for k in s), axis=(0, 1, 2)))
+
+
+def _check_setup(C, ctx, st, nt, tol=TOL):
+    dp = host(ctx.get_field(C.FIELD_DISP_PLUS))
+    dm = host(ctx.get_field(C.FIELD_DISP_MINUS))
+    # displacements: compare in voxels against the largest displacement
+    assert rel_err(dp, st.d_plus) < tol
+    assert rel_err(dm, st.d_minus) < tol
+    for j in range(nt + 1):
+        assert rel_err(host(ctx.get_field(C.FIELD_STATE, j)), st.m[j]) < tol
+        assert rel_err(host(ctx.get_field(C.FIELD_GRAD_STATE, j)), st.grad_m[j]) < tol
+        assert rel_err(host(ctx.get_field(C.FIELD_ADJOINT, j)), st.lam[j]) < tol
+    assert rel_err(host(ctx.get_field(C.FIELD_DIVV)), st.div_v) < tol
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_setup_gradient_and_matvec_blobs32(C, p):
+    nt, alpha = 4, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v = f32(0.5 * vstar)     # off-grid departure points
+    vt = f32(bandlimited_velocity(grid.n, 77, 4, 0.5))
+    st = O.setup_velocity(grid, m0, m1, v, alpha, nt, p)
+    with C.Context(grid.n, nt, alpha, p) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(v))
+        _check_setup(C, ctx, st, nt)
+        g, J = ctx.gradient()
+        assert rel_err(host(g), st.g) < TOL
+        assert abs(J - st.J) <= TOL * abs(st.J)
+        hv = host(ctx.hessian_matvec(dev(vt)))
+        assert rel_err(hv, O.hessian_matvec(st, vt)) < TOL
+        # objective alone (line-search trial) equals the setup's J
+        assert abs(ctx.objective(dev(v)) - st.J) <= TOL * abs(st.J)
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_matvec_small_nt_and_noncubic(C, nt):
+    n = (16, 32, 8)
+    grid = O.Grid(n)
+    m0 = f32(ellipsoid_phantom(n, 9))
+    vstar = f32(bandlimited_velocity(n, 10, 3, 0.8))
+    m1 = f32(O.transport(grid, m0, vstar, nt))
+    v = f32(0.7 * vstar)
+    vt = f32(bandlimited_velocity(n, 11, 3, 1.0))
+    st = O.setup_velocity(grid, m0, m1, v, 5e-3, nt, 1)
+    with C.Context(n, nt, 5e-3, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(v))
+        g, J = ctx.gradient()
+        assert rel_err(host(g), st.g) < TOL
+        assert rel_err(host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt)) < TOL
+
+
+def test_phantom128_h2(C):
+    grid, m0, m1, vstar, w = phantom_problem("ellipsoids128")
+    nt, alpha, p = w["nt"], 1e-3, 2
+    v = f32(0.6 * vstar)
+    vt = f32(bandlimited_velocity(grid.n, 12, 8, 1.0))
+    st = O.setup_velocity(grid, m0, m1, v, alpha, nt, p)
+    with C.Context(grid.n, nt, alpha, p) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(v))
+        _check_setup(C, ctx, st, nt)
+        g, J = ctx.gradient()
+        assert rel_err(host(g), st.g) < TOL
+        assert abs(J - st.J) <= TOL * abs(st.J)
+        assert rel_err(host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt)) < TOL
+
+
+def test_stateless_calls(C):
+    nt, alpha = 4, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v = f32(0.5 * vstar)
+    vt = f32(bandlimited_velocity(grid.n, 78, 4, 0.5))
+    st = O.setup_velocity(grid, m0, m1, v, alpha, nt, 1)
+    mt = host(C.transport(dev(m0), dev(v), nt))
+    assert rel_err(mt, st.m[-1]) < TOL
+    g, J = C.gradient(dev(m0), dev(m1), dev(v), alpha, nt, 1)
+    assert rel_err(host(g), st.g) < TOL and abs(J - st.J) <= TOL * abs(st.J)
+    hv = C.hessian_matvec(dev(m0), dev(m1), dev(v), dev(vt), alpha, nt, 1)
+    assert rel_err(host(hv), O.hessian_matvec(st, vt)) < TOL
+
+
+def test_one_gn_step_ten_matvecs_blobs32(C):
+    # one Gauss--Newton step from v = 0 with exactly 10 PCG matvecs
+    nt, alpha = 4, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v_ref, st_ref, stats_ref = O.gn_solve(grid, m0, m1, nt, 1, [alpha], max_gn=1, fixed_pcg=10)
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v, stats = ctx.solve(max_gn=1, fixed_pcg_iters=10)
+        vh = host(v)
+    assert stats["matvecs"] == 10 and stats["gn_iters"] == 1
+    assert stats["linesearch_trials"] == stats_ref.ls_trials
+    assert rel_err(vh, v_ref) < 1e-4
+    assert abs(stats["J0"] - stats_ref.J0) <= TOL * stats_ref.J0
+    assert abs(stats["J"] - stats_ref.J) <= 1e-4 * stats_ref.J
+
+
+def test_full_solve_blobs32(C):
+    nt, alpha = 4, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v_ref, st_ref, s_ref = O.gn_solve(grid, m0, m1, nt, 1, [alpha])
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v, stats = ctx.solve()
+        vh = host(v)
+    assert stats["status"] == 0
+    assert stats["gn_iters"] == s_ref.gn_iters and stats["matvecs"] == s_ref.matvecs
+    assert stats["rel_grad"] <= 5e-2
+    assert rel_err(vh, v_ref) < 1e-4
+    assert abs(stats["J"] - s_ref.J) <= 1e-4 * s_ref.J
+
+
+def test_detdefgrad(C):
+    nt = 4
+    grid, m0, m1, vstar = blob_problem()
+    v = f32(1.5 * vstar)
+    ref = O.deformation_determinant(grid, v, nt)
+    with C.Context(grid.n, nt, 1e-2, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(v))
+        det, s = ctx.detdefgrad(want_field=True)
+        d = host(det)
+    assert rel_err(d, ref) < TOL
+    assert abs(s["min"] - ref.min()) <= TOL * abs(ref).max()
+    assert abs(s["max"] - ref.max()) <= TOL * abs(ref).max()
+    assert abs(s["mean"] - ref.mean()) <= TOL * abs(ref).max()
+    assert s["nonpositive"] == int((ref <= 0).sum())
+
+
+def test_errors_are_reported(C):
+    with pytest.raises(C.ClaireError) as e:
+        C.Context((12, 16, 16), 4, 1.0, 1)
+    assert e.value.code == -1
+    with pytest.raises(C.ClaireError):
+        C.Context((16, 16, 16), 0, 1.0, 1)
+    with pytest.raises(C.ClaireError):
+        C.Context((16, 16, 16), 4, -1.0, 1)
+    with C.Context((16, 16, 16), 2, 1.0, 1) as ctx:
+        with pytest.raises(C.ClaireError) as e:
+            ctx.hessian_matvec(torch.zeros((3, 16, 16, 16), device="cuda"))
+        assert e.value.code == -5
+        with pytest.raises(ValueError):
+            ctx.set_images(torch.zeros((16, 16, 8), device="cuda"),
+                           torch.zeros((16, 16, 16), device="cuda"))
