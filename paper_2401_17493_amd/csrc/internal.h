@@ -39,11 +39,14 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line);
 #define CL_LAUNCH_CHECK() CL_HIP(hipGetLastError())
 
 // ------------------------------------------------------------ spectral
-// Workspace of the FFT-based operators: three half-complex spectra and the
-// twiddle table exp(-2 pi i k / tw_n), k < tw_n, tw_n = max extent.
+// Workspace of the FFT-based operators: three half-complex spectra in float
+// and in double (the forward half of alpha L runs in double), and the twiddle
+// tables exp(-2 pi i k / tw_n), k < tw_n, tw_n = max extent.
 struct SpectralWork {
-    float2* spec = nullptr;   // [3][nspec]
-    float2* tw = nullptr;     // [tw_n]
+    float2* spec = nullptr;     // [3][nspec]
+    double2* spec64 = nullptr;  // [3][nspec]
+    float2* tw = nullptr;       // [tw_n]
+    double2* tw64 = nullptr;    // [tw_n]
     int tw_n = 0;
 };
 
@@ -59,8 +62,8 @@ enum SpecMode {
 };
 
 // out = F^{-1}[ sigma F[in] ] for the mode above; in and out are real fields
-// (SoA). `add` (nullable, same shape as out) is added to the result and
-// `scale` multiplies the spectral part. in and out must not overlap.
+// (SoA). `add` (nullable, same shape as out) is added to the result. in and
+// out must not overlap.
 int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in,
                    float* out, double alpha, int p, hipStream_t s,
                    const float* add = nullptr);

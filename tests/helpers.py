@@ -40,3 +40,30 @@ def phantom_problem(name, n=None, nt=None):
     m0 = f32(clean + noise(n, seed + 2000, w["noise"]))
     m1 = f32(O.transport(grid, clean, vstar, nt) + noise(n, seed + 3000, w["noise"]))
     return grid, m0, m1, vstar, w
+
+
+class Parity:
+    """Collects (name, error, tolerance) triples, prints them, and fails at
+    the end if any error exceeds its tolerance (so one run shows them all)."""
+
+    def __init__(self, label):
+        self.label = label
+        self.rows = []
+
+    def rel(self, name, got, ref, tol):
+        e = rel_err(got, ref)
+        self.rows.append((name, e, tol))
+        print("PARITY %s %-28s rel_err %.3e  tol %.1e  %s"
+              % (self.label, name, e, tol, "ok" if e <= tol else "FAIL"), flush=True)
+        return e
+
+    def value(self, name, got, ref, tol):
+        e = abs(got - ref) / max(abs(ref), 1e-300)
+        self.rows.append((name, e, tol))
+        print("PARITY %s %-28s rel_err %.3e  tol %.1e  %s"
+              % (self.label, name, e, tol, "ok" if e <= tol else "FAIL"), flush=True)
+        return e
+
+    def done(self):
+        bad = [(n, e, t) for n, e, t in self.rows if not e <= t]
+        assert not bad, bad

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import blob_problem, f32, phantom_problem, rel_err
+from helpers import Parity, blob_problem, f32, phantom_problem, rel_err
 from synthetic import bandlimited_velocity, ellipsoid_phantom, trig_field
 
 torch = pytest.importorskip("torch")
@@ -43,18 +43,20 @@ def test_spectral_operators(C, n):
     grid = O.Grid(n)
     u = f32(ellipsoid_phantom(n, 3))
     v = f32(bandlimited_velocity(n, 4, min(4, min(n) // 2 - 1), 1.0))
+    P = Parity("spectral%s" % (n,))
     for p in (1, 2):
         with C.Context(n, 4, 3e-2, p) as ctx:
             g = host(ctx.spectral(C.OP_GRAD, dev(u)))
-            assert rel_err(g, O.spectral_gradient(grid, u)) < TOL
+            P.rel("grad p%d" % p, g, O.spectral_gradient(grid, u), TOL)
             d = host(ctx.spectral(C.OP_DIV, dev(v)))
-            assert rel_err(d, O.spectral_divergence(grid, v)) < TOL
+            P.rel("div p%d" % p, d, O.spectral_divergence(grid, v), TOL)
             r = host(ctx.spectral(C.OP_REG, dev(v)))
-            assert rel_err(r, O.regularization_operator(grid, v, 3e-2, p)) < TOL
+            P.rel("reg p%d" % p, r, O.regularization_operator(grid, v, 3e-2, p), TOL)
             z = host(ctx.spectral(C.OP_REG_INV, dev(v)))
-            assert rel_err(z, O.precondition(grid, v, 3e-2, p)) < TOL
+            P.rel("reg_inv p%d" % p, z, O.precondition(grid, v, 3e-2, p), TOL)
             z2 = host(ctx.precond(dev(v)))
             assert np.array_equal(z, z2)
+    P.done()
 
 
 def test_spectral_exact_on_trig_polynomial(C):
@@ -85,17 +87,17 @@ def test_interpolation(C, n):
         assert np.array_equal(r, np.roll(f[0], tuple(-k for k in s), axis=(0, 1, 2)))
 
 
-def _check_setup(C, ctx, st, nt, tol=TOL):
+def _check_setup(C, ctx, st, nt, P, tol=TOL):
     dp = host(ctx.get_field(C.FIELD_DISP_PLUS))
     dm = host(ctx.get_field(C.FIELD_DISP_MINUS))
     # displacements: compare in voxels against the largest displacement
-    assert rel_err(dp, st.d_plus) < tol
-    assert rel_err(dm, st.d_minus) < tol
+    P.rel("disp+", dp, st.d_plus, tol)
+    P.rel("disp-", dm, st.d_minus, tol)
     for j in range(nt + 1):
-        assert rel_err(host(ctx.get_field(C.FIELD_STATE, j)), st.m[j]) < tol
-        assert rel_err(host(ctx.get_field(C.FIELD_GRAD_STATE, j)), st.grad_m[j]) < tol
-        assert rel_err(host(ctx.get_field(C.FIELD_ADJOINT, j)), st.lam[j]) < tol
-    assert rel_err(host(ctx.get_field(C.FIELD_DIVV)), st.div_v) < tol
+        P.rel("m^%d" % j, host(ctx.get_field(C.FIELD_STATE, j)), st.m[j], tol)
+        P.rel("grad m^%d" % j, host(ctx.get_field(C.FIELD_GRAD_STATE, j)), st.grad_m[j], tol)
+        P.rel("lambda^%d" % j, host(ctx.get_field(C.FIELD_ADJOINT, j)), st.lam[j], tol)
+    P.rel("div v", host(ctx.get_field(C.FIELD_DIVV)), st.div_v, tol)
 
 
 @pytest.mark.parametrize("p", [1, 2])
@@ -105,17 +107,19 @@ def test_setup_gradient_and_matvec_blobs32(C, p):
     v = f32(0.5 * vstar)     # off-grid departure points
     vt = f32(bandlimited_velocity(grid.n, 77, 4, 0.5))
     st = O.setup_velocity(grid, m0, m1, v, alpha, nt, p)
+    P = Parity("blobs32 p%d" % p)
     with C.Context(grid.n, nt, alpha, p) as ctx:
         ctx.set_images(dev(m0), dev(m1))
         ctx.set_velocity(dev(v))
-        _check_setup(C, ctx, st, nt)
+        _check_setup(C, ctx, st, nt, P)
         g, J = ctx.gradient()
-        assert rel_err(host(g), st.g) < TOL
-        assert abs(J - st.J) <= TOL * abs(st.J)
+        P.rel("g", host(g), st.g, TOL)
+        P.value("J", J, st.J, TOL)
         hv = host(ctx.hessian_matvec(dev(vt)))
-        assert rel_err(hv, O.hessian_matvec(st, vt)) < TOL
+        P.rel("Hv", hv, O.hessian_matvec(st, vt), TOL)
         # objective alone (line-search trial) equals the setup's J
-        assert abs(ctx.objective(dev(v)) - st.J) <= TOL * abs(st.J)
+        P.value("J(objective)", ctx.objective(dev(v)), st.J, TOL)
+    P.done()
 
 
 @pytest.mark.parametrize("nt", [1, 2, 3])
@@ -128,12 +132,14 @@ def test_matvec_small_nt_and_noncubic(C, nt):
     v = f32(0.7 * vstar)
     vt = f32(bandlimited_velocity(n, 11, 3, 1.0))
     st = O.setup_velocity(grid, m0, m1, v, 5e-3, nt, 1)
+    P = Parity("nt%d %s" % (nt, n))
     with C.Context(n, nt, 5e-3, 1) as ctx:
         ctx.set_images(dev(m0), dev(m1))
         ctx.set_velocity(dev(v))
         g, J = ctx.gradient()
-        assert rel_err(host(g), st.g) < TOL
-        assert rel_err(host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt)) < TOL
+        P.rel("g", host(g), st.g, TOL)
+        P.rel("Hv", host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt), TOL)
+    P.done()
 
 
 def test_phantom128_h2(C):
@@ -142,14 +148,16 @@ def test_phantom128_h2(C):
     v = f32(0.6 * vstar)
     vt = f32(bandlimited_velocity(grid.n, 12, 8, 1.0))
     st = O.setup_velocity(grid, m0, m1, v, alpha, nt, p)
+    P = Parity("ellipsoids128 H2")
     with C.Context(grid.n, nt, alpha, p) as ctx:
         ctx.set_images(dev(m0), dev(m1))
         ctx.set_velocity(dev(v))
-        _check_setup(C, ctx, st, nt)
+        _check_setup(C, ctx, st, nt, P)
         g, J = ctx.gradient()
-        assert rel_err(host(g), st.g) < TOL
-        assert abs(J - st.J) <= TOL * abs(st.J)
-        assert rel_err(host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt)) < TOL
+        P.rel("g", host(g), st.g, TOL)
+        P.value("J", J, st.J, TOL)
+        P.rel("Hv", host(ctx.hessian_matvec(dev(vt))), O.hessian_matvec(st, vt), TOL)
+    P.done()
 
 
 def test_stateless_calls(C):
