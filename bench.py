@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: Gauss--Newton--Krylov time-to-solution + Hessian matvecs/s.
+
+One step = one full registration solve (Algorithm 1 with PCG, Armijo line
+search and the final det F check) on the 256^3 nested-ellipsoid workload:
+H1 seminorm, alpha = 1e-3, n_t = 4, gradient tolerance 5e-2, from v = 0,
+inputs resident in HBM. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Besides the solve time (``value``, seconds) the line carries the Hessian
+matvec throughput, the HBM roofline of the dominant kernel (average launch
+duration measured here with HIP events) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GN-Krylov time-to-solution at 256^3 (s, gtol 5e-2) + Hessian matvecs/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per voxel of one launch of each timed kernel (float32):
+#   inc-state step: gather source w^j (4), y+ displacement (12), grad m^{j+1} (12),
+#                   v~ (12), output (4);
+#   adjoint step:   gather source (4), y- displacement (12), A (4), output (4);
+#   assembly:       lambda~^j (4 (nt+1)), grad m^j (12 (nt+1)), alpha L v~ (12), output (12);
+#   copy:           3 floats in, 3 floats out.
+def kernel_bytes_per_voxel(kernel, nt):
+    return {"inc_state_step": 44, "adjoint_step": 24,
+            "assemble": 16 * (nt + 1) + 24, "copy": 24}[kernel]
+
+
+def source_digest():
+    """Hash of the HIP sources: counter data taken for another build is stale."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2401_17493_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_inputs(name, torch, C):
+    import numpy as np
+
+    from synthetic import (WORKLOADS, bandlimited_velocity, ellipsoid_phantom, noise)
+    w = WORKLOADS[name]
+    n, seed = w["n"], w["seed"]
+    clean = ellipsoid_phantom(n, seed)
+    vstar = bandlimited_velocity(n, seed + 1000, w["kmax"], w["vmax"])
+    m0 = clean + noise(n, seed + 2000, w["noise"])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa: E731
+    # the reference image: clean template transported by v* (this library's
+    # transport), plus independent noise
+    m1 = C.transport(dev(clean), dev(vstar), w["nt"]) + dev(noise(n, seed + 3000, w["noise"]))
+    torch.cuda.synchronize()
+    return w, dev(m0), m1.contiguous(), dev(vstar), (clean, vstar)
+
+
+def cpu_baseline(name, host_inputs):
+    """FP64 oracle on the host: one GN Hessian matvec at v = v*/2 (untimed
+    setup first). Returns the cpu_baseline record."""
+    import numpy as np
+
+    import oracle as O
+    from synthetic import WORKLOADS, bandlimited_velocity, noise
+    w = WORKLOADS[name]
+    n, seed, nt = w["n"], w["seed"], w["nt"]
+    clean, vstar = host_inputs
+    grid = O.Grid(n)
+    m0 = clean + noise(n, seed + 2000, w["noise"])
+    m1 = O.transport(grid, clean, vstar, nt) + noise(n, seed + 3000, w["noise"])
+    st = O.setup_velocity(grid, m0, m1, 0.5 * vstar, w["alphas"][-1], nt, w["reg_order"])
+    vt = bandlimited_velocity(n, seed + 4000, w["kmax"], 1.0)
+    t0 = time.perf_counter()
+    O.hessian_matvec(st, vt)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "Hessian matvecs/s", "cores": O.WORKERS,
+            "kind": "oracle", "seconds_per_matvec": dt,
+            "sample": "1 FP64 GN Hessian matvec at %dx%dx%d, nt=%d, v=v*/2, after an "
+                      "untimed setup (numpy/scipy.fft + C/OpenMP tricubic)" % (n + (nt,))}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ellipsoids256")
+    ap.add_argument("--matvecs", type=int, default=40, help="timed Hessian matvecs")
+    ap.add_argument("--roofline-kernel", default="inc_state_step",
+                    choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this engine has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_17493_amd import claire as C
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w, m0, m1, vstar, host_inputs = make_inputs(args.workload, torch, C)
+    n, nt = w["n"], w["nt"]
+    alpha = w["alphas"][-1]
+    levels = list(w["alphas"]) if len(w["alphas"]) > 1 else None
+    opts = dict(gtol=w.get("gtol", 5e-2), compute_det=1)
+    if levels:
+        opts["alpha_levels"] = levels
+
+    ctx = C.Context(n, nt, alpha, w["reg_order"])
+    ctx.set_images(m0, m1)
+    for _ in range(args.warmup):
+        ctx.solve(**opts)
+    torch.cuda.synchronize()
+    times, stats = [], None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, stats = ctx.solve(**opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print("step: solve %.3f s, %d GN iterations, %d matvecs" %
+              (times[-1], stats["gn_iters"], stats["matvecs"]), file=sys.stderr, flush=True)
+    tts = sum(times) / len(times)
+
+    # Hessian matvec throughput at the solution, HIP events on the context stream
+    ctx.set_velocity(v)
+    vt = (0.5 * vstar).contiguous()
+    hv = torch.empty_like(vt)
+    ctx.hessian_matvec(vt, hv)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(args.matvecs):
+        ctx.hessian_matvec(vt, hv)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms_matvec = e0.elapsed_time(e1) / args.matvecs
+
+    # roofline of the dominant kernel: algorithmic bytes / live launch duration
+    kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
+           "assemble": C.KERNEL_ASSEMBLE, "copy": C.KERNEL_COPY}[args.roofline_kernel]
+    ms_kernel = ctx.time_kernel(kid, reps=50)
+    voxels = n[0] * n[1] * n[2]
+    alg_bytes = kernel_bytes_per_voxel(args.roofline_kernel, nt) * voxels
+    achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
+    ms_copy = ctx.time_kernel(C.KERNEL_COPY, reps=50)
+    copy_gbs = 24 * voxels / (ms_copy * 1e-3) / 1e9
+    print("kernel %s: %.4f ms/launch, %.0f GB/s algorithmic; copy kernel %.0f GB/s; "
+          "matvec %.3f ms" % (args.roofline_kernel, ms_kernel, achieved, copy_gbs, ms_matvec),
+          file=sys.stderr, flush=True)
+    ctx.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(tts, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tts * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded nested-ellipsoid phantom, band-limited v*)",
+        "config": {"workload": args.workload, "grid": list(n), "nt": nt,
+                   "alpha": alpha if not levels else levels,
+                   "regularization": "H%d seminorm" % w["reg_order"],
+                   "gtol": opts["gtol"], "preconditioner": "(alpha L)^-1",
+                   "parallelism": "single GPU"},
+        "hessian_matvecs_per_s": round(1000.0 / ms_matvec, 2),
+        "ms_per_matvec": round(ms_matvec, 4),
+        "solve": {k: stats[k] for k in ("gn_iters", "matvecs", "pde_solves",
+                                        "linesearch_trials", "rel_grad", "rel_mismatch",
+                                        "J0", "J", "det_min", "det_max",
+                                        "det_nonpositive")},
+        "roofline": {"kernel": args.roofline_kernel, "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(args.roofline_kernel, args.workload),
+                     "ms_per_launch": round(ms_kernel, 5),
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "copy_kernel_GBs": round(copy_gbs, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, host_inputs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

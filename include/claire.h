@@ -178,6 +178,22 @@ enum { CLAIRE_FIELD_DISP_PLUS = 0, CLAIRE_FIELD_DISP_MINUS = 1, CLAIRE_FIELD_STA
        CLAIRE_FIELD_GRAD_STATE = 3, CLAIRE_FIELD_ADJOINT = 4, CLAIRE_FIELD_DIVV = 5 };
 int claire_ctx_get_field(claire_ctx *ctx, int which, int index, float *out);
 
+/* Average duration of one launch of a single hot-path kernel, timed with HIP
+ * events over `reps` back-to-back launches on the context's stream, with the
+ * arguments the Hessian matvec uses (needs a prior set_velocity). kernel:
+ *   CLAIRE_KERNEL_INC_STATE_STEP  one incremental-state SL step (gather of
+ *                                 w^j at y+, source -grad m^{j+1}.v~)
+ *   CLAIRE_KERNEL_ADJOINT_STEP    one (incremental) adjoint SL step
+ *   CLAIRE_KERNEL_ASSEMBLE        h_t sum_j c_j lambda~^j grad m^j + alpha L v~
+ *   CLAIRE_KERNEL_COPY            a plain copy of 3n floats (bandwidth and
+ *                                 counter calibration)
+ * *avg_ms (host) receives milliseconds per launch. The launches overwrite the
+ * context's scratch buffers (incremental fields, adjoint history), not v, g
+ * or the state. */
+enum { CLAIRE_KERNEL_INC_STATE_STEP = 0, CLAIRE_KERNEL_ADJOINT_STEP = 1,
+       CLAIRE_KERNEL_ASSEMBLE = 2, CLAIRE_KERNEL_COPY = 3 };
+int claire_ctx_time_kernel(claire_ctx *ctx, int kernel, int reps, double *avg_ms);
+
 /* --------------------------------------------- stateless convenience calls
  * Each builds a context, runs, and destroys it (setup cost paid per call). */
 

@@ -59,7 +59,7 @@ import numpy as np
 import scipy.fft as sfft
 
 TWO_PI = 2.0 * np.pi
-WORKERS = os.cpu_count() or 1
+WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _C_SRC = os.path.join(_HERE, "tricubic_oracle.c")

@@ -18,6 +18,7 @@ import torch
 from . import _lib as L
 
 OP_GRAD, OP_DIV, OP_REG, OP_REG_INV = 0, 1, 2, 3
+KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY = 0, 1, 2, 3
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
 WARNINGS = {1: "gauss-newton max iterations", 2: "line search failed",
@@ -197,6 +198,12 @@ class Context:
         _check(self.lib.claire_ctx_get_field(self._h, int(which), int(index),
                                              _ptr(out, shape, "out")))
         return out
+
+    def time_kernel(self, kernel: int, reps: int = 20) -> float:
+        """Average milliseconds per launch of one hot-path kernel (HIP events)."""
+        ms = ctypes.c_double()
+        _check(self.lib.claire_ctx_time_kernel(self._h, int(kernel), int(reps), ctypes.byref(ms)))
+        return ms.value
 
 
 # ------------------------------------------------------ stateless functions

@@ -697,6 +697,49 @@ int claire_ctx_get_field(claire_ctx* c, int which, int index, float* out) {
     }
 }
 
+int claire_ctx_time_kernel(claire_ctx* c, int kernel, int reps, double* avg_ms) {
+    CL_TRY(need(c, true));
+    if (!avg_ms) { set_error("avg_ms is NULL"); return CLAIRE_EINVAL; }
+    if (reps < 1 || reps > 100000) { set_error("reps must be in [1, 100000]"); return CLAIRE_EINVAL; }
+    if (kernel < CLAIRE_KERNEL_INC_STATE_STEP || kernel > CLAIRE_KERNEL_COPY) {
+        set_error("unknown kernel id %d", kernel);
+        return CLAIRE_EINVAL;
+    }
+    const Geo& g = c->g;
+    const long long n = g.n;
+    const double ht = 1.0 / c->nt;
+    auto launch = [&]() -> int {
+        switch (kernel) {
+        case CLAIRE_KERNEL_INC_STATE_STEP:
+            return launch_inc_state_step(g, c->w0, c->dp, c->gm + 3 * n, c->regv, c->w1,
+                                         (float)ht, 1.0f, c->s);
+        case CLAIRE_KERNEL_ADJOINT_STEP:
+            return launch_adjoint_step(g, c->lam + n, c->dm, c->A, c->lam, c->s);
+        case CLAIRE_KERNEL_ASSEMBLE:
+            return launch_assemble(g, c->lam, c->gm, c->nt, c->tmp3, c->tmp3, c->s);
+        default:
+            return launch_scale_copy(c->regv, c->tmp3, 1.0f, 3 * n, c->s);
+        }
+    };
+    CL_TRY(launch());   // warm-up
+    hipEvent_t e0, e1;
+    CL_HIP(hipEventCreate(&e0));
+    CL_HIP(hipEventCreate(&e1));
+    int rc = 0;
+    if (hipEventRecord(e0, c->s) != hipSuccess) rc = CLAIRE_EDEVICE;
+    for (int i = 0; i < reps && rc == 0; ++i) rc = launch();
+    float ms = 0.f;
+    if (rc == 0 && hipEventRecord(e1, c->s) != hipSuccess) rc = CLAIRE_EDEVICE;
+    if (rc == 0 && hipEventSynchronize(e1) != hipSuccess) rc = CLAIRE_EDEVICE;
+    if (rc == 0 && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = CLAIRE_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == CLAIRE_EDEVICE) set_error("HIP event timing failed");
+    if (rc < 0) return rc;
+    *avg_ms = (double)ms / reps;
+    return 0;
+}
+
 // ------------------------------------------------------------- stateless
 namespace {
 struct Owned {

@@ -148,6 +148,23 @@ __device__ __forceinline__ void load_twiddles(C* tw_s, const C* __restrict__ tw,
     for (int q = tid; q < T; q += kThreads) tw_s[q] = tw[q];
 }
 
+// Copy `total` (<= kThreads*E) values into LDS: all of a thread's loads are
+// issued before any store, so their latencies overlap.
+template <int E, typename C, typename F>
+__device__ __forceinline__ void stage(C* buf, int total, int tid, F load) {
+    C tmp[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < total) tmp[i] = load(e);
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < total) buf[e] = tmp[i];
+    }
+}
+
 // ---------------------------------------------------------------- pass 1
 // n1*n2 rows of n3 reals -> rows of nh bins in precision C. Grid (rows/RB, ncomp).
 template <int E, typename C>
@@ -165,10 +182,10 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
     const float2* src = reinterpret_cast<const float2*>(in + blockIdx.y * n) + row0 * M;
     C* dst = out + blockIdx.y * nspec + row0 * nh;
     load_twiddles(tw_s, tw, 1 << logT, tid);
-    for (int e = tid; e < RB * M; e += kThreads) {
+    stage<E>(buf, RB * M, tid, [&](int e) {
         const float2 x = src[e];
-        buf[e] = cx<C>((R)x.x, (R)x.y);
-    }
+        return cx<C>((R)x.x, (R)x.y);
+    });
     __syncthreads();
     lds_fft<-1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
     // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) w^k (Z[k] - conj Z[M-k]), w = exp(-2 pi i / n3)
@@ -205,18 +222,18 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     // Z[k] = (X[k] + conj X[M-k]) + i conj(w^k) (X[k] - conj X[M-k]); the
     // imaginary parts of the DC and Nyquist bins are ignored (real signal).
     const int tsh = logT - l3;
-    for (int e = tid; e < RB * M; e += kThreads) {
+    stage<E>(buf, RB * M, tid, [&](int e) {
         const int r = e >> (l3 - 1), k = e & (M - 1);
         const float2* x = src + (long long)r * nh;
         float2 xk = x[k];
         float2 xm = x[M - k];
         if (k == 0) { xk.y = 0.f; xm.y = 0.f; }
         const float2 xc = cconj(xm);
-        const float2 s = cadd(xk, xc);
-        const float2 d = csub(xk, xc);
+        const float2 sm = cadd(xk, xc);
+        const float2 df = csub(xk, xc);
         const float2 w = cconj(tw_s[k << tsh]);
-        buf[e] = cadd(s, times_i(cmul(w, d)));
-    }
+        return cadd(sm, times_i(cmul(w, df)));
+    });
     __syncthreads();
     lds_fft<+1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
     float2* dst = reinterpret_cast<float2*>(out + blockIdx.y * n) + row0 * M;
@@ -245,10 +262,10 @@ __global__ __launch_bounds__(kThreads) void k_c2c_cols(C* __restrict__ data, int
     const int cw = min(CW, nh - c0);
     C* base = data + blockIdx.z * nspec + blockIdx.y * ystride + c0;
     load_twiddles(tw_s, tw, 1 << logT, tid);
-    for (int e = tid; e < N * CW; e += kThreads) {
+    stage<E>(buf, N * CW, tid, [&](int e) {
         const int r = e / CW, c = e - r * CW;
-        buf[e] = (c < cw) ? base[r * stride + c] : cx<C>(0, 0);
-    }
+        return (c < cw) ? base[r * stride + c] : cx<C>(0, 0);
+    });
     __syncthreads();
     lds_fft<DIR, E, true>(buf, logN, CW, 1, CW, tw_s, logT, tid);
     for (int e = tid; e < N * CW; e += kThreads) {
@@ -300,10 +317,10 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     const int k2 = signed_k(blockIdx.y, m.n2);
     load_twiddles(tw_d, tw64, 1 << logT, tid);
     load_twiddles(tw_f, tw32, 1 << logT, tid);
-    for (int e = tid; e < N * CW; e += kThreads) {
+    stage<E>(A, N * CW, tid, [&](int e) {
         const int r = e / CW, c = e - r * CW;
-        A[e] = (c < cw) ? in[off + r * stride + c] : make_double2(0.0, 0.0);
-    }
+        return (c < cw) ? in[off + r * stride + c] : make_double2(0.0, 0.0);
+    });
     __syncthreads();
     lds_fft<-1, E, true>(A, l1, CW, 1, CW, tw_d, logT, tid);
     // multiply in double, narrow to float: read all, barrier, write all
@@ -356,10 +373,10 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     load_twiddles(tw_s, tw, 1 << logT, tid);
 
     auto load_tile = [&](float2* dstb, const float2* src) {
-        for (int e = tid; e < N * CW; e += kThreads) {
+        stage<E>(dstb, N * CW, tid, [&](int e) {
             const int r = e / CW, c = e - r * CW;
-            dstb[e] = (c < cw) ? src[off + r * stride + c] : make_float2(0.f, 0.f);
-        }
+            return (c < cw) ? src[off + r * stride + c] : make_float2(0.f, 0.f);
+        });
     };
     auto store_tile = [&](const float2* srcb, float2* dstp) {
         for (int e = tid; e < N * CW; e += kThreads) {

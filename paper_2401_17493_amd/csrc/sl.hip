@@ -94,6 +94,222 @@ __device__ __forceinline__ void coords(const G3& g, long long idx, int& i1, int&
     i1 = (int)(idx >> g.s1);
 }
 
+// ------------------------------------------------------------------------
+// LDS-staged single-field gathers (the state, adjoint and incremental steps).
+//
+// A workgroup owns an output brick of up to 8 x 8 x 16 voxels. It reads the
+// brick's displacements, reduces the bounding box of all 4x4x4 stencils,
+// copies that box of the source field into LDS with row-contiguous loads,
+// and interpolates from LDS: 64 LDS reads per voxel instead of 64 scattered
+// global loads, which otherwise saturate the vector-memory address path long
+// before HBM. A brick whose box exceeds the LDS budget (extreme local
+// deformation) gathers directly from global memory instead. Bricks are
+// handed out so that each XCD sweeps a contiguous slab of the grid, keeping
+// the halo rows shared by neighbouring bricks in one L2.
+constexpr int kBoxCap = 12288;     // floats of LDS per workgroup (48 KiB)
+constexpr int kVox = 4;            // voxels per thread (brick <= 1024 voxels)
+constexpr int kBatch = 8;          // independent loads in flight per thread while staging
+
+struct Brick {
+    int lb1, lb2, lb3;     // log2 of the brick extents
+    int lnb2, lnb3;        // log2 of the bricks per axis along x2, x3
+    int nbricks;
+};
+
+Brick make_brick(const Geo& g) {
+    Brick b;
+    b.lb1 = g.l1 < 3 ? g.l1 : 3;
+    b.lb2 = g.l2 < 3 ? g.l2 : 3;
+    b.lb3 = g.l3 < 4 ? g.l3 : 4;
+    b.lnb2 = g.l2 - b.lb2;
+    b.lnb3 = g.l3 - b.lb3;
+    b.nbricks = 1 << (g.l1 - b.lb1 + b.lnb2 + b.lnb3);
+    return b;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Epilogues: combine the interpolated value u at voxel i with pointwise data.
+// load() fetches the pointwise inputs early (before the box is staged) so
+// their latency overlaps the staging; store() writes the result.
+struct EpiStore {        // out = u
+    float* out;
+    struct Pre {};
+    __device__ Pre load(long long) const { return Pre{}; }
+    __device__ void store(long long i, float u, const Pre&) const { out[i] = u; }
+};
+struct EpiScale {        // out = A u  (continuity-equation step along -v)
+    const float* A;
+    float* out;
+    struct Pre { float a; };
+    __device__ Pre load(long long i) const { return Pre{A[i]}; }
+    __device__ void store(long long i, float u, const Pre& p) const { out[i] = p.a * u; }
+};
+struct EpiIncState {     // out = sign (u + coef f), f = -grad m . v~
+    const float* gm;
+    const float* vt;
+    float* out;
+    long long n;
+    float coef, sign;
+    struct Pre { float f; };
+    __device__ Pre load(long long i) const {
+        return Pre{-(gm[i] * vt[i] + gm[n + i] * vt[n + i] + gm[2 * n + i] * vt[2 * n + i])};
+    }
+    __device__ void store(long long i, float u, const Pre& p) const {
+        out[i] = sign * (u + coef * p.f);
+    }
+};
+struct EpiMakeA {        // out = 1 + (h_t/2)(D(y-) + D + h_t D(y-) D)
+    const float* D;
+    float* out;
+    float ht;
+    struct Pre { float dx; };
+    __device__ Pre load(long long i) const { return Pre{D[i]}; }
+    __device__ void store(long long i, float u, const Pre& p) const {
+        out[i] = 1.0f + 0.5f * ht * (u + p.dx + ht * u * p.dx);
+    }
+};
+
+template <class Epi>
+__global__ __launch_bounds__(kThreads) void k_gather_lds(const float* __restrict__ src,
+                                                         const float* __restrict__ d, Epi epi,
+                                                         G3 g, Brick br, long long n) {
+    __shared__ float box[kBoxCap];
+    __shared__ int red[kThreads / 64][6];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int bid = blockIdx.x;
+    if ((br.nbricks & 7) == 0) bid = (bid & 7) * (br.nbricks >> 3) + (bid >> 3);
+    const int bb3 = bid & ((1 << br.lnb3) - 1);
+    const int bb2 = (bid >> br.lnb3) & ((1 << br.lnb2) - 1);
+    const int bb1 = bid >> (br.lnb3 + br.lnb2);
+    const int bvol = 1 << (br.lb1 + br.lb2 + br.lb3);
+
+    float dd[kVox][3];
+    int q[kVox][3];
+    long long gi[kVox];
+    typename Epi::Pre pre[kVox];
+    int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
+    int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
+#pragma unroll
+    for (int k = 0; k < kVox; ++k) {
+        const int v = tid + k * kThreads;
+        gi[k] = -1;
+        if (v < bvol) {
+            const int i3 = (bb3 << br.lb3) + (v & ((1 << br.lb3) - 1));
+            const int i2 = (bb2 << br.lb2) + ((v >> br.lb3) & ((1 << br.lb2) - 1));
+            const int i1 = (bb1 << br.lb1) + (v >> (br.lb3 + br.lb2));
+            const long long idx = ((long long)i1 << g.s1) + ((long long)i2 << g.l3) + i3;
+            gi[k] = idx;
+            dd[k][0] = d[idx];
+            dd[k][1] = d[n + idx];
+            dd[k][2] = d[2 * n + idx];
+            pre[k] = epi.load(idx);
+            q[k][0] = i1 + (int)floorf(dd[k][0]) - 1;
+            q[k][1] = i2 + (int)floorf(dd[k][1]) - 1;
+            q[k][2] = i3 + (int)floorf(dd[k][2]) - 1;
+            mn1 = min(mn1, q[k][0]); mx1 = max(mx1, q[k][0]);
+            mn2 = min(mn2, q[k][1]); mx2 = max(mx2, q[k][1]);
+            mn3 = min(mn3, q[k][2]); mx3 = max(mx3, q[k][2]);
+        }
+    }
+    mn1 = wave_min(mn1); mn2 = wave_min(mn2); mn3 = wave_min(mn3);
+    mx1 = wave_max(mx1); mx2 = wave_max(mx2); mx3 = wave_max(mx3);
+    if (lane == 0) {
+        red[wid][0] = mn1; red[wid][1] = mn2; red[wid][2] = mn3;
+        red[wid][3] = mx1; red[wid][4] = mx2; red[wid][5] = mx3;
+    }
+    __syncthreads();
+    int lo1 = red[0][0], lo2 = red[0][1], lo3 = red[0][2];
+    int hi1 = red[0][3], hi2 = red[0][4], hi3 = red[0][5];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) {
+        lo1 = min(lo1, red[w][0]); lo2 = min(lo2, red[w][1]); lo3 = min(lo3, red[w][2]);
+        hi1 = max(hi1, red[w][3]); hi2 = max(hi2, red[w][4]); hi3 = max(hi3, red[w][5]);
+    }
+    const int e1 = hi1 - lo1 + 4, e2 = hi2 - lo2 + 4, e3 = hi3 - lo3 + 4;
+    const long long vol = (long long)e1 * e2 * e3;
+
+    if (vol <= kBoxCap) {
+        // stage the source box [e1][e2][e3] (rows along x3 are contiguous):
+        // batches of independent loads, then the LDS stores
+        const int nvol = (int)vol;
+        for (int e0 = 0; e0 < nvol; e0 += kThreads * kBatch) {
+            float tmp[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + u * kThreads + tid;
+                if (e < nvol) {
+                    const int row = e / e3, a3 = e - row * e3;
+                    const int a1 = row / e2, a2 = row - a1 * e2;
+                    tmp[u] = src[((long long)((lo1 + a1) & g.m1) << g.s1) +
+                                 ((long long)((lo2 + a2) & g.m2) << g.l3) + ((lo3 + a3) & g.m3)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + u * kThreads + tid;
+                if (e < nvol) box[e] = tmp[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kVox; ++k) {
+            if (gi[k] < 0) continue;
+            float w1[4], w2[4], w3[4];
+            cubic_basis(dd[k][0] - floorf(dd[k][0]), w1);
+            cubic_basis(dd[k][1] - floorf(dd[k][1]), w2);
+            cubic_basis(dd[k][2] - floorf(dd[k][2]), w3);
+            const int r1 = q[k][0] - lo1, r2 = q[k][1] - lo2, r3 = q[k][2] - lo3;
+            float acc = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float* p = box + ((r1 + a) * e2 + (r2 + b)) * e3 + r3;
+                    float t = w3[0] * p[0];
+                    t = fmaf(w3[1], p[1], t);
+                    t = fmaf(w3[2], p[2], t);
+                    t = fmaf(w3[3], p[3], t);
+                    acc = fmaf(w1[a] * w2[b], t, acc);
+                }
+            }
+            epi.store(gi[k], acc, pre[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kVox; ++k) {
+            if (gi[k] < 0) continue;
+            const long long idx = gi[k];
+            int i1, i2, i3;
+            coords(g, idx, i1, i2, i3);
+            Stencil st;
+            make_stencil(g, i1, i2, i3, dd[k][0], dd[k][1], dd[k][2], st);
+            float u;
+            gather<1>(src, n, st, &u);
+            epi.store(idx, u, pre[k]);
+        }
+    }
+}
+
+template <class Epi>
+int launch_gather_lds(const Geo& g, const float* src, const float* disp, const Epi& epi,
+                      hipStream_t s) {
+    const Brick br = make_brick(g);
+    hipLaunchKernelGGL(k_gather_lds<Epi>, dim3(br.nbricks), dim3(kThreads), 0, s, src, disp, epi,
+                       make_g3(g), br, g.n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
 // RK2 backtrace for +v and -v (Section 2.5.2):
 //   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
 // c_a = h_t / h_a converts velocity to voxels per step.
@@ -139,46 +355,11 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ f
     for (int k = 0; k < NF; ++k) out[k * n + idx] = r[k];
 }
 
-// Factor of one RK2 step of the continuity equation along -v:
-// u^j = u^{j+1}(y-) [1 + (h_t/2)(D(y-) + D + h_t D(y-) D)], D = div v.
-__global__ __launch_bounds__(kThreads) void k_make_A(const float* __restrict__ D,
-                                                     const float* __restrict__ dm,
-                                                     float* __restrict__ A, G3 g, long long n,
-                                                     float ht) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    int i1, i2, i3;
-    coords(g, idx, i1, i2, i3);
-    Stencil st;
-    make_stencil(g, i1, i2, i3, dm[idx], dm[n + idx], dm[2 * n + idx], st);
-    float Dy;
-    gather<1>(D, n, st, &Dy);
-    const float Dx = D[idx];
-    A[idx] = 1.0f + 0.5f * ht * (Dy + Dx + ht * Dy * Dx);
-}
-
 __global__ __launch_bounds__(kThreads) void k_final_adjoint(const float* __restrict__ mT,
                                                             const float* __restrict__ m1,
                                                             float* __restrict__ lam, long long n) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx < n) lam[idx] = m1[idx] - mT[idx];
-}
-
-// lam^j = A * lam^{j+1}(y-)
-__global__ __launch_bounds__(kThreads) void k_adjoint_step(const float* __restrict__ ln,
-                                                           const float* __restrict__ dm,
-                                                           const float* __restrict__ A,
-                                                           float* __restrict__ l, G3 g,
-                                                           long long n) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    int i1, i2, i3;
-    coords(g, idx, i1, i2, i3);
-    Stencil st;
-    make_stencil(g, i1, i2, i3, dm[idx], dm[n + idx], dm[2 * n + idx], st);
-    float u;
-    gather<1>(ln, n, st, &u);
-    l[idx] = A[idx] * u;
 }
 
 // w^0 = (h_t/2) f^0 with f^0 = -grad m^0 . v~
@@ -190,31 +371,6 @@ __global__ __launch_bounds__(kThreads) void k_inc_first(const float* __restrict_
     if (idx >= n) return;
     const float f = gm[idx] * vt[idx] + gm[n + idx] * vt[n + idx] + gm[2 * n + idx] * vt[2 * n + idx];
     w[idx] = -half_ht * f;
-}
-
-// Incremental state step, RK2 along +v with the grid source f^j = -grad m^j . v~
-// merged into the gathered field (interpolation is linear):
-//   m~^{j+1} = (m~^j + (h_t/2) f^j)(y+) + (h_t/2) f^{j+1}.
-// The gather source w^j carries m~^j + (h_t/2) f^j; this kernel writes
-//   sign * (w^j(y+) + coef * f^{j+1}),
-// coef = h_t for an intermediate step (giving w^{j+1}), h_t/2 for the last
-// step (giving m~^{nt}; sign -1 turns it into lambda~^{nt} = -m~^{nt}).
-__global__ __launch_bounds__(kThreads) void k_inc_step(const float* __restrict__ w,
-                                                       const float* __restrict__ dp,
-                                                       const float* __restrict__ gm,
-                                                       const float* __restrict__ vt,
-                                                       float* __restrict__ out, G3 g, long long n,
-                                                       float coef, float sign) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    int i1, i2, i3;
-    coords(g, idx, i1, i2, i3);
-    Stencil st;
-    make_stencil(g, i1, i2, i3, dp[idx], dp[n + idx], dp[2 * n + idx], st);
-    float u;
-    gather<1>(w, n, st, &u);
-    const float f = -(gm[idx] * vt[idx] + gm[n + idx] * vt[n + idx] + gm[2 * n + idx] * vt[2 * n + idx]);
-    out[idx] = sign * (u + coef * f);
 }
 
 // out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2)
@@ -320,6 +476,7 @@ int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus, 
 
 int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, float* out,
                   hipStream_t s) {
+    if (nfield == 1) return launch_gather_lds(g, f, disp, EpiStore{out}, s);
     const G3 g3 = make_g3(g);
     int k = 0;
     while (k < nfield) {
@@ -340,10 +497,7 @@ int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, f
 
 int launch_make_A(const Geo& g, const float* divv, const float* dminus, float* A, double ht,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_make_A, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, divv, dminus, A,
-                       make_g3(g), g.n, (float)ht);
-    CL_LAUNCH_CHECK();
-    return 0;
+    return launch_gather_lds(g, divv, dminus, EpiMakeA{divv, A, (float)ht}, s);
 }
 
 int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* lamT,
@@ -356,10 +510,7 @@ int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* 
 
 int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus, const float* A,
                         float* lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_adjoint_step, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, lam_next,
-                       dminus, A, lam, make_g3(g), g.n);
-    CL_LAUNCH_CHECK();
-    return 0;
+    return launch_gather_lds(g, lam_next, dminus, EpiScale{A, lam}, s);
 }
 
 int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, float* w0,
@@ -373,10 +524,7 @@ int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, f
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const float* gradm_next, const float* vt, float* out, float coef,
                           float sign, hipStream_t s) {
-    hipLaunchKernelGGL(k_inc_step, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, w_prev, dplus,
-                       gradm_next, vt, out, make_g3(g), g.n, coef, sign);
-    CL_LAUNCH_CHECK();
-    return 0;
+    return launch_gather_lds(g, w_prev, dplus, EpiIncState{gradm_next, vt, out, g.n, coef, sign}, s);
 }
 
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, const float* add,

@@ -50,3 +50,10 @@ def test_library_refuses_to_load_when_missing(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libclaire_gfx950.so")
     with pytest.raises(RuntimeError):
         _lib.load()
+
+
+def test_binding_imports_without_gpu():
+    # the torch binding must import (and stay syntactically valid) on the CPU
+    from paper_2401_17493_amd import claire
+    assert claire.FIELD_GRAD_STATE == 3 and claire.KERNEL_COPY == 3
+    assert hasattr(claire.Context, "time_kernel")
