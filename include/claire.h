@@ -187,11 +187,13 @@ int claire_ctx_get_field(claire_ctx *ctx, int which, int index, float *out);
  *   CLAIRE_KERNEL_ASSEMBLE        h_t sum_j c_j lambda~^j grad m^j + alpha L v~
  *   CLAIRE_KERNEL_COPY            a plain copy of 3n floats (bandwidth and
  *                                 counter calibration)
+ *   CLAIRE_KERNEL_BACKTRACE       the RK2 backtrace of +v and -v (recomputes
+ *                                 the cached departure displacements)
  * *avg_ms (host) receives milliseconds per launch. The launches overwrite the
  * context's scratch buffers (incremental fields, adjoint history), not v, g
  * or the state. */
 enum { CLAIRE_KERNEL_INC_STATE_STEP = 0, CLAIRE_KERNEL_ADJOINT_STEP = 1,
-       CLAIRE_KERNEL_ASSEMBLE = 2, CLAIRE_KERNEL_COPY = 3 };
+       CLAIRE_KERNEL_ASSEMBLE = 2, CLAIRE_KERNEL_COPY = 3, CLAIRE_KERNEL_BACKTRACE = 4 };
 int claire_ctx_time_kernel(claire_ctx *ctx, int kernel, int reps, double *avg_ms);
 
 /* --------------------------------------------- stateless convenience calls

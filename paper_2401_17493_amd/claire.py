@@ -18,7 +18,7 @@ import torch
 from . import _lib as L
 
 OP_GRAD, OP_DIV, OP_REG, OP_REG_INV = 0, 1, 2, 3
-KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY = 0, 1, 2, 3
+KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE = range(5)
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
 WARNINGS = {1: "gauss-newton max iterations", 2: "line search failed",

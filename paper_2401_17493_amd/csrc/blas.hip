@@ -46,7 +46,7 @@ __device__ double block_reduce(double v, double* sh) {
     return r;
 }
 
-// KIND 0: sum a*b; 1: sum (a-b)^2; 2: max |a|
+// KIND 0: sum a*b; 1: sum (a-b)^2; 2: max |a|; 3: sum a
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_partial(const float* __restrict__ a,
                                                       const float* __restrict__ b, long long n,
@@ -58,7 +58,8 @@ __global__ __launch_bounds__(kThreads) void k_partial(const float* __restrict__ 
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
         if (KIND == 0) acc += (double)a[i] * (double)b[i];
         else if (KIND == 1) { const double d = (double)a[i] - (double)b[i]; acc += d * d; }
-        else acc = fmax(acc, fabs((double)a[i]));
+        else if (KIND == 2) acc = fmax(acc, fabs((double)a[i]));
+        else acc += (double)a[i];
     }
     acc = block_reduce<OP>(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -120,6 +121,17 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ 
                                                       long long n) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i < n) y[i] = fmaf(b, z[i], x[i]);
+}
+
+// als_a = (r_a - mean_a) + mu als_a for the three components of a vector field
+__global__ __launch_bounds__(kThreads) void k_als_update(const float* __restrict__ r,
+                                                         float* __restrict__ als, float m0,
+                                                         float m1, float m2, float mu,
+                                                         long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= 3 * n) return;
+    const float mean = (i < n) ? m0 : (i < 2 * n ? m1 : m2);
+    als[i] = fmaf(mu, als[i], r[i] - mean);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ y, float v, long long n) {
@@ -190,6 +202,10 @@ int red_absmax(Reducer& r, const float* a, long long n, int slot, hipStream_t s)
     return red_generic<2>(r, a, a, n, slot, s);
 }
 
+int red_sum(Reducer& r, const float* a, long long n, int slot, hipStream_t s) {
+    return red_generic<3>(r, a, a, n, slot, s);
+}
+
 int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s) {
     const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_partial_stats, dim3(nb), dim3(kThreads), 0, s, a, n, r.partial);
@@ -222,6 +238,14 @@ int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
 
 int launch_lincomb(const float* x, const float* z, float* y, float b, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, z, y, b, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_als_update(const float* r, float* als, const double mean[3], float mu, long long n,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_als_update, dim3(blocks_for(3 * n)), dim3(kThreads), 0, s, r, als,
+                       (float)mean[0], (float)mean[1], (float)mean[2], mu, n);
     CL_LAUNCH_CHECK();
     return 0;
 }

@@ -79,6 +79,8 @@ struct claire_ctx {
     float* w0 = nullptr;     // [n] incremental-state ping-pong
     float* w1 = nullptr;     // [n]
     float* tmp3 = nullptr;   // [3][n]
+    int* box_p = nullptr;    // per-brick stencil boxes of dp
+    int* box_m = nullptr;    // per-brick stencil boxes of dm
     SpectralWork sw;
     Reducer red;
     int* flag = nullptr;     // device int (non-finite check)
@@ -90,6 +92,7 @@ struct claire_ctx {
     float* sd = nullptr;
     float* hs = nullptr;
     float* vtrial = nullptr;
+    float* als = nullptr;    // alpha L s, kept by recursion inside PCG
 
     bool have_images = false;
     bool state_valid = false;      // dp, dm, m valid for the content of v
@@ -143,6 +146,8 @@ int ctx_alloc(claire_ctx* c) {
     CL_TRY(dalloc(&c->w1, n));
     CL_TRY(dalloc(&c->tmp3, 3 * n));
     CL_TRY(dalloc(&c->flag, 1));
+    CL_TRY(dalloc(&c->box_p, brick_table_ints(c->g)));
+    CL_TRY(dalloc(&c->box_m, brick_table_ints(c->g)));
     CL_TRY(spectral_init(c->sw, c->g));
     CL_TRY(reducer_init(c->red));
     return 0;
@@ -151,9 +156,11 @@ int ctx_alloc(claire_ctx* c) {
 void ctx_release(claire_ctx* c) {
     float* bufs[] = {c->m0, c->m1, c->v, c->dp, c->dm, c->m, c->gm, c->divv, c->A, c->grad,
                      c->regv, c->lam, c->w0, c->w1, c->tmp3, c->vt, c->r, c->z, c->sd, c->hs,
-                     c->vtrial};
+                     c->vtrial, c->als};
     for (float* b : bufs) dfree(b);
     dfree(c->flag);
+    dfree(c->box_p);
+    dfree(c->box_m);
     spectral_free(c->sw);
     reducer_free(c->red);
 }
@@ -170,10 +177,12 @@ int run_state(claire_ctx* c) {
     const Geo& g = c->g;
     const double ht = 1.0 / c->nt;
     CL_TRY(launch_backtrace(g, c->v, c->dp, c->dm, ht, c->s));
+    CL_TRY(launch_brick_boxes(g, c->dp, c->box_p, c->s));
+    CL_TRY(launch_brick_boxes(g, c->dm, c->box_m, c->s));
     CL_TRY(copy_d2d(c->m, c->m0, g.n, c->s));
     for (int j = 0; j < c->nt; ++j)
         CL_TRY(launch_interp(g, c->m + (long long)j * g.n, 1, c->dp, c->m + (long long)(j + 1) * g.n,
-                             c->s));
+                             c->s, c->box_p));
     c->state_valid = true;
     return 0;
 }
@@ -196,12 +205,12 @@ int run_setup(claire_ctx* c) {
                               c->gm + (long long)j * 3 * n, c->alpha, c->p, c->s));
     // div v and the adjoint step factor
     CL_TRY(spectral_apply(g, c->sw, SPEC_DIV, c->v, c->divv, c->alpha, c->p, c->s));
-    CL_TRY(launch_make_A(g, c->divv, c->dm, c->A, ht, c->s));
+    CL_TRY(launch_make_A(g, c->divv, c->dm, c->A, ht, c->s, c->box_m));
     // adjoint (eq. e:adjoint): lam^nt = -(m^nt - m1), lam^j = A lam^{j+1}(y-)
     CL_TRY(launch_final_adjoint(g, c->m + nt * n, c->m1, c->lam + nt * n, c->s));
     for (int j = nt - 1; j >= 0; --j)
         CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
-                                   c->lam + (long long)j * n, c->s));
+                                   c->lam + (long long)j * n, c->s, c->box_m));
     // reduced gradient (eq. e:rgrad), trapezoid in time
     CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->regv, c->grad, c->s));
     CL_TRY(red_absmax(c->red, c->grad, 3 * n, 2, c->s));
@@ -220,7 +229,9 @@ int run_setup(claire_ctx* c) {
 }
 
 // Gauss--Newton Hessian matvec (eqs. e:matvec, e:incstate, e:incadj).
-int run_matvec(claire_ctx* c, const float* vt, float* out) {
+// reg_part: alpha L vt when the caller already has it (PCG), else NULL and
+// it is computed here by FFT.
+int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -232,22 +243,26 @@ int run_matvec(claire_ctx* c, const float* vt, float* out) {
     for (int j = 0; j < nt; ++j) {
         const float* gnext = c->gm + (long long)(j + 1) * 3 * n;
         if (j + 1 < nt) {
-            CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, nxt, (float)ht, 1.0f, c->s));
+            CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, nxt, (float)ht, 1.0f, c->s,
+                                         c->box_p));
             float* t = src;
             src = nxt;
             nxt = t;
         } else {
             CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, c->lam + (long long)nt * n,
-                                         (float)(0.5 * ht), -1.0f, c->s));
+                                         (float)(0.5 * ht), -1.0f, c->s, c->box_p));
         }
     }
     // incremental adjoint (GN), backward in time
     for (int j = nt - 1; j >= 0; --j)
         CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
-                                   c->lam + (long long)j * n, c->s));
+                                   c->lam + (long long)j * n, c->s, c->box_m));
     // H v~ = alpha L v~ + h_t sum_j c_j lambda~^j grad m^j
-    CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
-    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->tmp3, out, c->s));
+    if (!reg_part) {
+        CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
+        reg_part = c->tmp3;
+    }
+    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s));
     return 0;
 }
 
@@ -271,6 +286,7 @@ int ensure_solver_buffers(claire_ctx* c) {
     if (!c->sd) CL_TRY(dalloc(&c->sd, n3));
     if (!c->hs) CL_TRY(dalloc(&c->hs, n3));
     if (!c->vtrial) CL_TRY(dalloc(&c->vtrial, n3));
+    if (!c->als) CL_TRY(dalloc(&c->als, n3));
     return 0;
 }
 
@@ -281,8 +297,14 @@ struct PcgResult {
 
 // PCG (Algorithm 2) on H v~ = -g with M = alpha L; v~^0 = 0. Stopping per
 // Section 2.5.5: ||r||_inf <= eta ||g||_inf, or a fixed number of matvecs.
+//
+// The regularisation part of H s needs no FFT here: with z = (alpha L)^{-1} r
+// (mean passed through), alpha L z = r - mean(r), so the directions
+// s_{l+1} = z_{l+1} + mu s_l satisfy
+//   alpha L s_{l+1} = (r_{l+1} - mean(r_{l+1})) + mu alpha L s_l,
+// which is carried along in c->als; only the data part of H s is computed.
 int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
-    const long long n3 = 3 * c->g.n;
+    const long long n = c->g.n, n3 = 3 * n;
     const hipStream_t s = c->s;
     const double gn = c->gnorm;
     const double eta = (o.forcing == 1) ? std::fmin(0.5, gn) : std::fmin(0.5, std::sqrt(gn));
@@ -294,12 +316,16 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
     CL_TRY(copy_d2d(c->sd, c->z, n3, s));
     CL_TRY(red_dot(c->red, c->r, c->z, n3, 0, s));
+    for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
     CL_TRY(red_fetch(c->red, s));
     double rz = c->red.host[0];
+    double mean[3] = {c->red.host[3] / n, c->red.host[4] / n, c->red.host[5] / n};
+    CL_TRY(launch_fill(c->als, 0.f, n3, s));
+    CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
     res = PcgResult();
     bool converged = false;
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs));
+        CL_TRY(run_matvec(c, c->sd, c->hs, c->als));
         ++res.its;
         CL_TRY(red_dot(c->red, c->sd, c->hs, n3, 0, s));
         CL_TRY(red_fetch(c->red, s));
@@ -314,15 +340,18 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
         CL_TRY(launch_axpy(c->hs, c->r, (float)(-kappa), n3, s));
         if (res.its == limit) break;
-        // preconditioned residual and the stopping norm in one host round trip
+        // preconditioned residual, stopping norm and residual means in one round trip
         CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
         CL_TRY(red_absmax(c->red, c->r, n3, 1, s));
         CL_TRY(red_dot(c->red, c->z, c->r, n3, 2, s));
+        for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
         CL_TRY(red_fetch(c->red, s));
         if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
         const double rz_new = c->red.host[2];
         const double mu = rz_new / rz;
+        for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
         CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
+        CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }
     if (!fixed && !converged && res.its >= limit) {
@@ -602,19 +631,22 @@ int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {
     }
     const Geo& g = c->g;
     const long long n = g.n;
-    float* G = nullptr;
-    float* F = nullptr;
-    float* Fo = nullptr;
+    float* G = nullptr;    // [9][n] grad v, G_ab = d_b v_a
+    float* Gy = nullptr;   // [9][n] G at y+
+    float* F = nullptr;    // [9][n]
+    float* Fy = nullptr;   // [9][n] F^j at y+
     double* det = det_out;
     int rc = 0;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(c->s);
         dfree(G);
+        dfree(Gy);
         dfree(F);
-        dfree(Fo);
+        dfree(Fy);
         if (!det_out) dfree(det);
     };
-    if ((rc = dalloc(&G, 9 * n)) < 0 || (rc = dalloc(&F, 9 * n)) < 0 || (rc = dalloc(&Fo, 9 * n)) < 0 ||
+    if ((rc = dalloc(&G, 9 * n)) < 0 || (rc = dalloc(&Gy, 9 * n)) < 0 ||
+        (rc = dalloc(&F, 9 * n)) < 0 || (rc = dalloc(&Fy, 9 * n)) < 0 ||
         (!det_out && (rc = dalloc(&det, n)) < 0)) {
         cleanup();
         return rc;
@@ -623,11 +655,14 @@ int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {
     for (int a = 0; a < 3 && rc >= 0; ++a)
         rc = spectral_apply(g, c->sw, SPEC_GRAD, c->v + (long long)a * n, G + (long long)a * 3 * n,
                             c->alpha, c->p, c->s);
-    for (int j = 0; j < c->nt && rc >= 0; ++j) {
-        rc = launch_defgrad_step(g, F, G, c->dp, Fo, ht, j == 0, c->s);
-        float* t = F;
-        F = Fo;
-        Fo = t;
+    for (int q = 0; q < 9 && rc >= 0; ++q)
+        rc = launch_interp(g, G + (long long)q * n, 1, c->dp, Gy + (long long)q * n, c->s, c->box_p);
+    if (rc >= 0) rc = launch_defgrad_update(g, nullptr, Gy, G, F, ht, c->s);
+    for (int j = 1; j < c->nt && rc >= 0; ++j) {
+        for (int q = 0; q < 9 && rc >= 0; ++q)
+            rc = launch_interp(g, F + (long long)q * n, 1, c->dp, Fy + (long long)q * n, c->s,
+                               c->box_p);
+        if (rc >= 0) rc = launch_defgrad_update(g, Fy, Gy, G, F, ht, c->s);
     }
     if (rc >= 0) rc = launch_det(g, F, det, c->s);
     if (rc >= 0) rc = red_stats_f64(c->red, det, n, c->s);
@@ -701,7 +736,7 @@ int claire_ctx_time_kernel(claire_ctx* c, int kernel, int reps, double* avg_ms) 
     CL_TRY(need(c, true));
     if (!avg_ms) { set_error("avg_ms is NULL"); return CLAIRE_EINVAL; }
     if (reps < 1 || reps > 100000) { set_error("reps must be in [1, 100000]"); return CLAIRE_EINVAL; }
-    if (kernel < CLAIRE_KERNEL_INC_STATE_STEP || kernel > CLAIRE_KERNEL_COPY) {
+    if (kernel < CLAIRE_KERNEL_INC_STATE_STEP || kernel > CLAIRE_KERNEL_BACKTRACE) {
         set_error("unknown kernel id %d", kernel);
         return CLAIRE_EINVAL;
     }
@@ -712,11 +747,13 @@ int claire_ctx_time_kernel(claire_ctx* c, int kernel, int reps, double* avg_ms) 
         switch (kernel) {
         case CLAIRE_KERNEL_INC_STATE_STEP:
             return launch_inc_state_step(g, c->w0, c->dp, c->gm + 3 * n, c->regv, c->w1,
-                                         (float)ht, 1.0f, c->s);
+                                         (float)ht, 1.0f, c->s, c->box_p);
         case CLAIRE_KERNEL_ADJOINT_STEP:
-            return launch_adjoint_step(g, c->lam + n, c->dm, c->A, c->lam, c->s);
+            return launch_adjoint_step(g, c->lam + n, c->dm, c->A, c->lam, c->s, c->box_m);
         case CLAIRE_KERNEL_ASSEMBLE:
             return launch_assemble(g, c->lam, c->gm, c->nt, c->tmp3, c->tmp3, c->s);
+        case CLAIRE_KERNEL_BACKTRACE:
+            return launch_backtrace(g, c->v, c->dp, c->dm, ht, c->s);
         default:
             return launch_scale_copy(c->regv, c->tmp3, 1.0f, 3 * n, c->s);
         }

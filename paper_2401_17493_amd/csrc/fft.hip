@@ -468,25 +468,36 @@ int tile_cols(int N, int nh, int elems) {
     return C;
 }
 
-int row_block(int n3, long long rows) {
-    // rows per block for the x3 passes: RB * n3/2 <= kThreads * 16
+int row_block(int n3, long long rows, int elems) {
+    // rows per block for the x3 passes: RB * n3/2 <= elems
     const int M = n3 / 2;
-    int RB = (kThreads * 16) / M;
+    int RB = elems / M;
     if (RB < 1) RB = 1;
     while (RB > 1 && rows % RB) RB >>= 1;
     return RB;
 }
 
+// double spectra use half-size tiles (same LDS bytes as float tiles) so that
+// several workgroups still fit on a CU
+template <typename C>
+constexpr int tile_elems() { return sizeof(C) == 8 ? 4096 : 2048; }
+
 template <typename C>
 int fwd_x3(const Geo& g, const C* tw, int T, const float* in, C* spec, int ncomp, hipStream_t s) {
     const long long rows = (long long)g.n1 * g.n2;
-    const int RB = row_block(g.n3, rows);
+    const int RB = row_block(g.n3, rows, tile_elems<C>());
     const int logT = ilog2(T);
     const size_t sh = sizeof(C) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
-    CL_TRY(allow_lds(k_r2c_x3<16, C>, sh));
-    hipLaunchKernelGGL((k_r2c_x3<16, C>), grid, dim3(kThreads), sh, s, in, spec, g.l3, RB, g.n,
-                       g.nspec, tw, logT);
+    if (sizeof(C) == 8) {
+        CL_TRY(allow_lds(k_r2c_x3<16, C>, sh));
+        hipLaunchKernelGGL((k_r2c_x3<16, C>), grid, dim3(kThreads), sh, s, in, spec, g.l3, RB,
+                           g.n, g.nspec, tw, logT);
+    } else {
+        CL_TRY(allow_lds(k_r2c_x3<8, C>, sh));
+        hipLaunchKernelGGL((k_r2c_x3<8, C>), grid, dim3(kThreads), sh, s, in, spec, g.l3, RB,
+                           g.n, g.nspec, tw, logT);
+    }
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -494,7 +505,7 @@ int fwd_x3(const Geo& g, const C* tw, int T, const float* in, C* spec, int ncomp
 int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, const float* add,
            int ncomp, hipStream_t s) {
     const long long rows = (long long)g.n1 * g.n2;
-    const int RB = row_block(g.n3, rows);
+    const int RB = row_block(g.n3, rows, 4096);
     const int logT = ilog2(w.tw_n);
     const size_t sh = sizeof(float2) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
@@ -505,26 +516,28 @@ int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, 
     return 0;
 }
 
+template <int DIR, int E, typename C>
+int cols_launch(const Geo& g, const C* tw, int logT, C* spec, int CW, size_t sh, dim3 grid,
+                hipStream_t s) {
+    CL_TRY(allow_lds(k_c2c_cols<DIR, E, C>, sh));
+    hipLaunchKernelGGL((k_c2c_cols<DIR, E, C>), grid, dim3(kThreads), sh, s, spec, g.l2, CW,
+                       (long long)g.nh, (long long)g.n2 * g.nh, g.nh, g.nspec, tw, logT);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
 template <int DIR, typename C>
 int cols_x2(const Geo& g, const C* tw, int T, C* spec, int ncomp, hipStream_t s) {
-    // float tiles hold up to 8192 values (E = 32), double tiles 4096 (E = 16)
-    constexpr int elems = sizeof(C) == 8 ? 8192 : 4096;
+    // float tiles hold up to 8192 values, double tiles 2048
+    constexpr int elems = sizeof(C) == 8 ? 8192 : 2048;
     const int CW = tile_cols(g.n2, g.nh, elems);
     const int logT = ilog2(T);
     const size_t sh = sizeof(C) * ((1 << logT) + (size_t)g.n2 * CW);
     dim3 grid((g.nh + CW - 1) / CW, g.n1, ncomp);
-    const long long stride = g.nh, ystride = (long long)g.n2 * g.nh;
-    if (g.n2 * CW <= 16 * kThreads) {
-        CL_TRY(allow_lds(k_c2c_cols<DIR, 16, C>, sh));
-        hipLaunchKernelGGL((k_c2c_cols<DIR, 16, C>), grid, dim3(kThreads), sh, s, spec, g.l2, CW,
-                           stride, ystride, g.nh, g.nspec, tw, logT);
-    } else {
-        CL_TRY(allow_lds(k_c2c_cols<DIR, 32, C>, sh));
-        hipLaunchKernelGGL((k_c2c_cols<DIR, 32, C>), grid, dim3(kThreads), sh, s, spec, g.l2, CW,
-                           stride, ystride, g.nh, g.nspec, tw, logT);
-    }
-    CL_LAUNCH_CHECK();
-    return 0;
+    const int per = (g.n2 * CW + kThreads - 1) / kThreads;
+    if (per <= 8) return cols_launch<DIR, 8>(g, tw, logT, spec, CW, sh, grid, s);
+    if (per <= 16) return cols_launch<DIR, 16>(g, tw, logT, spec, CW, sh, grid, s);
+    return cols_launch<DIR, 32>(g, tw, logT, spec, CW, sh, grid, s);
 }
 
 template <int MODE>
@@ -550,13 +563,13 @@ int fused_x1(const Geo& g, const SpectralWork& w, const float2* in, float2* out,
 
 int reg_x1(const Geo& g, const SpectralWork& w, const double2* in, float2* out, Mult m,
            hipStream_t s) {
-    const int CW = tile_cols(g.n1, g.nh, 4096);
+    const int CW = tile_cols(g.n1, g.nh, 2048);
     const int logT = ilog2(w.tw_n);
     const size_t sh = (sizeof(double2) + sizeof(float2)) * (1 << logT) +
                       sizeof(double2) * (size_t)g.n1 * CW;
     dim3 grid((g.nh + CW - 1) / CW, g.n2, 3);
-    CL_TRY(allow_lds(k_x1_reg64<16>, sh));
-    hipLaunchKernelGGL(k_x1_reg64<16>, grid, dim3(kThreads), sh, s, in, out, g.l1, CW, g.nh,
+    CL_TRY(allow_lds(k_x1_reg64<8>, sh));
+    hipLaunchKernelGGL(k_x1_reg64<8>, grid, dim3(kThreads), sh, s, in, out, g.l1, CW, g.nh,
                        g.nspec, m, w.tw64, w.tw, logT);
     CL_LAUNCH_CHECK();
     return 0;

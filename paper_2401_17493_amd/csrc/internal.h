@@ -69,25 +69,31 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
                    const float* add = nullptr);
 
 // ------------------------------------------------------ semi-Lagrangian
+// Single-field gathers accept an optional per-brick box table of their
+// departure field (from launch_brick_boxes); NULL computes the boxes inline.
+int brick_table_ints(const Geo& g);
+int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s);
 int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus,
                      double ht, hipStream_t s);
 int launch_interp(const Geo& g, const float* f, int nfield, const float* disp,
-                  float* out, hipStream_t s);
+                  float* out, hipStream_t s, const int* boxes = nullptr);
 int launch_make_A(const Geo& g, const float* divv, const float* dminus, float* A,
-                  double ht, hipStream_t s);
+                  double ht, hipStream_t s, const int* boxes = nullptr);
 int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* lamT,
                          hipStream_t s);
 int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus,
-                        const float* A, float* lam, hipStream_t s);
+                        const float* A, float* lam, hipStream_t s, const int* boxes = nullptr);
 int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt,
                            float* w0, double ht, hipStream_t s);
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const float* gradm_next, const float* vt, float* out,
-                          float coef, float sign, hipStream_t s);
+                          float coef, float sign, hipStream_t s, const int* boxes = nullptr);
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt,
                     const float* add, float* out, hipStream_t s);
-int launch_defgrad_step(const Geo& g, const float* F, const float* G, const float* dplus,
-                        float* Fout, double ht, int first, hipStream_t s);
+// one RK2 step of the deformation-gradient transport from gathered F_y, G_y
+// (Fy NULL: F^0 = I); F may alias Fy
+int launch_defgrad_update(const Geo& g, const float* Fy, const float* Gy, const float* G,
+                          float* F, double ht, hipStream_t s);
 int launch_det(const Geo& g, const float* F, double* det, hipStream_t s);
 
 // --------------------------------------------------------- reductions
@@ -108,6 +114,7 @@ int red_dot(Reducer& r, const float* a, const float* b, long long n, int slot, h
 int red_sumsq_diff(Reducer& r, const float* a, const float* b, long long n, int slot,
                    hipStream_t s);
 int red_absmax(Reducer& r, const float* a, long long n, int slot, hipStream_t s);
+int red_sum(Reducer& r, const float* a, long long n, int slot, hipStream_t s);
 // min, sum, max and count of non-positive values of a float64 array -> slots 0..3
 int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
 int red_fetch(Reducer& r, hipStream_t s);
@@ -121,6 +128,9 @@ int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s);
 int launch_lincomb(const float* x, const float* z, float* y, float b, long long n,
                    hipStream_t s);
 int launch_fill(float* y, float value, long long n, hipStream_t s);
+// als_a = (r_a - mean[a]) + mu als_a, a = 0..2 (vector fields of 3 components of n)
+int launch_als_update(const float* r, float* als, const double mean[3], float mu, long long n,
+                      hipStream_t s);
 int launch_scale_copy(const float* x, float* y, float a, long long n, hipStream_t s);
 int launch_check_finite(const float* x, long long n, int* flag, hipStream_t s);
 

@@ -97,17 +97,33 @@ __device__ __forceinline__ void coords(const G3& g, long long idx, int& i1, int&
 // ------------------------------------------------------------------------
 // LDS-staged single-field gathers (the state, adjoint and incremental steps).
 //
-// A workgroup owns an output brick of up to 8 x 8 x 16 voxels. It reads the
-// brick's displacements, reduces the bounding box of all 4x4x4 stencils,
-// copies that box of the source field into LDS with row-contiguous loads,
-// and interpolates from LDS: 64 LDS reads per voxel instead of 64 scattered
+// A workgroup owns an output brick of 4 x 8 x 16 voxels. The bounding box of
+// all the brick's 4x4x4 stencils comes from a per-brick table computed once
+// per departure field (the departure points are fixed for a velocity and
+// reused by every state, adjoint and incremental step) or, without a table,
+// from a block reduction over the brick's displacements. The box of the
+// source field is copied into LDS with row-contiguous loads and the values
+// are interpolated from LDS: 64 LDS reads per voxel instead of 64 scattered
 // global loads, which otherwise saturate the vector-memory address path long
-// before HBM. A brick whose box exceeds the LDS budget (extreme local
-// deformation) gathers directly from global memory instead. Bricks are
+// before HBM. With the table, the box, displacement and epilogue loads are
+// all in flight together. A brick whose box exceeds the LDS budget (extreme
+// local deformation) gathers directly from global memory instead. Bricks are
 // handed out so that each XCD sweeps a contiguous slab of the grid, keeping
 // the halo rows shared by neighbouring bricks in one L2.
-constexpr int kBoxCap = 12288;     // floats of LDS per workgroup (48 KiB)
-constexpr int kVox = 4;            // voxels per thread (brick <= 1024 voxels)
+#ifndef CLAIRE_GATHER_BOXCAP
+#define CLAIRE_GATHER_BOXCAP 6144
+#endif
+#ifndef CLAIRE_GATHER_VOX
+#define CLAIRE_GATHER_VOX 2
+#endif
+constexpr int kBoxCap = CLAIRE_GATHER_BOXCAP;  // floats of LDS per workgroup
+constexpr int kVox = CLAIRE_GATHER_VOX;        // voxels per thread: brick = 256 kVox voxels
+constexpr int kLogVox = kVox == 1 ? 0 : (kVox == 2 ? 1 : 2);
+#ifndef CLAIRE_GATHER_WAVES
+#define CLAIRE_GATHER_WAVES 4
+#endif
+// waves per SIMD the gather kernels are compiled for (bounds their VGPRs)
+constexpr int kGatherWaves = CLAIRE_GATHER_WAVES;
 constexpr int kBatch = 8;          // independent loads in flight per thread while staging
 
 struct Brick {
@@ -116,9 +132,10 @@ struct Brick {
     int nbricks;
 };
 
+// brick 2^(1 + log2 kVox) x 8 x 16 (4 x 8 x 16 for kVox = 2), clipped to the grid
 Brick make_brick(const Geo& g) {
     Brick b;
-    b.lb1 = g.l1 < 3 ? g.l1 : 3;
+    b.lb1 = g.l1 < 1 + kLogVox ? g.l1 : 1 + kLogVox;
     b.lb2 = g.l2 < 3 ? g.l2 : 3;
     b.lb3 = g.l3 < 4 ? g.l3 : 4;
     b.lnb2 = g.l2 - b.lb2;
@@ -179,48 +196,45 @@ struct EpiMakeA {        // out = 1 + (h_t/2)(D(y-) + D + h_t D(y-) D)
     }
 };
 
-template <class Epi>
-__global__ __launch_bounds__(kThreads) void k_gather_lds(const float* __restrict__ src,
-                                                         const float* __restrict__ d, Epi epi,
-                                                         G3 g, Brick br, long long n) {
-    __shared__ float box[kBoxCap];
-    __shared__ int red[kThreads / 64][6];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+// Brick owned by this workgroup (XCD-contiguous order) and its voxels.
+struct BrickPos {
+    int o1, o2, o3;    // first voxel
+    int bvol;          // voxels in the brick
+    int id;            // brick index (x3 fastest), independent of the launch order
+};
+
+__device__ __forceinline__ BrickPos brick_pos(const Brick& br) {
     int bid = blockIdx.x;
     if ((br.nbricks & 7) == 0) bid = (bid & 7) * (br.nbricks >> 3) + (bid >> 3);
-    const int bb3 = bid & ((1 << br.lnb3) - 1);
-    const int bb2 = (bid >> br.lnb3) & ((1 << br.lnb2) - 1);
-    const int bb1 = bid >> (br.lnb3 + br.lnb2);
-    const int bvol = 1 << (br.lb1 + br.lb2 + br.lb3);
+    BrickPos p;
+    p.o3 = (bid & ((1 << br.lnb3) - 1)) << br.lb3;
+    p.o2 = ((bid >> br.lnb3) & ((1 << br.lnb2) - 1)) << br.lb2;
+    p.o1 = (bid >> (br.lnb3 + br.lnb2)) << br.lb1;
+    p.bvol = 1 << (br.lb1 + br.lb2 + br.lb3);
+    p.id = bid;
+    return p;
+}
 
-    float dd[kVox][3];
-    int q[kVox][3];
-    long long gi[kVox];
-    typename Epi::Pre pre[kVox];
-    int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
-    int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
-#pragma unroll
-    for (int k = 0; k < kVox; ++k) {
-        const int v = tid + k * kThreads;
-        gi[k] = -1;
-        if (v < bvol) {
-            const int i3 = (bb3 << br.lb3) + (v & ((1 << br.lb3) - 1));
-            const int i2 = (bb2 << br.lb2) + ((v >> br.lb3) & ((1 << br.lb2) - 1));
-            const int i1 = (bb1 << br.lb1) + (v >> (br.lb3 + br.lb2));
-            const long long idx = ((long long)i1 << g.s1) + ((long long)i2 << g.l3) + i3;
-            gi[k] = idx;
-            dd[k][0] = d[idx];
-            dd[k][1] = d[n + idx];
-            dd[k][2] = d[2 * n + idx];
-            pre[k] = epi.load(idx);
-            q[k][0] = i1 + (int)floorf(dd[k][0]) - 1;
-            q[k][1] = i2 + (int)floorf(dd[k][1]) - 1;
-            q[k][2] = i3 + (int)floorf(dd[k][2]) - 1;
-            mn1 = min(mn1, q[k][0]); mx1 = max(mx1, q[k][0]);
-            mn2 = min(mn2, q[k][1]); mx2 = max(mx2, q[k][1]);
-            mn3 = min(mn3, q[k][2]); mx3 = max(mx3, q[k][2]);
-        }
-    }
+// k-th voxel of this thread: grid coordinates and linear index (false if none)
+__device__ __forceinline__ bool brick_voxel(const G3& g, const Brick& br, const BrickPos& p,
+                                            int k, int& i1, int& i2, int& i3, long long& idx) {
+    const int v = threadIdx.x + k * kThreads;
+    if (v >= p.bvol) return false;
+    i3 = p.o3 + (v & ((1 << br.lb3) - 1));
+    i2 = p.o2 + ((v >> br.lb3) & ((1 << br.lb2) - 1));
+    i1 = p.o1 + (v >> (br.lb3 + br.lb2));
+    idx = ((long long)i1 << g.s1) + ((long long)i2 << g.l3) + i3;
+    return true;
+}
+
+// Box covering all stencil origins q (already reduced per thread into
+// mn/mx): block reduction through `red`, result in lo[3], e[3]. Contains a
+// barrier; callers must not be reading `red` from an earlier call.
+struct Box { int lo1, lo2, lo3, e1, e2, e3; long long vol; };
+
+__device__ __forceinline__ Box reduce_box(int mn1, int mn2, int mn3, int mx1, int mx2, int mx3,
+                                          int (*red)[6]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     mn1 = wave_min(mn1); mn2 = wave_min(mn2); mn3 = wave_min(mn3);
     mx1 = wave_max(mx1); mx2 = wave_max(mx2); mx3 = wave_max(mx3);
     if (lane == 0) {
@@ -235,107 +249,262 @@ __global__ __launch_bounds__(kThreads) void k_gather_lds(const float* __restrict
         lo1 = min(lo1, red[w][0]); lo2 = min(lo2, red[w][1]); lo3 = min(lo3, red[w][2]);
         hi1 = max(hi1, red[w][3]); hi2 = max(hi2, red[w][4]); hi3 = max(hi3, red[w][5]);
     }
-    const int e1 = hi1 - lo1 + 4, e2 = hi2 - lo2 + 4, e3 = hi3 - lo3 + 4;
-    const long long vol = (long long)e1 * e2 * e3;
+    Box b;
+    b.lo1 = lo1; b.lo2 = lo2; b.lo3 = lo3;
+    b.e1 = hi1 - lo1 + 4; b.e2 = hi2 - lo2 + 4; b.e3 = hi3 - lo3 + 4;
+    b.vol = (long long)b.e1 * b.e2 * b.e3;
+    return b;
+}
 
-    if (vol <= kBoxCap) {
-        // stage the source box [e1][e2][e3] (rows along x3 are contiguous):
-        // batches of independent loads, then the LDS stores
-        const int nvol = (int)vol;
-        for (int e0 = 0; e0 < nvol; e0 += kThreads * kBatch) {
-            float tmp[kBatch];
+// a / b for 0 <= a < 2^24, 0 < b, with inv_b = 1/b: the float quotient is off
+// by at most one, corrected through the remainder r.
+__device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
+    int q = (int)((float)a * inv_b);
+    r = a - q * b;
+    if (r < 0) { --q; r += b; } else if (r >= b) { ++q; r -= b; }
+    return q;
+}
+
+// Copy the box [e1][e2][e3] of field `src` into LDS (rows along x3 are
+// contiguous): batches of independent loads, then the LDS stores.
+__device__ __forceinline__ void stage_box(float* box, const float* __restrict__ src, const G3& g,
+                                          const Box& b) {
+    const int tid = threadIdx.x;
+    const int nvol = (int)b.vol;
+    const float inv3 = 1.0f / (float)b.e3, inv2 = 1.0f / (float)b.e2;
+    for (int e0 = 0; e0 < nvol; e0 += kThreads * kBatch) {
+        float tmp[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int e = e0 + u * kThreads + tid;
-                if (e < nvol) {
-                    const int row = e / e3, a3 = e - row * e3;
-                    const int a1 = row / e2, a2 = row - a1 * e2;
-                    tmp[u] = src[((long long)((lo1 + a1) & g.m1) << g.s1) +
-                                 ((long long)((lo2 + a2) & g.m2) << g.l3) + ((lo3 + a3) & g.m3)];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int e = e0 + u * kThreads + tid;
-                if (e < nvol) box[e] = tmp[u];
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            if (e < nvol) {
+                int a3, a2;
+                const int row = quot(e, b.e3, inv3, a3);
+                const int a1 = quot(row, b.e2, inv2, a2);
+                tmp[u] = src[((long long)((b.lo1 + a1) & g.m1) << g.s1) +
+                             ((long long)((b.lo2 + a2) & g.m2) << g.l3) + ((b.lo3 + a3) & g.m3)];
             }
         }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads + tid;
+            if (e < nvol) box[e] = tmp[u];
+        }
+    }
+}
+
+// Tricubic value from the staged box at stencil origin q (grid units) with
+// fractional offsets given by the displacement d.
+__device__ __forceinline__ float interp_box(const float* box, const Box& b, const int q[3],
+                                            const float d[3]) {
+    float w1[4], w2[4], w3[4];
+    cubic_basis(d[0] - floorf(d[0]), w1);
+    cubic_basis(d[1] - floorf(d[1]), w2);
+    cubic_basis(d[2] - floorf(d[2]), w3);
+    const int r1 = q[0] - b.lo1, r2 = q[1] - b.lo2, r3 = q[2] - b.lo3;
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float* p = box + ((r1 + a) * b.e2 + (r2 + c)) * b.e3 + r3;
+            float t = w3[0] * p[0];
+            t = fmaf(w3[1], p[1], t);
+            t = fmaf(w3[2], p[2], t);
+            t = fmaf(w3[3], p[3], t);
+            acc = fmaf(w1[a] * w2[c], t, acc);
+        }
+    }
+    return acc;
+}
+
+// Tricubic value by direct global gathers (bricks whose box does not fit).
+__device__ __forceinline__ float interp_global(const float* __restrict__ src, const G3& g,
+                                               long long n, int i1, int i2, int i3,
+                                               const float d[3]) {
+    Stencil st;
+    make_stencil(g, i1, i2, i3, d[0], d[1], d[2], st);
+    float u;
+    gather<1>(src, n, st, &u);
+    return u;
+}
+
+// Per-brick stencil bounding boxes of a departure field: 6 ints per brick
+// (lo1, lo2, lo3, e1, e2, e3), indexed by BrickPos::id.
+__global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restrict__ d,
+                                                          int* __restrict__ table, G3 g,
+                                                          Brick br, long long n) {
+    __shared__ int red[kThreads / 64][6];
+    const BrickPos bp = brick_pos(br);
+    int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
+    int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
+#pragma unroll
+    for (int k = 0; k < kVox; ++k) {
+        int i1, i2, i3;
+        long long idx;
+        if (brick_voxel(g, br, bp, k, i1, i2, i3, idx)) {
+            const int q1 = i1 + (int)floorf(d[idx]) - 1;
+            const int q2 = i2 + (int)floorf(d[n + idx]) - 1;
+            const int q3 = i3 + (int)floorf(d[2 * n + idx]) - 1;
+            mn1 = min(mn1, q1); mx1 = max(mx1, q1);
+            mn2 = min(mn2, q2); mx2 = max(mx2, q2);
+            mn3 = min(mn3, q3); mx3 = max(mx3, q3);
+        }
+    }
+    const Box b = reduce_box(mn1, mn2, mn3, mx1, mx2, mx3, red);
+    if (threadIdx.x == 0) {
+        int* t = table + 6 * bp.id;
+        t[0] = b.lo1; t[1] = b.lo2; t[2] = b.lo3;
+        t[3] = b.e1; t[4] = b.e2; t[5] = b.e3;
+    }
+}
+
+// Single-field gather u = src(x + d(x)) with epilogue; `table` holds the
+// per-brick boxes of d (NULL: reduce them here).
+template <class Epi>
+__global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
+    const float* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
+    Epi epi, G3 g, Brick br, long long n) {
+    __shared__ float box[kBoxCap];
+    __shared__ int red[kThreads / 64][6];
+    const BrickPos bp = brick_pos(br);
+    float dd[kVox][3];
+    int q[kVox][3];
+    int ii[kVox][3];
+    long long gi[kVox];
+    typename Epi::Pre pre[kVox];
+    int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
+    int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
+#pragma unroll
+    for (int k = 0; k < kVox; ++k) {
+        gi[k] = -1;
+        long long idx;
+        if (brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], idx)) {
+            gi[k] = idx;
+            dd[k][0] = d[idx];
+            dd[k][1] = d[n + idx];
+            dd[k][2] = d[2 * n + idx];
+            pre[k] = epi.load(idx);
+        }
+    }
+    Box b;
+    if (table) {
+        const int* t = table + 6 * bp.id;
+        b.lo1 = t[0]; b.lo2 = t[1]; b.lo3 = t[2];
+        b.e1 = t[3]; b.e2 = t[4]; b.e3 = t[5];
+        b.vol = (long long)b.e1 * b.e2 * b.e3;
+        if (b.vol <= kBoxCap) stage_box(box, src, g, b);
+    }
+#pragma unroll
+    for (int k = 0; k < kVox; ++k) {
+        if (gi[k] < 0) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[k][a] = ii[k][a] + (int)floorf(dd[k][a]) - 1;
+        mn1 = min(mn1, q[k][0]); mx1 = max(mx1, q[k][0]);
+        mn2 = min(mn2, q[k][1]); mx2 = max(mx2, q[k][1]);
+        mn3 = min(mn3, q[k][2]); mx3 = max(mx3, q[k][2]);
+    }
+    if (!table) {
+        b = reduce_box(mn1, mn2, mn3, mx1, mx2, mx3, red);
+        if (b.vol <= kBoxCap) stage_box(box, src, g, b);
+    }
+    if (b.vol <= kBoxCap) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kVox; ++k) {
-            if (gi[k] < 0) continue;
-            float w1[4], w2[4], w3[4];
-            cubic_basis(dd[k][0] - floorf(dd[k][0]), w1);
-            cubic_basis(dd[k][1] - floorf(dd[k][1]), w2);
-            cubic_basis(dd[k][2] - floorf(dd[k][2]), w3);
-            const int r1 = q[k][0] - lo1, r2 = q[k][1] - lo2, r3 = q[k][2] - lo3;
-            float acc = 0.f;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const float* p = box + ((r1 + a) * e2 + (r2 + b)) * e3 + r3;
-                    float t = w3[0] * p[0];
-                    t = fmaf(w3[1], p[1], t);
-                    t = fmaf(w3[2], p[2], t);
-                    t = fmaf(w3[3], p[3], t);
-                    acc = fmaf(w1[a] * w2[b], t, acc);
-                }
-            }
-            epi.store(gi[k], acc, pre[k]);
-        }
+        for (int k = 0; k < kVox; ++k)
+            if (gi[k] >= 0) epi.store(gi[k], interp_box(box, b, q[k], dd[k]), pre[k]);
     } else {
 #pragma unroll
+        for (int k = 0; k < kVox; ++k)
+            if (gi[k] >= 0)
+                epi.store(gi[k], interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]),
+                          pre[k]);
+    }
+}
+
+// RK2 backtrace for +v and -v (Section 2.5.2), LDS-staged:
+//   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
+// c_a = h_t / h_a converts velocity to voxels per step. For each direction
+// the three components of v are staged through the brick's box in turn.
+__global__ __launch_bounds__(kThreads, kGatherWaves) void k_backtrace_lds(const float* __restrict__ v,
+                                                            float* __restrict__ dp,
+                                                            float* __restrict__ dm, G3 g,
+                                                            Brick br, long long n, float c1,
+                                                            float c2, float c3) {
+    __shared__ float box[kBoxCap];
+    __shared__ int red[kThreads / 64][6];
+    const BrickPos bp = brick_pos(br);
+    const float c[3] = {c1, c2, c3};
+    float vx[kVox][3];
+    int ii[kVox][3];
+    long long gi[kVox];
+#pragma unroll
+    for (int k = 0; k < kVox; ++k) {
+        gi[k] = -1;
+        long long idx;
+        if (brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], idx)) {
+            gi[k] = idx;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) vx[k][a] = v[a * n + idx];
+        }
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+        const float sg = dir == 0 ? -1.f : 1.f;   // y~ = x + sg h_t v(x)
+        float dd[kVox][3];
+        int q[kVox][3];
+        int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
+        int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
+#pragma unroll
         for (int k = 0; k < kVox; ++k) {
             if (gi[k] < 0) continue;
-            const long long idx = gi[k];
-            int i1, i2, i3;
-            coords(g, idx, i1, i2, i3);
-            Stencil st;
-            make_stencil(g, i1, i2, i3, dd[k][0], dd[k][1], dd[k][2], st);
-            float u;
-            gather<1>(src, n, st, &u);
-            epi.store(idx, u, pre[k]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dd[k][a] = sg * c[a] * vx[k][a];
+                q[k][a] = ii[k][a] + (int)floorf(dd[k][a]) - 1;
+            }
+            mn1 = min(mn1, q[k][0]); mx1 = max(mx1, q[k][0]);
+            mn2 = min(mn2, q[k][1]); mx2 = max(mx2, q[k][1]);
+            mn3 = min(mn3, q[k][2]); mx3 = max(mx3, q[k][2]);
+        }
+        __syncthreads();   // `red` and `box` of the previous direction are free
+        const Box b = reduce_box(mn1, mn2, mn3, mx1, mx2, mx3, red);
+        const bool fits = b.vol <= kBoxCap;
+        float u[kVox][3];
+        for (int f = 0; f < 3; ++f) {
+            const float* src = v + (long long)f * n;
+            if (fits) {
+                if (f > 0) __syncthreads();   // previous component's reads are done
+                stage_box(box, src, g, b);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kVox; ++k)
+                    if (gi[k] >= 0) u[k][f] = interp_box(box, b, q[k], dd[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kVox; ++k)
+                    if (gi[k] >= 0)
+                        u[k][f] = interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]);
+            }
+        }
+        float* out = dir == 0 ? dp : dm;
+#pragma unroll
+        for (int k = 0; k < kVox; ++k) {
+            if (gi[k] < 0) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                out[a * n + gi[k]] = sg * 0.5f * c[a] * (vx[k][a] + u[k][a]);
         }
     }
 }
 
 template <class Epi>
-int launch_gather_lds(const Geo& g, const float* src, const float* disp, const Epi& epi,
-                      hipStream_t s) {
+int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
+                      const Epi& epi, hipStream_t s) {
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL(k_gather_lds<Epi>, dim3(br.nbricks), dim3(kThreads), 0, s, src, disp, epi,
-                       make_g3(g), br, g.n);
+    hipLaunchKernelGGL(k_gather_lds<Epi>, dim3(br.nbricks), dim3(kThreads), 0, s, src, disp, table,
+                       epi, make_g3(g), br, g.n);
     CL_LAUNCH_CHECK();
     return 0;
-}
-
-// RK2 backtrace for +v and -v (Section 2.5.2):
-//   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
-// c_a = h_t / h_a converts velocity to voxels per step.
-__global__ __launch_bounds__(kThreads) void k_backtrace(const float* __restrict__ v,
-                                                        float* __restrict__ dp,
-                                                        float* __restrict__ dm, G3 g, long long n,
-                                                        float c1, float c2, float c3) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    int i1, i2, i3;
-    coords(g, idx, i1, i2, i3);
-    const float v1 = v[idx], v2 = v[n + idx], v3 = v[2 * n + idx];
-    Stencil st;
-    float vy[3];
-    // forward characteristics (+v)
-    make_stencil(g, i1, i2, i3, -c1 * v1, -c2 * v2, -c3 * v3, st);
-    gather<3>(v, n, st, vy);
-    dp[idx] = -0.5f * c1 * (v1 + vy[0]);
-    dp[n + idx] = -0.5f * c2 * (v2 + vy[1]);
-    dp[2 * n + idx] = -0.5f * c3 * (v3 + vy[2]);
-    // backward characteristics (-v): y~ = x + h_t v(x), y = x + (h_t/2)(v(x) + v(y~))
-    make_stencil(g, i1, i2, i3, c1 * v1, c2 * v2, c3 * v3, st);
-    gather<3>(v, n, st, vy);
-    dm[idx] = 0.5f * c1 * (v1 + vy[0]);
-    dm[n + idx] = 0.5f * c2 * (v2 + vy[1]);
-    dm[2 * n + idx] = 0.5f * c3 * (v3 + vy[2]);
 }
 
 // out[k](x) = f[k](x + d(x)), k < nf (nf <= 4 per launch chunk)
@@ -400,50 +569,43 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__
     out[2 * n + idx] = acc2;
 }
 
-// Deformation gradient, eq. (e:def-grad): D F/Dt = (grad v) F along +v,
-// RK2 along the characteristics: F_y = F^j(y+), f0 = G(y+) F_y,
-// F~ = F_y + h_t f0, f1 = G(x) F~, F^{j+1} = F_y + (h_t/2)(f0 + f1).
-// F, G: [9][n] row-major 3x3 (G_ab = d_b v_a). first: F^0 = I (no gather).
-__global__ __launch_bounds__(kThreads) void k_defgrad(const float* __restrict__ F,
-                                                      const float* __restrict__ G,
-                                                      const float* __restrict__ dp,
-                                                      float* __restrict__ Fo, G3 g, long long n,
-                                                      float ht, int first) {
+// Deformation gradient, eq. (e:def-grad): D F/Dt = (grad v) F along +v, one
+// RK2 step along the characteristics given the gathered values
+// F_y = F^j(y+) and G_y = G(y+) (G_ab = d_b v_a, fields row-major [9][n]):
+//   f0 = G_y F_y, F~ = F_y + h_t f0, f1 = G(x) F~, F^{j+1} = F_y + (h_t/2)(f0 + f1).
+// Fy == NULL means F^0 = I (nothing to gather). F may alias Fy.
+__global__ __launch_bounds__(kThreads) void k_defgrad_update(const float* __restrict__ Fy,
+                                                             const float* __restrict__ Gy,
+                                                             const float* __restrict__ G,
+                                                             float* F, long long n, float ht) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= n) return;
-    int i1, i2, i3;
-    coords(g, idx, i1, i2, i3);
-    Stencil st;
-    make_stencil(g, i1, i2, i3, dp[idx], dp[n + idx], dp[2 * n + idx], st);
-    float Gy[9], Fy[9], Gx[9];
-    gather<9>(G, n, st, Gy);
-    if (first) {
+    float gy[9], fy[9], gx[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Fy[q] = (q % 4 == 0) ? 1.f : 0.f;
-    } else {
-        gather<9>(F, n, st, Fy);
+    for (int q = 0; q < 9; ++q) {
+        gy[q] = Gy[q * n + idx];
+        gx[q] = G[q * n + idx];
+        fy[q] = Fy ? Fy[q * n + idx] : ((q % 4 == 0) ? 1.f : 0.f);
     }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Gx[q] = G[q * n + idx];
-    float f0[9], Ft[9];
+    float f0[9], ft[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float s = 0.f;
+            float acc = 0.f;
 #pragma unroll
-            for (int b = 0; b < 3; ++b) s = fmaf(Gy[3 * a + b], Fy[3 * b + c], s);
-            f0[3 * a + c] = s;
-            Ft[3 * a + c] = Fy[3 * a + c] + ht * s;
+            for (int b = 0; b < 3; ++b) acc = fmaf(gy[3 * a + b], fy[3 * b + c], acc);
+            f0[3 * a + c] = acc;
+            ft[3 * a + c] = fy[3 * a + c] + ht * acc;
         }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float s = 0.f;
+            float acc = 0.f;
 #pragma unroll
-            for (int b = 0; b < 3; ++b) s = fmaf(Gx[3 * a + b], Ft[3 * b + c], s);
-            Fo[(3 * a + c) * n + idx] = Fy[3 * a + c] + 0.5f * ht * (f0[3 * a + c] + s);
+            for (int b = 0; b < 3; ++b) acc = fmaf(gx[3 * a + b], ft[3 * b + c], acc);
+            F[(3 * a + c) * n + idx] = fy[3 * a + c] + 0.5f * ht * (f0[3 * a + c] + acc);
         }
 }
 
@@ -468,15 +630,16 @@ int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus, 
     const float c1 = (float)(ht * g.n1 / (2.0 * M_PI));
     const float c2 = (float)(ht * g.n2 / (2.0 * M_PI));
     const float c3 = (float)(ht * g.n3 / (2.0 * M_PI));
-    hipLaunchKernelGGL(k_backtrace, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, v, dplus, dminus,
-                       make_g3(g), g.n, c1, c2, c3);
+    const Brick br = make_brick(g);
+    hipLaunchKernelGGL(k_backtrace_lds, dim3(br.nbricks), dim3(kThreads), 0, s, v, dplus, dminus,
+                       make_g3(g), br, g.n, c1, c2, c3);
     CL_LAUNCH_CHECK();
     return 0;
 }
 
 int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, float* out,
-                  hipStream_t s) {
-    if (nfield == 1) return launch_gather_lds(g, f, disp, EpiStore{out}, s);
+                  hipStream_t s, const int* boxes) {
+    if (nfield == 1) return launch_gather_lds(g, f, disp, boxes, EpiStore{out}, s);
     const G3 g3 = make_g3(g);
     int k = 0;
     while (k < nfield) {
@@ -496,8 +659,8 @@ int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, f
 }
 
 int launch_make_A(const Geo& g, const float* divv, const float* dminus, float* A, double ht,
-                  hipStream_t s) {
-    return launch_gather_lds(g, divv, dminus, EpiMakeA{divv, A, (float)ht}, s);
+                  hipStream_t s, const int* boxes) {
+    return launch_gather_lds(g, divv, dminus, boxes, EpiMakeA{divv, A, (float)ht}, s);
 }
 
 int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* lamT,
@@ -509,8 +672,8 @@ int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* 
 }
 
 int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus, const float* A,
-                        float* lam, hipStream_t s) {
-    return launch_gather_lds(g, lam_next, dminus, EpiScale{A, lam}, s);
+                        float* lam, hipStream_t s, const int* boxes) {
+    return launch_gather_lds(g, lam_next, dminus, boxes, EpiScale{A, lam}, s);
 }
 
 int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, float* w0,
@@ -523,8 +686,9 @@ int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, f
 
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const float* gradm_next, const float* vt, float* out, float coef,
-                          float sign, hipStream_t s) {
-    return launch_gather_lds(g, w_prev, dplus, EpiIncState{gradm_next, vt, out, g.n, coef, sign}, s);
+                          float sign, hipStream_t s, const int* boxes) {
+    return launch_gather_lds(g, w_prev, dplus, boxes,
+                             EpiIncState{gradm_next, vt, out, g.n, coef, sign}, s);
 }
 
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, const float* add,
@@ -535,10 +699,20 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
     return 0;
 }
 
-int launch_defgrad_step(const Geo& g, const float* F, const float* G, const float* dplus,
-                        float* Fout, double ht, int first, hipStream_t s) {
-    hipLaunchKernelGGL(k_defgrad, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, F, G, dplus, Fout,
-                       make_g3(g), g.n, (float)ht, first);
+int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
+
+int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s) {
+    const Brick br = make_brick(g);
+    hipLaunchKernelGGL(k_brick_boxes, dim3(br.nbricks), dim3(kThreads), 0, s, disp, table,
+                       make_g3(g), br, g.n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_defgrad_update(const Geo& g, const float* Fy, const float* Gy, const float* G,
+                          float* F, double ht, hipStream_t s) {
+    hipLaunchKernelGGL(k_defgrad_update, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, Fy, Gy, G,
+                       F, g.n, (float)ht);
     CL_LAUNCH_CHECK();
     return 0;
 }
