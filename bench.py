@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--roofline-kernel", default="inc_state_step",
                     choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set up at v = v*/2 and launch only the roofline kernel and the copy "
+                         "kernel (for hardware-counter runs); prints their timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this engine has no multi-GPU path "
@@ -136,6 +139,16 @@ def main():
 
     ctx = C.Context(n, nt, alpha, w["reg_order"])
     ctx.set_images(m0, m1)
+    kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
+           "assemble": C.KERNEL_ASSEMBLE, "copy": C.KERNEL_COPY}[args.roofline_kernel]
+    if args.kernels_only:
+        ctx.set_velocity((0.5 * vstar).contiguous())
+        ms_k = ctx.time_kernel(kid, reps=5)
+        ms_c = ctx.time_kernel(C.KERNEL_COPY, reps=5)
+        print(json.dumps({"kernel": args.roofline_kernel, "ms_per_launch": ms_k,
+                          "copy_ms_per_launch": ms_c, "voxels": n[0] * n[1] * n[2]}))
+        ctx.close()
+        return
     for _ in range(args.warmup):
         ctx.solve(**opts)
     torch.cuda.synchronize()
@@ -165,8 +178,6 @@ def main():
     ms_matvec = e0.elapsed_time(e1) / args.matvecs
 
     # roofline of the dominant kernel: algorithmic bytes / live launch duration
-    kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
-           "assemble": C.KERNEL_ASSEMBLE, "copy": C.KERNEL_COPY}[args.roofline_kernel]
     ms_kernel = ctx.time_kernel(kid, reps=50)
     voxels = n[0] * n[1] * n[2]
     alg_bytes = kernel_bytes_per_voxel(args.roofline_kernel, nt) * voxels
