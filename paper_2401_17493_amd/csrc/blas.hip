@@ -91,6 +91,41 @@ __global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __rest
     }
 }
 
+// v~ += kappa s; r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0), with
+// per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
+__global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restrict__ sd,
+                                                         const float4* __restrict__ hs,
+                                                         float4* __restrict__ vt,
+                                                         float4* __restrict__ r, float kappa,
+                                                         long long n4, double* __restrict__ partial) {
+    __shared__ double sh[kThreads / kWave];
+    double mx = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
+        const float4 a = sd[i], h = hs[i];
+        float4 v = vt[i], q = r[i];
+        v.x = fmaf(kappa, a.x, v.x); v.y = fmaf(kappa, a.y, v.y);
+        v.z = fmaf(kappa, a.z, v.z); v.w = fmaf(kappa, a.w, v.w);
+        q.x = fmaf(-kappa, h.x, q.x); q.y = fmaf(-kappa, h.y, q.y);
+        q.z = fmaf(-kappa, h.z, q.z); q.w = fmaf(-kappa, h.w, q.w);
+        vt[i] = v;
+        r[i] = q;
+        mx = fmax(mx, (double)fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+        const double sum = (double)q.x + (double)q.y + (double)q.z + (double)q.w;
+        if (i < n4) s0 += sum; else if (i < 2 * n4) s1 += sum; else s2 += sum;
+    }
+    mx = block_reduce<OP_MAX>(mx, sh);
+    s0 = block_reduce<OP_SUM>(s0, sh);
+    s1 = block_reduce<OP_SUM>(s1, sh);
+    s2 = block_reduce<OP_SUM>(s2, sh);
+    if (threadIdx.x == 0) {
+        partial[4 * blockIdx.x + 0] = mx;
+        partial[4 * blockIdx.x + 1] = s0;
+        partial[4 * blockIdx.x + 2] = s1;
+        partial[4 * blockIdx.x + 3] = s2;
+    }
+}
+
 // fold nb partials (with element stride `stride`, offset `off`) into result[slot]
 template <int OP>
 __global__ __launch_bounds__(kThreads) void k_fold(const double* __restrict__ partial, int nb,
@@ -175,8 +210,10 @@ int red_generic(Reducer& r, const float* a, const float* b, long long n, int slo
 
 }  // namespace
 
-int reducer_init(Reducer& r) {
-    CL_HIP(hipMalloc(&r.partial, sizeof(double) * kRedBlocks * 4));
+int reducer_init(Reducer& r, long long n) {
+    long long np = (long long)kRedBlocks * 4;
+    if ((n + kThreads - 1) / kThreads > np) np = (n + kThreads - 1) / kThreads;
+    CL_HIP(hipMalloc(&r.partial, sizeof(double) * np));
     CL_HIP(hipMalloc(&r.result, sizeof(double) * 8));
     CL_HIP(hipHostMalloc(&r.host, sizeof(double) * 8, hipHostMallocDefault));
     return 0;
@@ -214,6 +251,31 @@ int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 1, r.result, 1);
     hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 2, r.result, 2);
     hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 3, r.result, 3);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, nb, stride, off,
+                       r.result, slot);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
+               float kappa, long long n, int smax, int ssum, hipStream_t st) {
+    const long long n4 = n / 4;
+    unsigned nb = red_blocks(3 * n4);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kThreads), 0, st,
+                       reinterpret_cast<const float4*>(s_dir), reinterpret_cast<const float4*>(hs),
+                       reinterpret_cast<float4*>(vt), reinterpret_cast<float4*>(r), kappa, n4,
+                       red.partial);
+    CL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, st, red.partial, (int)nb, 4, 0,
+                       red.result, smax);
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, st, red.partial, (int)nb, 4,
+                           1 + a, red.result, ssum + a);
     CL_LAUNCH_CHECK();
     return 0;
 }

@@ -149,7 +149,7 @@ int ctx_alloc(claire_ctx* c) {
     CL_TRY(dalloc(&c->box_p, brick_table_ints(c->g)));
     CL_TRY(dalloc(&c->box_m, brick_table_ints(c->g)));
     CL_TRY(spectral_init(c->sw, c->g));
-    CL_TRY(reducer_init(c->red));
+    CL_TRY(reducer_init(c->red, c->g.n));
     return 0;
 }
 
@@ -230,8 +230,10 @@ int run_setup(claire_ctx* c) {
 
 // Gauss--Newton Hessian matvec (eqs. e:matvec, e:incstate, e:incadj).
 // reg_part: alpha L vt when the caller already has it (PCG), else NULL and
-// it is computed here by FFT.
-int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr) {
+// it is computed here by FFT. dot_slot >= 0: also <vt, out> into that
+// reduction slot.
+int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
+               int dot_slot = -1) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -262,7 +264,10 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
         CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
         reg_part = c->tmp3;
     }
-    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s));
+    if (dot_slot >= 0)
+        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot));
+    else
+        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s));
     return 0;
 }
 
@@ -325,9 +330,8 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     res = PcgResult();
     bool converged = false;
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, c->als));
+        CL_TRY(run_matvec(c, c->sd, c->hs, c->als, 0));   // also <s, Hs> -> slot 0
         ++res.its;
-        CL_TRY(red_dot(c->red, c->sd, c->hs, n3, 0, s));
         CL_TRY(red_fetch(c->red, s));
         const double shs = c->red.host[0];
         if (!(shs > 0.0) || !std::isfinite(shs)) {
@@ -337,14 +341,13 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
             return CLAIRE_ENONFINITE;
         }
         const double kappa = rz / shs;
-        CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
-        CL_TRY(launch_axpy(c->hs, c->r, (float)(-kappa), n3, s));
+        // v~ += kappa s, r -= kappa Hs, with max|r| -> slot 1 and the residual's
+        // component sums -> slots 3..5
+        CL_TRY(pcg_update(c->red, c->sd, c->hs, c->vt, c->r, (float)kappa, n, 1, 3, s));
         if (res.its == limit) break;
-        // preconditioned residual, stopping norm and residual means in one round trip
+        // preconditioned residual and <z, r>: one host round trip with the above
         CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
-        CL_TRY(red_absmax(c->red, c->r, n3, 1, s));
         CL_TRY(red_dot(c->red, c->z, c->r, n3, 2, s));
-        for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
         CL_TRY(red_fetch(c->red, s));
         if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
         const double rz_new = c->red.host[2];

@@ -20,6 +20,8 @@ struct Geo {
 
 Geo make_geo(const int nx[3]);
 
+struct Reducer;
+
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
@@ -88,8 +90,11 @@ int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt,
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const float* gradm_next, const float* vt, float* out,
                           float coef, float sign, hipStream_t s, const int* boxes = nullptr);
+// out = add + h_t sum_j c_j lam^j grad m^j; with dot_with (nullable), also
+// <dot_with, out> summed into red.result[slot]
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt,
-                    const float* add, float* out, hipStream_t s);
+                    const float* add, float* out, hipStream_t s,
+                    const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
 // one RK2 step of the deformation-gradient transport from gathered F_y, G_y
 // (Fy NULL: F^0 = I); F may alias Fy
 int launch_defgrad_update(const Geo& g, const float* Fy, const float* Gy, const float* G,
@@ -99,13 +104,24 @@ int launch_det(const Geo& g, const float* F, double* det, hipStream_t s);
 // --------------------------------------------------------- reductions
 // Device partial buffer + pinned host landing zone for float64 scalars.
 struct Reducer {
-    double* partial = nullptr;   // [kBlocks * 4]
+    double* partial = nullptr;   // [max(4 kRedBlocks, one per 256 voxels)]
     double* result = nullptr;    // [8] device
     double* host = nullptr;      // [8] pinned host
 };
 constexpr int kRedBlocks = 1024;
 
-int reducer_init(Reducer& r);
+// Sum of v over a 256-thread block (sh: 4 doubles of LDS); every thread
+// receives the total.
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+int reducer_init(Reducer& r, long long n);
 void reducer_free(Reducer& r);
 
 // Enqueue reductions; results land in r.result[slot]. fetch() copies
@@ -118,6 +134,13 @@ int red_sum(Reducer& r, const float* a, long long n, int slot, hipStream_t s);
 // min, sum, max and count of non-positive values of a float64 array -> slots 0..3
 int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
 int red_fetch(Reducer& r, hipStream_t s);
+// fold nb partial sums (r.partial[i*stride + off]) into r.result[slot]
+int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s);
+// PCG update v~ += kappa s, r -= kappa Hs on [3][n] vectors, fused with the
+// reductions of the new residual: max |r| -> slot smax, sum of each component
+// of r -> slots ssum..ssum+2
+int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
+               float kappa, long long n, int smax, int ssum, hipStream_t st);
 
 // ------------------------------------------------------- vector updates
 // y = a*x + y

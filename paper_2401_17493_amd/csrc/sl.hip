@@ -543,30 +543,42 @@ __global__ __launch_bounds__(kThreads) void k_inc_first(const float* __restrict_
 }
 
 // out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2)
+template <bool DOT>
 __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__ lam,
                                                        const float* __restrict__ gm, int nt,
                                                        const float* __restrict__ add,
                                                        float* __restrict__ out, long long n,
-                                                       float ht) {
+                                                       float ht, const float* __restrict__ dv,
+                                                       double* __restrict__ partial) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-    for (int j = 0; j <= nt; ++j) {
-        const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
-        const float l = c * lam[(long long)j * n + idx];
-        const float* gj = gm + (long long)j * 3 * n;
-        acc0 = fmaf(l, gj[idx], acc0);
-        acc1 = fmaf(l, gj[n + idx], acc1);
-        acc2 = fmaf(l, gj[2 * n + idx], acc2);
+    double dot = 0.0;
+    if (idx < n) {
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        for (int j = 0; j <= nt; ++j) {
+            const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
+            const float l = c * lam[(long long)j * n + idx];
+            const float* gj = gm + (long long)j * 3 * n;
+            acc0 = fmaf(l, gj[idx], acc0);
+            acc1 = fmaf(l, gj[n + idx], acc1);
+            acc2 = fmaf(l, gj[2 * n + idx], acc2);
+        }
+        if (add) {
+            acc0 += add[idx];
+            acc1 += add[n + idx];
+            acc2 += add[2 * n + idx];
+        }
+        out[idx] = acc0;
+        out[n + idx] = acc1;
+        out[2 * n + idx] = acc2;
+        if (DOT)
+            dot = (double)dv[idx] * acc0 + (double)dv[n + idx] * acc1 +
+                  (double)dv[2 * n + idx] * acc2;
     }
-    if (add) {
-        acc0 += add[idx];
-        acc1 += add[n + idx];
-        acc2 += add[2 * n + idx];
+    if (DOT) {
+        __shared__ double sh[4];
+        const double t = block_sum_256(dot, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
     }
-    out[idx] = acc0;
-    out[n + idx] = acc1;
-    out[2 * n + idx] = acc2;
 }
 
 // Deformation gradient, eq. (e:def-grad): D F/Dt = (grad v) F along +v, one
@@ -692,9 +704,16 @@ int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
 }
 
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, const float* add,
-                    float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, lam, gradm, nt, add,
-                       out, g.n, (float)(1.0 / nt));
+                    float* out, hipStream_t s, const float* dot_with, Reducer* red, int slot) {
+    const unsigned nb = blocks_for(g.n);
+    if (dot_with) {
+        hipLaunchKernelGGL(k_assemble<true>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
+                           out, g.n, (float)(1.0 / nt), dot_with, red->partial);
+        CL_LAUNCH_CHECK();
+        return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
+    }
+    hipLaunchKernelGGL(k_assemble<false>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add, out,
+                       g.n, (float)(1.0 / nt), nullptr, nullptr);
     CL_LAUNCH_CHECK();
     return 0;
 }
