@@ -132,10 +132,17 @@ __global__ __launch_bounds__(kThreads) void k_fold(const double* __restrict__ pa
                                                    int stride, int off,
                                                    double* __restrict__ result, int slot) {
     __shared__ double sh[kThreads / kWave];
-    double acc = identity<OP>();
-    for (int i = threadIdx.x; i < nb; i += kThreads) acc = combine<OP>(acc, partial[i * stride + off]);
-    acc = block_reduce<OP>(acc, sh);
-    if (threadIdx.x == 0) result[slot] = acc;
+    // four independent accumulators keep several loads in flight
+    double acc[4] = {identity<OP>(), identity<OP>(), identity<OP>(), identity<OP>()};
+    int i = threadIdx.x;
+    for (; i + 3 * kThreads < nb; i += 4 * kThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = combine<OP>(acc[u], partial[(i + u * kThreads) * stride + off]);
+    }
+    for (; i < nb; i += kThreads) acc[0] = combine<OP>(acc[0], partial[i * stride + off]);
+    double a = combine<OP>(combine<OP>(acc[0], acc[1]), combine<OP>(acc[2], acc[3]));
+    a = block_reduce<OP>(a, sh);
+    if (threadIdx.x == 0) result[slot] = a;
 }
 
 __global__ __launch_bounds__(kThreads) void k_axpy(const float* __restrict__ x,

@@ -111,7 +111,7 @@ __device__ __forceinline__ void coords(const G3& g, long long idx, int& i1, int&
 // handed out so that each XCD sweeps a contiguous slab of the grid, keeping
 // the halo rows shared by neighbouring bricks in one L2.
 #ifndef CLAIRE_GATHER_BOXCAP
-#define CLAIRE_GATHER_BOXCAP 6144
+#define CLAIRE_GATHER_BOXCAP 4096
 #endif
 #ifndef CLAIRE_GATHER_VOX
 #define CLAIRE_GATHER_VOX 2
@@ -120,10 +120,14 @@ constexpr int kBoxCap = CLAIRE_GATHER_BOXCAP;  // floats of LDS per workgroup
 constexpr int kVox = CLAIRE_GATHER_VOX;        // voxels per thread: brick = 256 kVox voxels
 constexpr int kLogVox = kVox == 1 ? 0 : (kVox == 2 ? 1 : 2);
 #ifndef CLAIRE_GATHER_WAVES
-#define CLAIRE_GATHER_WAVES 4
+#define CLAIRE_GATHER_WAVES 8
 #endif
 // waves per SIMD the gather kernels are compiled for (bounds their VGPRs)
 constexpr int kGatherWaves = CLAIRE_GATHER_WAVES;
+// The backtrace stages full-step departure boxes (larger) for three fields
+// in turn: its own LDS budget and occupancy target.
+constexpr int kBoxCapBT = 6144;
+constexpr int kBacktraceWaves = 4;
 constexpr int kBatch = 8;          // independent loads in flight per thread while staging
 
 struct Brick {
@@ -426,12 +430,12 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
 //   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
 // c_a = h_t / h_a converts velocity to voxels per step. For each direction
 // the three components of v are staged through the brick's box in turn.
-__global__ __launch_bounds__(kThreads, kGatherWaves) void k_backtrace_lds(const float* __restrict__ v,
+__global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(const float* __restrict__ v,
                                                             float* __restrict__ dp,
                                                             float* __restrict__ dm, G3 g,
                                                             Brick br, long long n, float c1,
                                                             float c2, float c3) {
-    __shared__ float box[kBoxCap];
+    __shared__ float box[kBoxCapBT];
     __shared__ int red[kThreads / 64][6];
     const BrickPos bp = brick_pos(br);
     const float c[3] = {c1, c2, c3};
@@ -448,6 +452,7 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_backtrace_lds(const 
             for (int a = 0; a < 3; ++a) vx[k][a] = v[a * n + idx];
         }
     }
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const float sg = dir == 0 ? -1.f : 1.f;   // y~ = x + sg h_t v(x)
         float dd[kVox][3];
@@ -468,8 +473,9 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_backtrace_lds(const 
         }
         __syncthreads();   // `red` and `box` of the previous direction are free
         const Box b = reduce_box(mn1, mn2, mn3, mx1, mx2, mx3, red);
-        const bool fits = b.vol <= kBoxCap;
+        const bool fits = b.vol <= kBoxCapBT;
         float u[kVox][3];
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             const float* src = v + (long long)f * n;
             if (fits) {
