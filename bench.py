@@ -7,11 +7,16 @@ H1 seminorm, alpha = 1e-3, n_t = 4, gradient tolerance 5e-2, from v = 0,
 inputs resident in HBM. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--precision mixed|fp32|both]
 
-Besides the solve time (``value``, seconds) the line carries the Hessian
-matvec throughput, the HBM roofline of the dominant kernel (average launch
-duration measured here with HIP events) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+``value`` is the time-to-solution (seconds) of the mixed-precision solve
+(float16 storage of grad m and the incremental sources in the Hessian matvec,
+float32 arithmetic); with --precision both (default) the float32 solve is
+timed too and the line reports both, with the differences of the two
+solutions. The line also carries the Hessian matvec throughput, the HBM
+roofline of the dominant kernel (average launch duration measured here with
+HIP events) and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -113,6 +118,7 @@ def main():
     ap.add_argument("--roofline-kernel", default="inc_state_step",
                     choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="both", choices=["mixed", "fp32", "both"])
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up at v = v*/2 and launch only the roofline kernel and the copy "
                          "kernel (for hardware-counter runs); prints their timings")
@@ -149,33 +155,42 @@ def main():
                           "copy_ms_per_launch": ms_c, "voxels": n[0] * n[1] * n[2]}))
         ctx.close()
         return
-    for _ in range(args.warmup):
-        ctx.solve(**opts)
-    torch.cuda.synchronize()
-    times, stats = [], None
-    for _ in range(args.steps):
+    precisions = {"mixed": [1], "fp32": [0], "both": [1, 0]}[args.precision]
+    runs = {}
+    for prec in precisions:
+        o = dict(opts, precision=prec)
+        for _ in range(args.warmup):
+            ctx.solve(**o)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        v, stats = ctx.solve(**opts)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        print("step: solve %.3f s, %d GN iterations, %d matvecs" %
-              (times[-1], stats["gn_iters"], stats["matvecs"]), file=sys.stderr, flush=True)
-    tts = sum(times) / len(times)
-
-    # Hessian matvec throughput at the solution, HIP events on the context stream
-    ctx.set_velocity(v)
-    vt = (0.5 * vstar).contiguous()
-    hv = torch.empty_like(vt)
-    ctx.hessian_matvec(vt, hv)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(ctx.stream)
-    for _ in range(args.matvecs):
+        times, stats, v = [], None, None
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v, stats = ctx.solve(**o)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            print("step (%s): solve %.3f s, %d GN iterations, %d matvecs" %
+                  ("mixed" if prec else "fp32", times[-1], stats["gn_iters"], stats["matvecs"]),
+                  file=sys.stderr, flush=True)
+        # Hessian matvec throughput at the solution, HIP events on the context stream
+        ctx.set_precision(prec)
+        ctx.set_velocity(v)
+        vt = (0.5 * vstar).contiguous()
+        hv = torch.empty_like(vt)
         ctx.hessian_matvec(vt, hv)
-    e1.record(ctx.stream)
-    e1.synchronize()
-    ms_matvec = e0.elapsed_time(e1) / args.matvecs
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.matvecs):
+            ctx.hessian_matvec(vt, hv)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        runs[prec] = dict(tts=sum(times) / len(times), stats=stats, v=v,
+                          ms_matvec=e0.elapsed_time(e1) / args.matvecs)
+    head = runs[precisions[0]]
+    tts, stats, ms_matvec = head["tts"], head["stats"], head["ms_matvec"]
+    ctx.set_precision(0)
+    ctx.set_velocity(head["v"])
 
     # roofline of the dominant kernel: algorithmic bytes / live launch duration
     ms_kernel = ctx.time_kernel(kid, reps=50)
@@ -188,6 +203,16 @@ def main():
           "matvec %.3f ms" % (args.roofline_kernel, ms_kernel, achieved, copy_gbs, ms_matvec),
           file=sys.stderr, flush=True)
     ctx.close()
+
+    def solve_rec(r):
+        st = r["stats"]
+        rec = {k: st[k] for k in ("gn_iters", "matvecs", "pde_solves", "linesearch_trials",
+                                  "rel_grad", "rel_mismatch", "J0", "J", "det_min", "det_max",
+                                  "det_nonpositive")}
+        rec.update(time_to_solution_s=round(r["tts"], 4),
+                   hessian_matvecs_per_s=round(1000.0 / r["ms_matvec"], 2),
+                   ms_per_matvec=round(r["ms_matvec"], 4))
+        return rec
 
     out = {
         "metric": METRIC,
@@ -206,13 +231,13 @@ def main():
                    "alpha": alpha if not levels else levels,
                    "regularization": "H%d seminorm" % w["reg_order"],
                    "gtol": opts["gtol"], "preconditioner": "(alpha L)^-1",
+                   "precision": "mixed: float16 grad m and incremental sources in the "
+                                "Hessian matvec, float32 arithmetic/FFTs, float64 reductions"
+                   if precisions[0] == 1 else "float32 fields and FFTs, float64 reductions",
                    "parallelism": "single GPU"},
         "hessian_matvecs_per_s": round(1000.0 / ms_matvec, 2),
         "ms_per_matvec": round(ms_matvec, 4),
-        "solve": {k: stats[k] for k in ("gn_iters", "matvecs", "pde_solves",
-                                        "linesearch_trials", "rel_grad", "rel_mismatch",
-                                        "J0", "J", "det_min", "det_max",
-                                        "det_nonpositive")},
+        "solve": solve_rec(head),
         "roofline": {"kernel": args.roofline_kernel, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -221,6 +246,15 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "copy_kernel_GBs": round(copy_gbs, 1)},
     }
+    if len(precisions) == 2:
+        mixed, plain = runs[1], runs[0]
+        vm, vp = mixed["v"], plain["v"]
+        out["fp32_solve"] = solve_rec(plain)
+        out["mixed_vs_fp32"] = {
+            "speedup": round(plain["tts"] / mixed["tts"], 3),
+            "v_rel_maxnorm": float((vm - vp).abs().max() / vp.abs().max()),
+            "J_rel": abs(mixed["stats"]["J"] - plain["stats"]["J"]) / plain["stats"]["J"],
+            "rel_grad": [mixed["stats"]["rel_grad"], plain["stats"]["rel_grad"]]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, host_inputs)
     print(json.dumps(out), flush=True)

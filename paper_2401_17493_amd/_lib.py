@@ -70,6 +70,7 @@ SIGNATURES = {
     "claire_ctx_objective": (c_int, [c_void_p, c_void_p, c_double_p]),
     "claire_ctx_hessian_matvec": (c_int, [c_void_p, c_void_p, c_void_p]),
     "claire_ctx_precond": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "claire_ctx_set_precision": (c_int, [c_void_p, c_int]),
     "claire_ctx_solve": (c_int, [c_void_p, ctypes.POINTER(ClaireOpts), c_void_p,
                                  ctypes.POINTER(ClaireStats)]),
     "claire_ctx_detdefgrad": (c_int, [c_void_p, c_void_p, c_double_p]),

@@ -123,6 +123,10 @@ class Context:
         _check(self.lib.claire_ctx_set_alpha(self._h, float(alpha)))
         self.alpha = float(alpha)
 
+    def set_precision(self, precision: int):
+        """0: float32 matvec storage; 1: float16 storage in the Hessian matvec."""
+        _check(self.lib.claire_ctx_set_precision(self._h, int(precision)))
+
     def set_images(self, m0: torch.Tensor, m1: torch.Tensor):
         _check(self.lib.claire_ctx_set_images(self._h, _ptr(m0, self.n, "m0"),
                                               _ptr(m1, self.n, "m1")))

@@ -81,6 +81,12 @@ struct claire_ctx {
     float* tmp3 = nullptr;   // [3][n]
     int* box_p = nullptr;    // per-brick stencil boxes of dp
     int* box_m = nullptr;    // per-brick stencil boxes of dm
+
+    // mixed precision (half storage in the Hessian matvec), allocated on demand
+    int precision = 0;       // 0 float32, 1 mixed
+    __half* gm16 = nullptr;  // [nt+1][3][n] grad m^j
+    __half* f16 = nullptr;   // [nt+1][n] incremental-state sources (scaled)
+    bool half_valid = false; // gm16 belongs to the current setup
     SpectralWork sw;
     Reducer red;
     int* flag = nullptr;     // device int (non-finite check)
@@ -158,6 +164,8 @@ void ctx_release(claire_ctx* c) {
                      c->regv, c->lam, c->w0, c->w1, c->tmp3, c->vt, c->r, c->z, c->sd, c->hs,
                      c->vtrial, c->als};
     for (float* b : bufs) dfree(b);
+    __half* hbufs[] = {c->gm16, c->f16};
+    for (__half* b : hbufs) dfree(b);
     dfree(c->flag);
     dfree(c->box_p);
     dfree(c->box_m);
@@ -187,6 +195,14 @@ int run_state(claire_ctx* c) {
     return 0;
 }
 
+int ensure_half_buffers(claire_ctx* c) {
+    const long long n = c->g.n;
+    const int nt = c->nt;
+    if (!c->gm16) CL_TRY(dalloc(&c->gm16, 3 * (nt + 1) * n));
+    if (!c->f16) CL_TRY(dalloc(&c->f16, (nt + 1) * n));
+    return 0;
+}
+
 // Full per-velocity setup; the state is reused when state_valid says the
 // backtrace and m^j already belong to c->v (accepted line-search trial).
 int run_setup(claire_ctx* c) {
@@ -211,6 +227,13 @@ int run_setup(claire_ctx* c) {
     for (int j = nt - 1; j >= 0; --j)
         CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
                                    c->lam + (long long)j * n, c->s, c->box_m));
+    // half copies for the mixed-precision matvec
+    c->half_valid = false;
+    if (c->precision == 1) {
+        CL_TRY(ensure_half_buffers(c));
+        CL_TRY(launch_to_half(c->gm, c->gm16, 3 * (nt + 1) * n, c->s));
+        c->half_valid = true;
+    }
     // reduced gradient (eq. e:rgrad), trapezoid in time
     CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->regv, c->grad, c->s));
     CL_TRY(red_absmax(c->red, c->grad, 3 * n, 2, c->s));
@@ -232,8 +255,12 @@ int run_setup(claire_ctx* c) {
 // reg_part: alpha L vt when the caller already has it (PCG), else NULL and
 // it is computed here by FFT. dot_slot >= 0: also <vt, out> into that
 // reduction slot.
+int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
+                     int dot_slot);
+
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
                int dot_slot = -1) {
+    if (c->precision == 1) return run_matvec_mixed(c, vt, out, reg_part, dot_slot);
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -268,6 +295,52 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
         CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot));
     else
         CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s));
+    return 0;
+}
+
+// Mixed-precision Gauss--Newton matvec: the same steps as run_matvec with
+// grad m^j and the incremental-state sources f^j = -grad m^j . v~ stored in
+// half (float arithmetic; the per-step fields, A and the displacements stay
+// float). The sources of all time levels are formed in one pass; v~ is
+// normalised by max|v~| (a device scalar, no host round trip) so no stored
+// value can overflow, and the assembly multiplies the scale back in.
+int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
+                     int dot_slot) {
+    const Geo& g = c->g;
+    const long long n = g.n;
+    const int nt = c->nt;
+    const double ht = 1.0 / nt;
+    const int kScaleSlot = 7;
+    const double* scale = c->red.result + kScaleSlot;
+    CL_TRY(red_absmax(c->red, vt, 3 * n, kScaleSlot, c->s));
+    CL_TRY(launch_mixed_sources(g, c->gm16, vt, scale, c->f16, c->w0, nt, c->s));
+    float* src = c->w0;
+    float* nxt = c->w1;
+    for (int j = 0; j < nt; ++j) {
+        const __half* fnext = c->f16 + (long long)(j + 1) * n;
+        if (j + 1 < nt) {
+            CL_TRY(launch_inc_state_step_mixed(g, src, c->dp, fnext, nxt, (float)ht, 1.0f, c->s,
+                                               c->box_p));
+            float* t = src;
+            src = nxt;
+            nxt = t;
+        } else {
+            CL_TRY(launch_inc_state_step_mixed(g, src, c->dp, fnext, c->lam + (long long)nt * n,
+                                               (float)(0.5 * ht), -1.0f, c->s, c->box_p));
+        }
+    }
+    for (int j = nt - 1; j >= 0; --j)
+        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
+                                   c->lam + (long long)j * n, c->s, c->box_m));
+    if (!reg_part) {
+        CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
+        reg_part = c->tmp3;
+    }
+    if (dot_slot >= 0)
+        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, reg_part, out, c->s, vt,
+                                 &c->red, dot_slot));
+    else
+        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, reg_part, out, c->s));
     return 0;
 }
 
@@ -618,12 +691,32 @@ int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
         set_error("opts->reg_order %d differs from the context's %d", o.reg_order, c->p);
         return CLAIRE_EINVAL;
     }
-    if (o.precision != 0) { set_error("only precision 0 (float32) is supported"); return CLAIRE_EINVAL; }
+    if (o.precision != 0 && o.precision != 1) {
+        set_error("precision must be 0 (float32) or 1 (mixed)");
+        return CLAIRE_EINVAL;
+    }
     if (o.max_gn < 0 || o.max_pcg < 1 || o.max_linesearch < 1 || !(o.gtol >= 0)) {
         set_error("invalid solver limits");
         return CLAIRE_EINVAL;
     }
-    return run_solve(c, o, v_inout, stats);
+    const int saved = c->precision;
+    c->precision = o.precision;
+    const int rc = run_solve(c, o, v_inout, stats);
+    c->precision = saved;
+    if (saved == 1 && o.precision != 1) c->have_velocity = false;   // half copies not made
+    return rc;
+}
+
+int claire_ctx_set_precision(claire_ctx* c, int precision) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    if (precision != 0 && precision != 1) {
+        set_error("precision must be 0 (float32) or 1 (mixed)");
+        return CLAIRE_EINVAL;
+    }
+    if (precision == 1) CL_TRY(ensure_half_buffers(c));
+    if (precision != c->precision) c->have_velocity = false;   // redo the setup
+    c->precision = precision;
+    return 0;
 }
 
 int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_fp16.h>
+
 #include <cstdint>
 
 #include "claire.h"
@@ -95,6 +97,21 @@ int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
 int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt,
                     const float* add, float* out, hipStream_t s,
                     const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
+// Mixed precision for the Hessian matvec: grad m^j and the incremental
+// sources f^j in half, everything else float.
+int launch_to_half(const float* x, __half* y, long long n, hipStream_t s);
+// f^j = -grad m^j . v~ / scale (j >= 1, half) and w^0 = (h_t/2) f^0 (float);
+// scale: device double
+int launch_mixed_sources(const Geo& g, const __half* gm, const float* vt, const double* scale,
+                         __half* f, float* w0, int nt, hipStream_t s);
+int launch_inc_state_step_mixed(const Geo& g, const float* w_prev, const float* dplus,
+                                const __half* f_next, float* out, float coef, float sign,
+                                hipStream_t s, const int* boxes);
+// out = add + scale h_t sum_j c_j lam^j grad m^j (+ <dot_with, out> into red slot)
+int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int nt,
+                      const double* scale, const float* add, float* out, hipStream_t s,
+                      const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
+
 // one RK2 step of the deformation-gradient transport from gathered F_y, G_y
 // (Fy NULL: F^0 = I); F may alias Fy
 int launch_defgrad_update(const Geo& g, const float* Fy, const float* Gy, const float* G,

@@ -10,6 +10,8 @@
 
 #include "internal.h"
 
+#include <hip/hip_fp16.h>
+
 namespace claire {
 namespace {
 
@@ -64,8 +66,12 @@ __device__ __forceinline__ void make_stencil(const G3& g, int i1, int i2, int i3
     }
 }
 
-template <int NF>
-__device__ __forceinline__ void gather(const float* __restrict__ f, long long fstride,
+// element loads of float or half fields, widened to float
+__device__ __forceinline__ float ldf(const float* p) { return *p; }
+__device__ __forceinline__ float ldf(const __half* p) { return __half2float(*p); }
+
+template <int NF, typename T = float>
+__device__ __forceinline__ void gather(const T* __restrict__ f, long long fstride,
                                        const Stencil& st, float out[NF]) {
 #pragma unroll
     for (int k = 0; k < NF; ++k) out[k] = 0.f;
@@ -77,11 +83,11 @@ __device__ __forceinline__ void gather(const float* __restrict__ f, long long fs
             const float wab = st.w1[a] * st.w2[b];
 #pragma unroll
             for (int k = 0; k < NF; ++k) {
-                const float* p = f + k * fstride + row;
-                float t = st.w3[0] * p[st.o3[0]];
-                t = fmaf(st.w3[1], p[st.o3[1]], t);
-                t = fmaf(st.w3[2], p[st.o3[2]], t);
-                t = fmaf(st.w3[3], p[st.o3[3]], t);
+                const T* p = f + k * fstride + row;
+                float t = st.w3[0] * ldf(p + st.o3[0]);
+                t = fmaf(st.w3[1], ldf(p + st.o3[1]), t);
+                t = fmaf(st.w3[2], ldf(p + st.o3[2]), t);
+                t = fmaf(st.w3[3], ldf(p + st.o3[3]), t);
                 out[k] = fmaf(wab, t, out[k]);
             }
         }
@@ -271,7 +277,8 @@ __device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
 
 // Copy the box [e1][e2][e3] of field `src` into LDS (rows along x3 are
 // contiguous): batches of independent loads, then the LDS stores.
-__device__ __forceinline__ void stage_box(float* box, const float* __restrict__ src, const G3& g,
+template <typename T>
+__device__ __forceinline__ void stage_box(float* box, const T* __restrict__ src, const G3& g,
                                           const Box& b) {
     const int tid = threadIdx.x;
     const int nvol = (int)b.vol;
@@ -285,8 +292,8 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
                 int a3, a2;
                 const int row = quot(e, b.e3, inv3, a3);
                 const int a1 = quot(row, b.e2, inv2, a2);
-                tmp[u] = src[((long long)((b.lo1 + a1) & g.m1) << g.s1) +
-                             ((long long)((b.lo2 + a2) & g.m2) << g.l3) + ((b.lo3 + a3) & g.m3)];
+                tmp[u] = ldf(src + ((long long)((b.lo1 + a1) & g.m1) << g.s1) +
+                             ((long long)((b.lo2 + a2) & g.m2) << g.l3) + ((b.lo3 + a3) & g.m3));
             }
         }
 #pragma unroll
@@ -323,13 +330,14 @@ __device__ __forceinline__ float interp_box(const float* box, const Box& b, cons
 }
 
 // Tricubic value by direct global gathers (bricks whose box does not fit).
-__device__ __forceinline__ float interp_global(const float* __restrict__ src, const G3& g,
+template <typename T>
+__device__ __forceinline__ float interp_global(const T* __restrict__ src, const G3& g,
                                                long long n, int i1, int i2, int i3,
                                                const float d[3]) {
     Stencil st;
     make_stencil(g, i1, i2, i3, d[0], d[1], d[2], st);
     float u;
-    gather<1>(src, n, st, &u);
+    gather<1, T>(src, n, st, &u);
     return u;
 }
 
@@ -365,9 +373,22 @@ __global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restric
 
 // Single-field gather u = src(x + d(x)) with epilogue; `table` holds the
 // per-brick boxes of d (NULL: reduce them here).
-template <class Epi>
+// Mixed precision: incremental-state step whose grid source f^{j+1} is
+// stored in half (float arithmetic, float gathered field and output).
+struct EpiIncStateMixed {    // out = sign (u + coef f)
+    const __half* f;
+    float* out;
+    float coef, sign;
+    struct Pre { float f; };
+    __device__ Pre load(long long i) const { return Pre{__half2float(f[i])}; }
+    __device__ void store(long long i, float u, const Pre& p) const {
+        out[i] = sign * (u + coef * p.f);
+    }
+};
+
+template <class Epi, typename T = float>
 __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
-    const float* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
+    const T* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
     Epi epi, G3 g, Brick br, long long n) {
     __shared__ float box[kBoxCap];
     __shared__ int red[kThreads / 64][6];
@@ -503,12 +524,12 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(con
     }
 }
 
-template <class Epi>
-int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
+template <class Epi, typename T>
+int launch_gather_lds(const Geo& g, const T* src, const float* disp, const int* table,
                       const Epi& epi, hipStream_t s) {
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL(k_gather_lds<Epi>, dim3(br.nbricks), dim3(kThreads), 0, s, src, disp, table,
-                       epi, make_g3(g), br, g.n);
+    hipLaunchKernelGGL((k_gather_lds<Epi, T>), dim3(br.nbricks), dim3(kThreads), 0, s, src, disp,
+                       table, epi, make_g3(g), br, g.n);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -639,6 +660,82 @@ __global__ __launch_bounds__(kThreads) void k_det(const float* __restrict__ F,
                a[2] * (a[3] * a[7] - a[4] * a[6]);
 }
 
+// ----------------------------------------------------------- mixed precision
+// Incremental-state sources for all time levels in one pass:
+// f^j = -grad m^j . v~ / sc (j = 1..nt, stored in half) and
+// w^0 = (h_t/2) f^0 (float); sc = max|v~| (device scalar) keeps every stored
+// value O(|grad m|), far inside the half range.
+__global__ __launch_bounds__(kThreads) void k_mixed_sources(const __half* __restrict__ gm,
+                                                            const float* __restrict__ vt,
+                                                            const double* __restrict__ scale,
+                                                            __half* __restrict__ f,
+                                                            float* __restrict__ w0, int nt,
+                                                            long long n, float half_ht) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    const double sc = *scale;
+    const float inv = sc > 0.0 ? (float)(1.0 / sc) : 0.f;
+    const float v0 = vt[idx] * inv, v1 = vt[n + idx] * inv, v2 = vt[2 * n + idx] * inv;
+    for (int j = 0; j <= nt; ++j) {
+        const __half* gj = gm + (long long)j * 3 * n;
+        const float fj = -(__half2float(gj[idx]) * v0 + __half2float(gj[n + idx]) * v1 +
+                           __half2float(gj[2 * n + idx]) * v2);
+        if (j == 0) w0[idx] = half_ht * fj;
+        else f[(long long)j * n + idx] = __float2half(fj);
+    }
+}
+
+// out = add + sc h_t sum_j c_j lam^j grad m^j with grad m^j in half; optional
+// <dv, out> per block.
+template <bool DOT>
+__global__ __launch_bounds__(kThreads) void k_assemble_h(const float* __restrict__ lam,
+                                                         const __half* __restrict__ gm, int nt,
+                                                         const float* __restrict__ add,
+                                                         float* __restrict__ out, long long n,
+                                                         float ht, const double* __restrict__ scale,
+                                                         const float* __restrict__ dv,
+                                                         double* __restrict__ partial) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    double dot = 0.0;
+    if (idx < n) {
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        for (int j = 0; j <= nt; ++j) {
+            const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
+            const float l = c * lam[(long long)j * n + idx];
+            const __half* gj = gm + (long long)j * 3 * n;
+            acc0 = fmaf(l, __half2float(gj[idx]), acc0);
+            acc1 = fmaf(l, __half2float(gj[n + idx]), acc1);
+            acc2 = fmaf(l, __half2float(gj[2 * n + idx]), acc2);
+        }
+        const float sc = (float)*scale;
+        acc0 *= sc;
+        acc1 *= sc;
+        acc2 *= sc;
+        if (add) {
+            acc0 += add[idx];
+            acc1 += add[n + idx];
+            acc2 += add[2 * n + idx];
+        }
+        out[idx] = acc0;
+        out[n + idx] = acc1;
+        out[2 * n + idx] = acc2;
+        if (DOT)
+            dot = (double)dv[idx] * acc0 + (double)dv[n + idx] * acc1 +
+                  (double)dv[2 * n + idx] * acc2;
+    }
+    if (DOT) {
+        __shared__ double sh[4];
+        const double t = block_sum_256(dot, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_to_half(const float* __restrict__ x,
+                                                      __half* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = __float2half(x[i]);
+}
+
 unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -725,6 +822,43 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
 }
 
 int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
+
+int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_mixed_sources(const Geo& g, const __half* gm, const float* vt, const double* scale,
+                         __half* f, float* w0, int nt, hipStream_t s) {
+    hipLaunchKernelGGL(k_mixed_sources, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gm, vt, scale,
+                       f, w0, nt, g.n, (float)(0.5 / nt));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_inc_state_step_mixed(const Geo& g, const float* w_prev, const float* dplus,
+                                const __half* f_next, float* out, float coef, float sign,
+                                hipStream_t s, const int* boxes) {
+    return launch_gather_lds(g, w_prev, dplus, boxes, EpiIncStateMixed{f_next, out, coef, sign},
+                             s);
+}
+
+int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int nt,
+                      const double* scale, const float* add, float* out, hipStream_t s,
+                      const float* dot_with, Reducer* red, int slot) {
+    const unsigned nb = blocks_for(g.n);
+    if (dot_with) {
+        hipLaunchKernelGGL(k_assemble_h<true>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
+                           out, g.n, (float)(1.0 / nt), scale, dot_with, red->partial);
+        CL_LAUNCH_CHECK();
+        return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
+    }
+    hipLaunchKernelGGL(k_assemble_h<false>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
+                       out, g.n, (float)(1.0 / nt), scale, nullptr, nullptr);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
 
 int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s) {
     const Brick br = make_brick(g);
