@@ -70,6 +70,23 @@ __device__ __forceinline__ void make_stencil(const G3& g, int i1, int i2, int i3
 __device__ __forceinline__ float ldf(const float* p) { return *p; }
 __device__ __forceinline__ float ldf(const __half* p) { return __half2float(*p); }
 
+// Element i of a field with a uniform base pointer: the per-lane offset is a
+// 32-bit byte offset (i < 2^30), so the load takes the scalar-base +
+// vector-offset form with no 64-bit address arithmetic per lane.
+__device__ __forceinline__ float ldi(const float* p, unsigned i) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (i << 2));
+}
+__device__ __forceinline__ float ldi(const __half* p, unsigned i) {
+    return __half2float(
+        *reinterpret_cast<const __half*>(reinterpret_cast<const char*>(p) + (i << 1)));
+}
+__device__ __forceinline__ float4 ldi4(const float* p, unsigned i) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + (i << 2));
+}
+__device__ __forceinline__ void sti(float* p, unsigned i, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(p) + (i << 2)) = v;
+}
+
 template <int NF, typename T = float>
 __device__ __forceinline__ void gather(const T* __restrict__ f, long long fstride,
                                        const Stencil& st, float out[NF]) {
@@ -134,7 +151,6 @@ constexpr int kGatherWaves = CLAIRE_GATHER_WAVES;
 // in turn: its own LDS budget and occupancy target.
 constexpr int kBoxCapBT = 6144;
 constexpr int kBacktraceWaves = 4;
-constexpr int kBatch = 8;          // independent loads in flight per thread while staging
 
 struct Brick {
     int lb1, lb2, lb3;     // log2 of the brick extents
@@ -171,15 +187,15 @@ __device__ __forceinline__ int wave_max(int v) {
 struct EpiStore {        // out = u
     float* out;
     struct Pre {};
-    __device__ Pre load(long long) const { return Pre{}; }
-    __device__ void store(long long i, float u, const Pre&) const { out[i] = u; }
+    __device__ Pre load(unsigned) const { return Pre{}; }
+    __device__ void store(unsigned i, float u, const Pre&) const { sti(out, i, u); }
 };
 struct EpiScale {        // out = A u  (continuity-equation step along -v)
     const float* A;
     float* out;
     struct Pre { float a; };
-    __device__ Pre load(long long i) const { return Pre{A[i]}; }
-    __device__ void store(long long i, float u, const Pre& p) const { out[i] = p.a * u; }
+    __device__ Pre load(unsigned i) const { return Pre{ldi(A, i)}; }
+    __device__ void store(unsigned i, float u, const Pre& p) const { sti(out, i, p.a * u); }
 };
 struct EpiIncState {     // out = sign (u + coef f), f = -grad m . v~
     const float* gm;
@@ -188,11 +204,12 @@ struct EpiIncState {     // out = sign (u + coef f), f = -grad m . v~
     long long n;
     float coef, sign;
     struct Pre { float f; };
-    __device__ Pre load(long long i) const {
-        return Pre{-(gm[i] * vt[i] + gm[n + i] * vt[n + i] + gm[2 * n + i] * vt[2 * n + i])};
+    __device__ Pre load(unsigned i) const {
+        return Pre{-(ldi(gm, i) * ldi(vt, i) + ldi(gm + n, i) * ldi(vt + n, i) +
+                     ldi(gm + 2 * n, i) * ldi(vt + 2 * n, i))};
     }
-    __device__ void store(long long i, float u, const Pre& p) const {
-        out[i] = sign * (u + coef * p.f);
+    __device__ void store(unsigned i, float u, const Pre& p) const {
+        sti(out, i, sign * (u + coef * p.f));
     }
 };
 struct EpiMakeA {        // out = 1 + (h_t/2)(D(y-) + D + h_t D(y-) D)
@@ -200,9 +217,22 @@ struct EpiMakeA {        // out = 1 + (h_t/2)(D(y-) + D + h_t D(y-) D)
     float* out;
     float ht;
     struct Pre { float dx; };
-    __device__ Pre load(long long i) const { return Pre{D[i]}; }
-    __device__ void store(long long i, float u, const Pre& p) const {
-        out[i] = 1.0f + 0.5f * ht * (u + p.dx + ht * u * p.dx);
+    __device__ Pre load(unsigned i) const { return Pre{ldi(D, i)}; }
+    __device__ void store(unsigned i, float u, const Pre& p) const {
+        sti(out, i, 1.0f + 0.5f * ht * (u + p.dx + ht * u * p.dx));
+    }
+};
+
+// Mixed precision: incremental-state step whose grid source f^{j+1} is
+// stored in half (float arithmetic, float gathered field and output).
+struct EpiIncStateMixed {    // out = sign (u + coef f)
+    const __half* f;
+    float* out;
+    float coef, sign;
+    struct Pre { float f; };
+    __device__ Pre load(unsigned i) const { return Pre{ldi(f, i)}; }
+    __device__ void store(unsigned i, float u, const Pre& p) const {
+        sti(out, i, sign * (u + coef * p.f));
     }
 };
 
@@ -225,23 +255,46 @@ __device__ __forceinline__ BrickPos brick_pos(const Brick& br) {
     return p;
 }
 
-// k-th voxel of this thread: grid coordinates and linear index (false if none)
+// k-th voxel of this thread: grid coordinates and linear index (false if
+// none). Order within the brick: x3 fastest, then x1, then x2, so the 64 lanes
+// of a wave cover 16 x3 voxels in each of 4 x1 planes of one x2 row.
 __device__ __forceinline__ bool brick_voxel(const G3& g, const Brick& br, const BrickPos& p,
-                                            int k, int& i1, int& i2, int& i3, long long& idx) {
+                                            int k, int& i1, int& i2, int& i3, unsigned& idx) {
     const int v = threadIdx.x + k * kThreads;
     if (v >= p.bvol) return false;
     i3 = p.o3 + (v & ((1 << br.lb3) - 1));
-    i2 = p.o2 + ((v >> br.lb3) & ((1 << br.lb2) - 1));
-    i1 = p.o1 + (v >> (br.lb3 + br.lb2));
-    idx = ((long long)i1 << g.s1) + ((long long)i2 << g.l3) + i3;
+    i1 = p.o1 + ((v >> br.lb3) & ((1 << br.lb1) - 1));
+    i2 = p.o2 + (v >> (br.lb3 + br.lb1));
+    idx = ((unsigned)i1 << g.s1) | ((unsigned)i2 << g.l3) | (unsigned)i3;
     return true;
 }
 
-// Box covering all stencil origins q (already reduced per thread into
-// mn/mx): block reduction through `red`, result in lo[3], e[3]. Contains a
-// barrier; callers must not be reading `red` from an earlier call.
-struct Box { int lo1, lo2, lo3, e1, e2, e3; long long vol; };
+// Box covering all stencil origins: [lo, lo + e) per axis (e = spread of
+// the origins + 4). In LDS each x3 row holds whole aligned float4 segments:
+// columns cb .. cb + p3 - 1 with cb = lo3 rounded down to a multiple of 4 and
+// p3 = 4 ng, so the box is staged with 16-byte loads and stores (n3 is a
+// multiple of 4: a segment never straddles the periodic wrap). Rows of one x1
+// plane are p3 apart and planes pp = e2 p3 + pad apart with pp = 16 mod 64:
+// the four 16-lane groups of a wave read four different planes, and with that
+// pitch their addresses fall in disjoint LDS banks (32 banks per half wave or
+// 64 per wave alike) as long as each group reads a contiguous run.
+struct Box {
+    int lo1, lo2, lo3, e1, e2, e3;
+    int cb, ng, p3, pp;
+    long long vol;     // LDS floats, e1 pp
+};
 
+__device__ __forceinline__ void box_layout(Box& b) {
+    b.cb = b.lo3 & ~3;
+    b.ng = ((b.lo3 + b.e3 - 1 - b.cb) >> 2) + 1;
+    b.p3 = 4 * b.ng;
+    const long long plane = (long long)b.e2 * b.p3;
+    b.pp = (int)(plane + ((16 - plane) & 63));
+    b.vol = (long long)b.e1 * b.pp;
+}
+
+// Block reduction of the per-thread origin bounds mn/mx through `red`.
+// Contains a barrier; callers must not be reading `red` from an earlier call.
 __device__ __forceinline__ Box reduce_box(int mn1, int mn2, int mn3, int mx1, int mx2, int mx3,
                                           int (*red)[6]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -262,69 +315,90 @@ __device__ __forceinline__ Box reduce_box(int mn1, int mn2, int mn3, int mx1, in
     Box b;
     b.lo1 = lo1; b.lo2 = lo2; b.lo3 = lo3;
     b.e1 = hi1 - lo1 + 4; b.e2 = hi2 - lo2 + 4; b.e3 = hi3 - lo3 + 4;
-    b.vol = (long long)b.e1 * b.e2 * b.e3;
+    box_layout(b);
     return b;
 }
 
-// a / b for 0 <= a < 2^24, 0 < b, with inv_b = 1/b: the float quotient is off
-// by at most one, corrected through the remainder r.
+// Exact a / b for 0 <= a < 2^14 and 1 <= b <= 4096 from one float product:
+// with inv_b = (1 + 2^-16) / b rounded to float, trunc(a * inv_b) = floor(a/b)
+// (the bias lifts exact multiples above the rounding error and stays below
+// 1/b for a < 2^14; verified exhaustively in IEEE single precision over that
+// range). 24-bit integer products keep the remainder full-rate.
+__device__ __forceinline__ float quot_inv(int b) { return (1.0f + 0x1p-16f) / (float)b; }
 __device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
-    int q = (int)((float)a * inv_b);
-    r = a - q * b;
-    if (r < 0) { --q; r += b; } else if (r >= b) { ++q; r -= b; }
+    const int q = (int)((float)a * inv_b);
+    r = a - (int)__umul24((unsigned)q, (unsigned)b);
     return q;
 }
 
-// Copy the box [e1][e2][e3] of field `src` into LDS (rows along x3 are
-// contiguous): batches of independent loads, then the LDS stores.
-template <typename T>
-__device__ __forceinline__ void stage_box(float* box, const T* __restrict__ src, const G3& g,
+// Copy the box of field `src` into LDS (requires b.vol within the LDS
+// budget; rows e1 e2 < 2^14). Row `row` = a1 e2 + a2 starts at LDS float
+// a1 pp + a2 p3 and holds columns cb .. cb + p3 - 1 as ng float4 segments. A
+// thread always moves segment j = tid mod ng of rows tid / ng + k (kThreads /
+// ng): one division per segment. Batches of independent 16-byte loads, then
+// the 16-byte LDS stores.
+constexpr int kSegBatch = 4;
+__device__ __forceinline__ void stage_box(float* box, const float* __restrict__ src, const G3& g,
                                           const Box& b) {
-    const int tid = threadIdx.x;
-    const int nvol = (int)b.vol;
-    const float inv3 = 1.0f / (float)b.e3, inv2 = 1.0f / (float)b.e2;
-    for (int e0 = 0; e0 < nvol; e0 += kThreads * kBatch) {
-        float tmp[kBatch];
+    const int nrows = b.e1 * b.e2;
+    const int rpp = kThreads / b.ng;               // rows per pass
+    int j;
+    int r0 = quot((int)threadIdx.x, b.ng, quot_inv(b.ng), j);
+    if (r0 >= rpp) r0 = nrows;                     // idle lanes of the last partial row set
+    const unsigned col = (unsigned)((b.cb + 4 * j) & g.m3);
+    const float inv_e2 = quot_inv(b.e2);
+    float4* box4 = reinterpret_cast<float4*>(box);
+    for (int r = r0; r < nrows; r += rpp * kSegBatch) {
+        float4 tmp[kSegBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            if (e < nvol) {
-                int a3, a2;
-                const int row = quot(e, b.e3, inv3, a3);
-                const int a1 = quot(row, b.e2, inv2, a2);
-                tmp[u] = ldf(src + ((long long)((b.lo1 + a1) & g.m1) << g.s1) +
-                             ((long long)((b.lo2 + a2) & g.m2) << g.l3) + ((b.lo3 + a3) & g.m3));
+        for (int u = 0; u < kSegBatch; ++u) {
+            const int row = r + u * rpp;
+            if (row < nrows) {
+                int a2;
+                const int a1 = quot(row, b.e2, inv_e2, a2);
+                const unsigned off = ((unsigned)((b.lo1 + a1) & g.m1) << g.s1) |
+                                     ((unsigned)((b.lo2 + a2) & g.m2) << g.l3) | col;
+                tmp[u] = ldi4(src, off);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads + tid;
-            if (e < nvol) box[e] = tmp[u];
+        for (int u = 0; u < kSegBatch; ++u) {
+            const int row = r + u * rpp;
+            if (row < nrows) {
+                int a2;
+                const int a1 = quot(row, b.e2, inv_e2, a2);
+                box4[__umul24((unsigned)a1, (unsigned)(b.pp >> 2)) +
+                     __umul24((unsigned)a2, (unsigned)b.ng) + j] = tmp[u];
+            }
         }
     }
 }
 
 // Tricubic value from the staged box at stencil origin q (grid units) with
-// fractional offsets given by the displacement d.
+// fractional offsets given by the displacement d: sum_a w1_a sum_c w2_c
+// sum_k w3_k f(q + (a, c, k)).
 __device__ __forceinline__ float interp_box(const float* box, const Box& b, const int q[3],
                                             const float d[3]) {
     float w1[4], w2[4], w3[4];
     cubic_basis(d[0] - floorf(d[0]), w1);
     cubic_basis(d[1] - floorf(d[1]), w2);
     cubic_basis(d[2] - floorf(d[2]), w3);
-    const int r1 = q[0] - b.lo1, r2 = q[1] - b.lo2, r3 = q[2] - b.lo3;
+    const int plane = b.pp;
+    const float* p0 = box + (q[0] - b.lo1) * b.pp + (q[1] - b.lo2) * b.p3 + (q[2] - b.cb);
     float acc = 0.f;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
+        float sa = 0.f;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const float* p = box + ((r1 + a) * b.e2 + (r2 + c)) * b.e3 + r3;
+            const float* p = p0 + a * plane + c * b.p3;
             float t = w3[0] * p[0];
             t = fmaf(w3[1], p[1], t);
             t = fmaf(w3[2], p[2], t);
             t = fmaf(w3[3], p[3], t);
-            acc = fmaf(w1[a] * w2[c], t, acc);
+            sa = c == 0 ? w2[0] * t : fmaf(w2[c], t, sa);
         }
+        acc = a == 0 ? w1[0] * sa : fmaf(w1[a], sa, acc);
     }
     return acc;
 }
@@ -353,11 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restric
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
         int i1, i2, i3;
-        long long idx;
+        unsigned idx;
         if (brick_voxel(g, br, bp, k, i1, i2, i3, idx)) {
-            const int q1 = i1 + (int)floorf(d[idx]) - 1;
-            const int q2 = i2 + (int)floorf(d[n + idx]) - 1;
-            const int q3 = i3 + (int)floorf(d[2 * n + idx]) - 1;
+            const int q1 = i1 + (int)floorf(ldi(d, idx)) - 1;
+            const int q2 = i2 + (int)floorf(ldi(d + n, idx)) - 1;
+            const int q3 = i3 + (int)floorf(ldi(d + 2 * n, idx)) - 1;
             mn1 = min(mn1, q1); mx1 = max(mx1, q1);
             mn2 = min(mn2, q2); mx2 = max(mx2, q2);
             mn3 = min(mn3, q3); mx3 = max(mx3, q3);
@@ -373,43 +447,29 @@ __global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restric
 
 // Single-field gather u = src(x + d(x)) with epilogue; `table` holds the
 // per-brick boxes of d (NULL: reduce them here).
-// Mixed precision: incremental-state step whose grid source f^{j+1} is
-// stored in half (float arithmetic, float gathered field and output).
-struct EpiIncStateMixed {    // out = sign (u + coef f)
-    const __half* f;
-    float* out;
-    float coef, sign;
-    struct Pre { float f; };
-    __device__ Pre load(long long i) const { return Pre{__half2float(f[i])}; }
-    __device__ void store(long long i, float u, const Pre& p) const {
-        out[i] = sign * (u + coef * p.f);
-    }
-};
-
-template <class Epi, typename T = float>
+template <class Epi>
 __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
-    const T* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
+    const float* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
     Epi epi, G3 g, Brick br, long long n) {
-    __shared__ float box[kBoxCap];
+    __shared__ __align__(16) float box[kBoxCap];
     __shared__ int red[kThreads / 64][6];
     const BrickPos bp = brick_pos(br);
     float dd[kVox][3];
     int q[kVox][3];
     int ii[kVox][3];
-    long long gi[kVox];
+    unsigned gi[kVox];
+    bool on[kVox];
     typename Epi::Pre pre[kVox];
     int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
     int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
-        gi[k] = -1;
-        long long idx;
-        if (brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], idx)) {
-            gi[k] = idx;
-            dd[k][0] = d[idx];
-            dd[k][1] = d[n + idx];
-            dd[k][2] = d[2 * n + idx];
-            pre[k] = epi.load(idx);
+        on[k] = brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
+        if (on[k]) {
+            dd[k][0] = ldi(d, gi[k]);
+            dd[k][1] = ldi(d + n, gi[k]);
+            dd[k][2] = ldi(d + 2 * n, gi[k]);
+            pre[k] = epi.load(gi[k]);
         }
     }
     Box b;
@@ -417,12 +477,12 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
         const int* t = table + 6 * bp.id;
         b.lo1 = t[0]; b.lo2 = t[1]; b.lo3 = t[2];
         b.e1 = t[3]; b.e2 = t[4]; b.e3 = t[5];
-        b.vol = (long long)b.e1 * b.e2 * b.e3;
+        box_layout(b);
         if (b.vol <= kBoxCap) stage_box(box, src, g, b);
     }
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
-        if (gi[k] < 0) continue;
+        if (!on[k]) continue;
 #pragma unroll
         for (int a = 0; a < 3; ++a) q[k][a] = ii[k][a] + (int)floorf(dd[k][a]) - 1;
         mn1 = min(mn1, q[k][0]); mx1 = max(mx1, q[k][0]);
@@ -437,11 +497,11 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kVox; ++k)
-            if (gi[k] >= 0) epi.store(gi[k], interp_box(box, b, q[k], dd[k]), pre[k]);
+            if (on[k]) epi.store(gi[k], interp_box(box, b, q[k], dd[k]), pre[k]);
     } else {
 #pragma unroll
         for (int k = 0; k < kVox; ++k)
-            if (gi[k] >= 0)
+            if (on[k])
                 epi.store(gi[k], interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]),
                           pre[k]);
     }
@@ -451,26 +511,23 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
 //   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
 // c_a = h_t / h_a converts velocity to voxels per step. For each direction
 // the three components of v are staged through the brick's box in turn.
-__global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(const float* __restrict__ v,
-                                                            float* __restrict__ dp,
-                                                            float* __restrict__ dm, G3 g,
-                                                            Brick br, long long n, float c1,
-                                                            float c2, float c3) {
-    __shared__ float box[kBoxCapBT];
+__global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
+    const float* __restrict__ v, float* __restrict__ dp, float* __restrict__ dm, G3 g, Brick br,
+    long long n, float c1, float c2, float c3) {
+    __shared__ __align__(16) float box[kBoxCapBT];
     __shared__ int red[kThreads / 64][6];
     const BrickPos bp = brick_pos(br);
     const float c[3] = {c1, c2, c3};
     float vx[kVox][3];
     int ii[kVox][3];
-    long long gi[kVox];
+    unsigned gi[kVox];
+    bool on[kVox];
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
-        gi[k] = -1;
-        long long idx;
-        if (brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], idx)) {
-            gi[k] = idx;
+        on[k] = brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
+        if (on[k]) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) vx[k][a] = v[a * n + idx];
+            for (int a = 0; a < 3; ++a) vx[k][a] = ldi(v + a * n, gi[k]);
         }
     }
 #pragma unroll
@@ -482,7 +539,7 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(con
         int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
 #pragma unroll
         for (int k = 0; k < kVox; ++k) {
-            if (gi[k] < 0) continue;
+            if (!on[k]) continue;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 dd[k][a] = sg * c[a] * vx[k][a];
@@ -498,37 +555,37 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(con
         float u[kVox][3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const float* src = v + (long long)f * n;
+            const float* src = v + f * n;
             if (fits) {
                 if (f > 0) __syncthreads();   // previous component's reads are done
                 stage_box(box, src, g, b);
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < kVox; ++k)
-                    if (gi[k] >= 0) u[k][f] = interp_box(box, b, q[k], dd[k]);
+                    if (on[k]) u[k][f] = interp_box(box, b, q[k], dd[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < kVox; ++k)
-                    if (gi[k] >= 0)
+                    if (on[k])
                         u[k][f] = interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]);
             }
         }
         float* out = dir == 0 ? dp : dm;
 #pragma unroll
         for (int k = 0; k < kVox; ++k) {
-            if (gi[k] < 0) continue;
+            if (!on[k]) continue;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                out[a * n + gi[k]] = sg * 0.5f * c[a] * (vx[k][a] + u[k][a]);
+                sti(out + a * n, gi[k], sg * 0.5f * c[a] * (vx[k][a] + u[k][a]));
         }
     }
 }
 
-template <class Epi, typename T>
-int launch_gather_lds(const Geo& g, const T* src, const float* disp, const int* table,
+template <class Epi>
+int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
                       const Epi& epi, hipStream_t s) {
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL((k_gather_lds<Epi, T>), dim3(br.nbricks), dim3(kThreads), 0, s, src, disp,
+    hipLaunchKernelGGL((k_gather_lds<Epi>), dim3(br.nbricks), dim3(kThreads), 0, s, src, disp,
                        table, epi, make_g3(g), br, g.n);
     CL_LAUNCH_CHECK();
     return 0;
