@@ -71,6 +71,10 @@ typedef struct claire_opts {
                                    (Section 2.6). NULL: the single alpha argument. */
     int n_levels;               /* length of alpha_levels */
     int compute_det;            /* 1: report det F(1) statistics at the end */
+    int tol_from_zero;          /* 1: g_0 of the gtol test is the gradient at v = 0 (one
+                                   extra state + adjoint solve per level) instead of the
+                                   gradient at the initial guess, so a warm-started solve
+                                   stops at the same gradient norm as one from v = 0 */
 } claire_opts;
 
 /* Statistics of a solve (row labels of the paper's result tables). */
@@ -83,7 +87,8 @@ typedef struct claire_stats {
     double J0;                  /* objective at the initial velocity, first level */
     double J;                   /* objective at exit */
     double rel_mismatch;        /* ||m(1) - m1||_2 / ||m0 - m1||_2 at exit */
-    double rel_grad;            /* ||g||_inf / ||g_0||_inf at exit, last level */
+    double rel_grad;            /* ||g||_inf / ||g_0||_inf at exit, last level (g_0 as
+                                   chosen by tol_from_zero) */
     double det_min, det_mean, det_max; /* det F(1), when compute_det = 1 */
     long long det_nonpositive;  /* voxels with det F(1) <= 0 */
     double seconds;             /* wall time of the solve (host clock) */

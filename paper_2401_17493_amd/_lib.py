@@ -1,4 +1,5 @@
-"""ctypes view of ``libclaire_gfx950.so`` (the C ABI declared in include/claire.h).
+"""ctypes view of ``libclaire_gfx950.so`` (the C ABI declared in include/claire.h and
+include/claire_net.h).
 
 Loading fails loudly when the library has not been built: there is no
 fallback implementation.
@@ -32,6 +33,7 @@ class ClaireOpts(ctypes.Structure):
         ("alpha_levels", c_double_p),
         ("n_levels", c_int),
         ("compute_det", c_int),
+        ("tol_from_zero", c_int),
     ]
 
 
@@ -86,6 +88,27 @@ SIGNATURES = {
     "claire_solve": (c_int, [c_void_p, c_void_p, c_int_p, c_double, c_int,
                              ctypes.POINTER(ClaireOpts), c_void_p, ctypes.POINTER(ClaireStats),
                              c_void_p]),
+    # learned warm start (include/claire_net.h)
+    "claire_net_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int_p, c_int,
+                                  ctypes.c_ulonglong, c_void_p]),
+    "claire_net_destroy": (c_int, [c_void_p]),
+    "claire_net_param_count": (ctypes.c_longlong, [c_void_p]),
+    "claire_net_set_params": (c_int, [c_void_p, c_void_p]),
+    "claire_net_get_params": (c_int, [c_void_p, c_void_p]),
+    "claire_net_get_grads": (c_int, [c_void_p, c_void_p]),
+    "claire_net_set_grads": (c_int, [c_void_p, c_void_p]),
+    "claire_net_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "claire_net_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double_p,
+                                     c_void_p]),
+    "claire_net_adam_step": (c_int, [c_void_p, c_double]),
+    "claire_net_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double,
+                                      c_double_p]),
+    "claire_net_warm_start": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "claire_resample": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_void_p]),
+    "claire_conv3d": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int,
+                              c_void_p, c_void_p]),
+    "claire_conv3d_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                       c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None

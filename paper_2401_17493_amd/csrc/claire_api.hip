@@ -458,12 +458,20 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
     double g0 = 0.0;
     for (size_t li = 0; li < levels.size() && !stop_all; ++li) {
         c->alpha = levels[li];
+        if (o.tol_from_zero) {
+            // reference gradient at v = 0 for the stopping test
+            CL_TRY(launch_fill(c->v, 0.f, n3, s));
+            c->state_valid = false;
+            CL_TRY(run_setup(c));
+            S.pde_solves += 2;
+            g0 = c->gnorm;
+        }
         CL_TRY(copy_d2d(c->v, v_io, n3, s));
         c->state_valid = false;
         CL_TRY(run_setup(c));
         S.pde_solves += 2;
         if (li == 0) S.J0 = c->J;
-        g0 = c->gnorm;
+        if (!o.tol_from_zero) g0 = c->gnorm;
         int k = 0;
         while (true) {
             if (c->gnorm <= o.gtol * g0 || c->gnorm <= o.gabs) break;
@@ -577,6 +585,7 @@ void claire_opts_default(claire_opts* o) {
     o->alpha_levels = nullptr;
     o->n_levels = 0;
     o->compute_det = 0;
+    o->tol_from_zero = 0;
 }
 
 const char* claire_last_error(void) { return g_err; }

@@ -1,0 +1,1244 @@
+// Learned warm start: a periodic 3D convolutional encoder--decoder trained
+// and evaluated on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Every 3x3x3 convolution is an implicit GEMM: rows are voxels (M), columns
+// output channels (N), the reduction runs over k = t cin + ci (27 taps times
+// the input channels, padded to a multiple of 32). Operands are bfloat16,
+// accumulation float32. The same kernel runs the backward-data pass with the
+// weights flipped in t and transposed in (co, ci); the weight gradient is a
+// second GEMM whose reduction runs over voxels, split across workgroups into
+// deterministic partial sums. Activations are channels last, batch first.
+//
+// MFMA 16x16x32 operand layout (lane l, g = l / 16): A row l % 16 holds
+// k = 8 g .. 8 g + 7; B column l % 16 holds the same k; the 4 results of a
+// lane are rows 4 g + r, column l % 16.
+
+#include "internal.h"
+
+#include "claire_net.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace claire {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLeak = 0.1f;
+constexpr int kInC = 8;        // input feature channels
+constexpr int kOutC = 3;       // velocity components
+constexpr int kLayers = 15;
+
+__device__ __forceinline__ float slope(bf16 y) { return (float)y > 0.f ? 1.f : kLeak; }
+
+// Voxel index of (b, j1, j2, j3) on a 2^l grid.
+__device__ __forceinline__ long long vox(int b, int j1, int j2, int j3, int l) {
+    return ((long long)b << (3 * l)) | ((long long)j1 << (2 * l)) | ((long long)j2 << l) | j3;
+}
+
+// Convolution input: channels [0, ca) from `a` (stored at half resolution
+// and read nearest-upsampled when a_up), channels [ca, ca + cb) from `b`.
+struct ConvIn {
+    const bf16* a;
+    int ca, a_up;
+    const bf16* b;
+    int cb;
+};
+
+// Element (voxel (bb, j1, j2, j3) at level l, channel ci) of the input view.
+__device__ __forceinline__ const bf16* in_ptr(const ConvIn& in, int l, int bb, int j1, int j2,
+                                              int j3, int ci) {
+    if (ci < in.ca) {
+        if (in.a_up) return in.a + vox(bb, j1 >> 1, j2 >> 1, j3 >> 1, l - 1) * in.ca + ci;
+        return in.a + vox(bb, j1, j2, j3, l) * in.ca + ci;
+    }
+    return in.b + vox(bb, j1, j2, j3, l) * in.cb + (ci - in.ca);
+}
+
+enum ConvEpi {
+    EPI_ACT = 0,        // y16 = bf16(leaky(acc + bias))
+    EPI_LINEAR = 1,     // y32 = acc + bias
+    EPI_DGRAD_ACT = 2,  // y16 = bf16(acc * slope(yprev))
+    EPI_DGRAD_RAW = 3,  // y32 (channels < csplit) / y32b (the rest) = acc
+    EPI_ACT32 = 4,      // y32 = leaky(acc + bias)
+};
+
+struct ConvOut {
+    bf16* y16;
+    float* y32;
+    float* y32b;
+    int csplit;
+    const bf16* yprev;
+    const float* bias;
+};
+
+// Implicit-GEMM convolution: each wave computes 16 voxels x 64 output
+// channels (4 MFMA tiles), a workgroup 64 voxels; grid (ceil(mtot/64),
+// ceil(nrows/64)). wt: [nrows][kpad] bfloat16, zero beyond cout rows and
+// 27 cin columns; cin = ca + cb and both multiples of 8.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv(ConvIn in, const bf16* __restrict__ wt, int kpad,
+                                              int nrows, int cout, int l, int mtot,
+                                              ConvOut out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int mbase = (blockIdx.x * 4 + wave) * 16;
+    const int n0 = blockIdx.y * 64;
+    const int cin = in.ca + in.cb;
+    const int m = mbase + li;
+    const bool mval = m < mtot;
+    const int i3 = m & mask, i2 = (m >> l) & mask, i1 = (m >> (2 * l)) & mask, bb = m >> (3 * l);
+    int t = 0, ci = 8 * g;
+    while (ci >= cin) { ci -= cin; ++t; }
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < kpad; kc += 32) {
+        bf16x8 av = {};
+        if (mval && t < 27) {
+            const int o1 = t / 9 - 1, o2 = (t / 3) % 3 - 1, o3 = t % 3 - 1;
+            av = *reinterpret_cast<const bf16x8*>(
+                in_ptr(in, l, bb, (i1 + o1) & mask, (i2 + o2) & mask, (i3 + o3) & mask, ci));
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int r0 = n0 + nt * 16;
+            if (r0 < nrows) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(
+                    wt + (size_t)(r0 + li) * kpad + kc + 8 * g);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+            }
+        }
+        ci += 32;
+        while (ci >= cin) { ci -= cin; ++t; }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int co = n0 + nt * 16 + li;
+        if (n0 + nt * 16 >= nrows || co >= cout) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mo = mbase + 4 * g + r;
+            if (mo >= mtot) continue;
+            const float a = acc[nt][r];
+            if (EPI == EPI_ACT) {
+                const float z = a + (out.bias ? out.bias[co] : 0.f);
+                out.y16[(size_t)mo * cout + co] = (bf16)(z > 0.f ? z : kLeak * z);
+            } else if (EPI == EPI_LINEAR) {
+                out.y32[(size_t)mo * cout + co] = a + (out.bias ? out.bias[co] : 0.f);
+            } else if (EPI == EPI_ACT32) {
+                const float z = a + (out.bias ? out.bias[co] : 0.f);
+                out.y32[(size_t)mo * cout + co] = z > 0.f ? z : kLeak * z;
+            } else if (EPI == EPI_DGRAD_ACT) {
+                out.y16[(size_t)mo * cout + co] = (bf16)(a * slope(out.yprev[(size_t)mo * cout + co]));
+            } else {
+                if (co < out.csplit) out.y32[(size_t)mo * out.csplit + co] = a;
+                else out.y32b[(size_t)mo * (cout - out.csplit) + (co - out.csplit)] = a;
+            }
+        }
+    }
+}
+
+// Weight-gradient GEMM: partial[s][row][k] = sum over the voxels of split s
+// of dz[m][row] x(m + o_t)[ci], k = t cin + ci. A workgroup covers 16 rows x
+// 256 columns (64 per wave, 4 MFMA tiles), grid (rowtiles * ktiles, splits);
+// voxels advance 32 per MFMA. chunk is a multiple of 32.
+__global__ __launch_bounds__(256) void k_wgrad(ConvIn in, const bf16* __restrict__ dz, int cdz,
+                                               int l, int mtot, int kpad, int ktiles,
+                                               int chunk, float* __restrict__ partial,
+                                               int nrows) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int row0 = (blockIdx.x / ktiles) * 16;
+    const int kcol0 = (blockIdx.x % ktiles) * 256 + wave * 64;
+    const int split = blockIdx.y;
+    const int mstart = split * chunk;
+    const int mend = min(mtot, mstart + chunk);
+    const int cin = in.ca + in.cb;
+    int tt[4], cc[4];
+    bool kv[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int k = kcol0 + nt * 16 + li;
+        kv[nt] = k < 27 * cin;
+        tt[nt] = k / cin;
+        cc[nt] = k - tt[nt] * cin;
+    }
+    const int co = row0 + li;
+    const bool cov = co < cdz;
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int mc = mstart; mc < mend; mc += 32) {
+        bf16x8 av = {};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int mm = mc + 8 * g + j;
+            if (cov && mm < mend) av[j] = dz[(size_t)mm * cdz + co];
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (kcol0 + nt * 16 >= kpad) continue;
+            bf16x8 bv = {};
+            if (kv[nt]) {
+                const int t = tt[nt];
+                const int o1 = t / 9 - 1, o2 = (t / 3) % 3 - 1, o3 = t % 3 - 1;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int mm = mc + 8 * g + j;
+                    if (mm < mend) {
+                        const int i3 = mm & mask, i2 = (mm >> l) & mask, i1 = (mm >> (2 * l)) & mask;
+                        const int bb = mm >> (3 * l);
+                        bv[j] = *in_ptr(in, l, bb, (i1 + o1) & mask, (i2 + o2) & mask,
+                                        (i3 + o3) & mask, cc[nt]);
+                    }
+                }
+            }
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int k = kcol0 + nt * 16 + li;
+        if (kcol0 + nt * 16 >= kpad) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            partial[((size_t)split * nrows + row0 + 4 * g + r) * kpad + k] = acc[nt][r];
+    }
+}
+
+// pb[s][c] = sum over the voxels of split s of dz[m][c]
+__global__ __launch_bounds__(256) void k_bias_partial(const bf16* __restrict__ dz, int cdz,
+                                                      int mtot, int chunk,
+                                                      float* __restrict__ pb) {
+    const int s = blockIdx.x;
+    const int mstart = s * chunk, mend = min(mtot, mstart + chunk);
+    for (int c = threadIdx.x; c < cdz; c += 256) {
+        float acc = 0.f;
+        for (int m = mstart; m < mend; ++m) acc += (float)dz[(size_t)m * cdz + c];
+        pb[(size_t)s * cdz + c] = acc;
+    }
+}
+
+// gw[co][k] = sum_s partial[s][co][k] (co < cout, k < ktot), gb[co] = sum_s pb[s][co]
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
+                                                      const float* __restrict__ pb, int splits,
+                                                      int nrows, int kpad, int cout, int ktot,
+                                                      int cdz, float* __restrict__ gw,
+                                                      float* __restrict__ gb) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long nw = (long long)cout * ktot;
+    if (idx < nw) {
+        const int co = (int)(idx / ktot), k = (int)(idx - (long long)co * ktot);
+        double acc = 0.0;
+        for (int s = 0; s < splits; ++s) acc += partial[((size_t)s * nrows + co) * kpad + k];
+        gw[idx] = (float)acc;
+    } else if (idx < nw + cout) {
+        const int co = (int)(idx - nw);
+        double acc = 0.0;
+        for (int s = 0; s < splits; ++s) acc += pb[(size_t)s * cdz + co];
+        gb[co] = (float)acc;
+    }
+}
+
+// x[m] = (m0, m1, m1 - m0, 0, 0, 0, 0, 0) in bfloat16; images [batch][R^3]
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ m0,
+                                                  const float* __restrict__ m1, int mtot,
+                                                  bf16* __restrict__ x) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= mtot) return;
+    const float a = m0[m], b = m1[m];
+    bf16x8 v = {};
+    v[0] = (bf16)a;
+    v[1] = (bf16)b;
+    v[2] = (bf16)(b - a);
+    *reinterpret_cast<bf16x8*>(x + (size_t)m * kInC) = v;
+}
+
+// 2x2x2 mean (float sum in a fixed order), output level lo
+__global__ __launch_bounds__(256) void k_pool(const bf16* __restrict__ x, int C, int lo,
+                                              int mtot_out, bf16* __restrict__ y) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)mtot_out * C) return;
+    const int m = (int)(idx / C), c = (int)(idx - (long long)m * C);
+    const int mask = (1 << lo) - 1;
+    const int i3 = m & mask, i2 = (m >> lo) & mask, i1 = (m >> (2 * lo)) & mask, bb = m >> (3 * lo);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b2 = 0; b2 < 2; ++b2)
+            for (int d = 0; d < 2; ++d)
+                s += (float)x[vox(bb, 2 * i1 + a, 2 * i2 + b2, 2 * i3 + d, lo + 1) * C + c];
+    y[idx] = (bf16)(0.125f * s);
+}
+
+// dz (coarse, level lc) = bf16(slope(y) * sum of the 8 fine children of dxa)
+__global__ __launch_bounds__(256) void k_up_adjoint_slope(const float* __restrict__ dxa,
+                                                          const bf16* __restrict__ y, int C,
+                                                          int lc, int mtot_c,
+                                                          bf16* __restrict__ dz) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)mtot_c * C) return;
+    const int m = (int)(idx / C), c = (int)(idx - (long long)m * C);
+    const int mask = (1 << lc) - 1;
+    const int i3 = m & mask, i2 = (m >> lc) & mask, i1 = (m >> (2 * lc)) & mask, bb = m >> (3 * lc);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b2 = 0; b2 < 2; ++b2)
+            for (int d = 0; d < 2; ++d)
+                s += dxa[vox(bb, 2 * i1 + a, 2 * i2 + b2, 2 * i3 + d, lc + 1) * C + c];
+    dz[idx] = (bf16)(s * slope(y[idx]));
+}
+
+// dz (fine, level lf) = bf16(slope(y) (dxp(parent) / 8 + dskip))
+__global__ __launch_bounds__(256) void k_pool_adjoint_slope(const float* __restrict__ dxp,
+                                                            const float* __restrict__ dskip,
+                                                            const bf16* __restrict__ y, int C,
+                                                            int lf, int mtot_f,
+                                                            bf16* __restrict__ dz) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)mtot_f * C) return;
+    const int m = (int)(idx / C), c = (int)(idx - (long long)m * C);
+    const int mask = (1 << lf) - 1;
+    const int i3 = m & mask, i2 = (m >> lf) & mask, i1 = (m >> (2 * lf)) & mask, bb = m >> (3 * lf);
+    const float s = dxp[vox(bb, i1 >> 1, i2 >> 1, i3 >> 1, lf - 1) * C + c] / 8.f + dskip[idx];
+    dz[idx] = (bf16)(s * slope(y[idx]));
+}
+
+// Mean squared error against target [batch][3][R^3]: dz = bf16(scale (v - t))
+// in channels 0..2 of [m][8] (zero elsewhere), per-block sums of squares.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ v,
+                                             const float* __restrict__ target, int l, int mtot,
+                                             float scale, bf16* __restrict__ dz,
+                                             double* __restrict__ partial) {
+    __shared__ double sh[4];
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    double ss = 0.0;
+    if (m < mtot) {
+        const int r3 = 3 * l;
+        const int b = m >> r3, i = m & ((1 << r3) - 1);
+        bf16x8 o = {};
+#pragma unroll
+        for (int c = 0; c < kOutC; ++c) {
+            const float d = v[(size_t)m * kOutC + c] - target[(((size_t)b * kOutC + c) << r3) + i];
+            ss += (double)d * d;
+            o[c] = (bf16)(scale * d);
+        }
+        *reinterpret_cast<bf16x8*>(dz + (size_t)m * 8) = o;
+    }
+    const double t = block_sum_256(ss, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// [m][3] -> [batch][3][R^3]
+__global__ __launch_bounds__(256) void k_out_transpose(const float* __restrict__ v, int l,
+                                                       int mtot, float* __restrict__ out) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= mtot) return;
+    const int r3 = 3 * l;
+    const int b = m >> r3, i = m & ((1 << r3) - 1);
+#pragma unroll
+    for (int c = 0; c < kOutC; ++c) out[(((size_t)b * kOutC + c) << r3) + i] = v[(size_t)m * kOutC + c];
+}
+
+// Adam step (update != 0) and/or repacking of one layer's parameters into
+// the bfloat16 GEMM operands: wt[co][k] (k = t cin + ci) and the
+// backward-data operand wtT[ci][(26 - t) coutE + co].
+__global__ __launch_bounds__(256) void k_adam_pack(float* __restrict__ p, float* __restrict__ mo,
+                                                   float* __restrict__ ve,
+                                                   const float* __restrict__ g, int nw, int nb,
+                                                   int update, float lr, float b1, float b2,
+                                                   float c1, float c2, float eps,
+                                                   bf16* __restrict__ wt, int kpad, int ktot,
+                                                   bf16* __restrict__ wtT, int kpadT, int cin,
+                                                   int coutE) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nw + nb) return;
+    float w = p[idx];
+    if (update) {
+        const float gi = g[idx];
+        const float m1 = b1 * mo[idx] + (1.f - b1) * gi;
+        const float v1 = b2 * ve[idx] + (1.f - b2) * gi * gi;
+        mo[idx] = m1;
+        ve[idx] = v1;
+        w -= lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+        p[idx] = w;
+    }
+    if (idx < nw) {
+        const int co = idx / ktot, k = idx - co * ktot;
+        const int t = k / cin, ci = k - t * cin;
+        const bf16 h = (bf16)w;
+        wt[(size_t)co * kpad + k] = h;
+        wtT[(size_t)ci * kpadT + (26 - t) * coutE + co] = h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero16(bf16* __restrict__ x, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = (bf16)0.f;
+}
+
+// float32 -> bfloat16 -> float32 (rounding of a conv operand for claire_conv3d)
+__global__ __launch_bounds__(256) void k_round16(const float* __restrict__ x, long long n,
+                                                 bf16* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = (bf16)x[i];
+}
+
+// ------------------------------------------------------------ grid transfer
+// dst (2^(l-1))^3 = 2x2x2 block means of src (2^l)^3, per component
+__global__ __launch_bounds__(256) void k_restrict2(const float* __restrict__ src, int l,
+                                                   long long ndst, int ncomp,
+                                                   float* __restrict__ dst) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= ndst * ncomp) return;
+    const int c = (int)(idx / ndst);
+    const long long m = idx - (long long)c * ndst;
+    const int lo = l - 1, mask = (1 << lo) - 1;
+    const int i3 = (int)(m & mask), i2 = (int)((m >> lo) & mask), i1 = (int)(m >> (2 * lo));
+    const float* s = src + ((long long)c << (3 * l));
+    float acc = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d)
+                acc += s[vox(0, 2 * i1 + a, 2 * i2 + b, 2 * i3 + d, l)];
+    dst[idx] = 0.125f * acc;
+}
+
+// Refine axis `ax` (0: x1, 1: x2, 2: x3) of fields with extents e[3] by 2:
+// even points copy, midpoints (-f(i-1) + 9 f(i) + 9 f(i+1) - f(i+2)) / 16.
+__global__ __launch_bounds__(256) void k_prolong_axis(const float* __restrict__ src, int e1,
+                                                      int e2, int e3, int ax, int ncomp,
+                                                      float* __restrict__ dst) {
+    const int d1 = ax == 0 ? 2 * e1 : e1, d2 = ax == 1 ? 2 * e2 : e2, d3 = ax == 2 ? 2 * e3 : e3;
+    const long long nd = (long long)d1 * d2 * d3;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nd * ncomp) return;
+    const int c = (int)(idx / nd);
+    const long long m = idx - (long long)c * nd;
+    int j3 = (int)(m % d3);
+    int j2 = (int)((m / d3) % d2);
+    int j1 = (int)(m / ((long long)d3 * d2));
+    const float* s = src + (long long)c * e1 * e2 * e3;
+    int* jj = ax == 0 ? &j1 : (ax == 1 ? &j2 : &j3);
+    const int ea = ax == 0 ? e1 : (ax == 1 ? e2 : e3);
+    const int i = *jj >> 1;
+    auto at = [&](int q) {
+        *jj = ((q % ea) + ea) % ea;
+        return s[((long long)j1 * e2 + j2) * e3 + j3];
+    };
+    float r;
+    if ((ax == 0 ? j1 : (ax == 1 ? j2 : j3)) & 1) {
+        const float fm1 = at(i - 1), f0 = at(i), fp1 = at(i + 1), fp2 = at(i + 2);
+        r = (-fm1 + 9.f * f0 + 9.f * fp1 - fp2) / 16.f;
+    } else {
+        r = at(i);
+    }
+    dst[idx] = r;
+}
+
+unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+int lg2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+
+template <typename T>
+int dalloc(T** p, long long count) {
+    CL_HIP(hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)(count > 0 ? count : 1)));
+    return 0;
+}
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+int zero16(bf16* x, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero16, dim3(nblk(n)), dim3(256), 0, s, x, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int roundup(int v, int q) { return (v + q - 1) / q * q; }
+
+// Resample [ncomp][n_src^3] -> [ncomp][n_dst^3] with two scratch buffers of
+// ncomp * max(n)^3 floats.
+int resample(const float* src, int ns, float* dst, int nd, int ncomp, float* t0, float* t1,
+             hipStream_t s) {
+    const float* cur = src;
+    int n = ns;
+    float* bufs[2] = {t0, t1};
+    int which = 0;
+    auto target = [&](bool last) { return last ? dst : bufs[which]; };
+    if (n == nd) {
+        CL_HIP(hipMemcpyAsync(dst, src, sizeof(float) * (size_t)ncomp * nd * nd * nd,
+                              hipMemcpyDeviceToDevice, s));
+        return 0;
+    }
+    while (n > nd) {
+        const bool last = n / 2 == nd;
+        float* out = target(last);
+        const long long ndst = (long long)(n / 2) * (n / 2) * (n / 2);
+        hipLaunchKernelGGL(k_restrict2, dim3(nblk(ndst * ncomp)), dim3(256), 0, s, cur, lg2(n),
+                           ndst, ncomp, out);
+        CL_LAUNCH_CHECK();
+        cur = out;
+        which ^= 1;
+        n /= 2;
+    }
+    while (n < nd) {
+        int e[3] = {n, n, n};
+        for (int ax = 0; ax < 3; ++ax) {
+            const bool last = (2 * n == nd) && ax == 2;
+            float* out = target(last);
+            const long long ndst = 2LL * e[0] * e[1] * e[2];
+            hipLaunchKernelGGL(k_prolong_axis, dim3(nblk(ndst * ncomp)), dim3(256), 0, s, cur,
+                               e[0], e[1], e[2], ax, ncomp, out);
+            CL_LAUNCH_CHECK();
+            e[ax] *= 2;
+            cur = out;
+            which ^= 1;
+        }
+        n *= 2;
+    }
+    return 0;
+}
+
+uint64_t splitmix64(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+// One convolution layer's geometry and GEMM operands.
+struct NetLayer {
+    int cin, cout, coutE;   // coutE: cout rounded up to 8 (channels of its dz)
+    int ktot, kpad, nrows;  // forward GEMM: [nrows][kpad]
+    int kpadT, nrowsT;      // backward-data GEMM: [nrowsT][kpadT]
+    long long off;          // parameter offset
+    bf16* wt = nullptr;
+    bf16* wtT = nullptr;
+};
+
+}  // namespace claire
+
+using namespace claire;
+
+struct claire_net {
+    int R = 0, l = 0, c[4] = {0, 0, 0, 0}, max_batch = 0;
+    hipStream_t s = nullptr;
+    NetLayer L[kLayers];
+    long long nparam = 0;
+    float *p = nullptr, *mo = nullptr, *ve = nullptr, *g = nullptr;
+    int adam_t = 0;
+    // activations (bfloat16, channels last)
+    bf16 *x0 = nullptr, *e1a = nullptr, *s1 = nullptr, *p1 = nullptr, *e2a = nullptr,
+         *s2 = nullptr, *p2 = nullptr, *e3a = nullptr, *s3 = nullptr, *p3 = nullptr,
+         *ba = nullptr, *bt = nullptr, *d3a = nullptr, *d3 = nullptr, *d2a = nullptr,
+         *d2 = nullptr, *d1a = nullptr, *d1 = nullptr;
+    float* vout = nullptr;   // [m][3]
+    // backward
+    bf16* dzh = nullptr;                    // [m1][8]
+    bf16 *dzA[4] = {}, *dzB[4] = {};        // per level ping-pong, [m_l][max(c_l, 8)]
+    float *dxA = nullptr, *dxp = nullptr;
+    float *dskip[3] = {};
+    float *partial = nullptr, *pb = nullptr;
+    long long partial_cap = 0, pb_cap = 0;
+    Reducer red;
+    bool have_grads = false;
+    // warm-start scratch, grown on demand: restricted images, velocity at
+    // the working resolution, two transfer buffers of 3 n^3 floats
+    float *ws_a = nullptr, *ws_b = nullptr, *ws_v = nullptr, *ws_t0 = nullptr, *ws_t1 = nullptr;
+    long long ws_cap = 0;
+};
+
+namespace claire {
+namespace {
+
+enum { ENC1A, ENC1B, ENC2A, ENC2B, ENC3A, ENC3B, BOTA, BOTB, DEC3A, DEC3B, DEC2A, DEC2B, DEC1A,
+       DEC1B, HEAD };
+
+long long vox_level(const claire_net* n, int level, int batch) {
+    const int lv = n->l - level;
+    return (long long)batch << (3 * lv);
+}
+
+// splits of the voxel reduction in the weight gradient and the chunk size
+void wgrad_split(long long mtot, int& splits, int& chunk) {
+    long long sp = (mtot + 511) / 512;
+    if (sp > 1024) sp = 1024;
+    if (sp < 1) sp = 1;
+    long long ch = (mtot + sp - 1) / sp;
+    ch = (ch + 31) / 32 * 32;
+    splits = (int)((mtot + ch - 1) / ch);
+    chunk = (int)ch;
+}
+
+int net_alloc(claire_net* n) {
+    const int c1 = n->c[0], c2 = n->c[1], c3 = n->c[2], c4 = n->c[3];
+    const int dims[kLayers][2] = {
+        {kInC, c1}, {c1, c1}, {c1, c2}, {c2, c2}, {c2, c3}, {c3, c3}, {c3, c4}, {c4, c4},
+        {c4 + c3, c3}, {c3, c3}, {c3 + c2, c2}, {c2, c2}, {c2 + c1, c1}, {c1, c1}, {c1, kOutC}};
+    long long off = 0;
+    for (int i = 0; i < kLayers; ++i) {
+        NetLayer& L = n->L[i];
+        L.cin = dims[i][0];
+        L.cout = dims[i][1];
+        L.coutE = roundup(L.cout, 8);
+        L.ktot = 27 * L.cin;
+        L.kpad = roundup(L.ktot, 32);
+        L.nrows = roundup(L.cout, 16);
+        L.kpadT = roundup(27 * L.coutE, 32);
+        L.nrowsT = roundup(L.cin, 16);
+        L.off = off;
+        off += (long long)L.cout * L.ktot + L.cout;
+        CL_TRY(dalloc(&L.wt, (long long)L.nrows * L.kpad));
+        CL_TRY(dalloc(&L.wtT, (long long)L.nrowsT * L.kpadT));
+        CL_TRY(zero16(L.wt, (long long)L.nrows * L.kpad, n->s));
+        CL_TRY(zero16(L.wtT, (long long)L.nrowsT * L.kpadT, n->s));
+    }
+    n->nparam = off;
+    CL_TRY(dalloc(&n->p, off));
+    CL_TRY(dalloc(&n->mo, off));
+    CL_TRY(dalloc(&n->ve, off));
+    CL_TRY(dalloc(&n->g, off));
+    const int B = n->max_batch;
+    const long long m1 = vox_level(n, 0, B), m2 = vox_level(n, 1, B), m3 = vox_level(n, 2, B),
+                    m4 = vox_level(n, 3, B);
+    CL_TRY(dalloc(&n->x0, m1 * kInC));
+    CL_TRY(dalloc(&n->e1a, m1 * c1));
+    CL_TRY(dalloc(&n->s1, m1 * c1));
+    CL_TRY(dalloc(&n->p1, m2 * c1));
+    CL_TRY(dalloc(&n->e2a, m2 * c2));
+    CL_TRY(dalloc(&n->s2, m2 * c2));
+    CL_TRY(dalloc(&n->p2, m3 * c2));
+    CL_TRY(dalloc(&n->e3a, m3 * c3));
+    CL_TRY(dalloc(&n->s3, m3 * c3));
+    CL_TRY(dalloc(&n->p3, m4 * c3));
+    CL_TRY(dalloc(&n->ba, m4 * c4));
+    CL_TRY(dalloc(&n->bt, m4 * c4));
+    CL_TRY(dalloc(&n->d3a, m3 * c3));
+    CL_TRY(dalloc(&n->d3, m3 * c3));
+    CL_TRY(dalloc(&n->d2a, m2 * c2));
+    CL_TRY(dalloc(&n->d2, m2 * c2));
+    CL_TRY(dalloc(&n->d1a, m1 * c1));
+    CL_TRY(dalloc(&n->d1, m1 * c1));
+    CL_TRY(dalloc(&n->vout, m1 * kOutC));
+    CL_TRY(dalloc(&n->dzh, m1 * 8));
+    const long long ml[4] = {m1, m2, m3, m4};
+    for (int k = 0; k < 4; ++k) {
+        const int ch = n->c[k] > 8 ? n->c[k] : 8;
+        CL_TRY(dalloc(&n->dzA[k], ml[k] * ch));
+        CL_TRY(dalloc(&n->dzB[k], ml[k] * ch));
+    }
+    long long dxa = m1 * c2;
+    if (m2 * c3 > dxa) dxa = m2 * c3;
+    if (m3 * c4 > dxa) dxa = m3 * c4;
+    CL_TRY(dalloc(&n->dxA, dxa));
+    long long dxp = m2 * c1;
+    if (m3 * c2 > dxp) dxp = m3 * c2;
+    if (m4 * c3 > dxp) dxp = m4 * c3;
+    CL_TRY(dalloc(&n->dxp, dxp));
+    CL_TRY(dalloc(&n->dskip[0], m1 * c1));
+    CL_TRY(dalloc(&n->dskip[1], m2 * c2));
+    CL_TRY(dalloc(&n->dskip[2], m3 * c3));
+    // weight-gradient partial sums: the largest splits x nrows x kpad over layers
+    const int lvl[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    for (int i = 0; i < kLayers; ++i) {
+        int splits, chunk;
+        wgrad_split(ml[lvl[i]], splits, chunk);
+        const long long need = (long long)splits * n->L[i].nrows * n->L[i].kpad;
+        if (need > n->partial_cap) n->partial_cap = need;
+        const long long needb = (long long)splits * n->L[i].coutE;
+        if (needb > n->pb_cap) n->pb_cap = needb;
+    }
+    CL_TRY(dalloc(&n->partial, n->partial_cap));
+    CL_TRY(dalloc(&n->pb, n->pb_cap));
+    CL_TRY(reducer_init(n->red, m1));
+    return 0;
+}
+
+void net_release(claire_net* n) {
+    for (auto& L : n->L) {
+        dfree(L.wt);
+        dfree(L.wtT);
+    }
+    void* bufs[] = {n->p, n->mo, n->ve, n->g, n->x0, n->e1a, n->s1, n->p1, n->e2a, n->s2,
+                    n->p2, n->e3a, n->s3, n->p3, n->ba, n->bt, n->d3a, n->d3, n->d2a, n->d2,
+                    n->d1a, n->d1, n->vout, n->dzh, n->dxA, n->dxp, n->partial, n->pb,
+                    n->dskip[0], n->dskip[1], n->dskip[2], n->ws_a, n->ws_b, n->ws_v,
+                    n->ws_t0, n->ws_t1};
+    for (void* b : bufs) dfree(b);
+    for (int k = 0; k < 4; ++k) {
+        dfree(n->dzA[k]);
+        dfree(n->dzB[k]);
+    }
+    reducer_free(n->red);
+}
+
+// Adam step (update) or repack of all layers' GEMM operands from n->p.
+int net_pack(claire_net* n, bool update, double lr) {
+    float c1 = 1.f, c2 = 1.f;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    if (update) {
+        ++n->adam_t;
+        c1 = (float)(1.0 - std::pow(0.9, n->adam_t));
+        c2 = (float)(1.0 - std::pow(0.999, n->adam_t));
+    }
+    for (auto& L : n->L) {
+        const int nw = L.cout * L.ktot, nb = L.cout;
+        hipLaunchKernelGGL(k_adam_pack, dim3(nblk(nw + nb)), dim3(256), 0, n->s, n->p + L.off,
+                           n->mo + L.off, n->ve + L.off, n->g + L.off, nw, nb, update ? 1 : 0,
+                           (float)lr, b1, b2, c1, c2, eps, L.wt, L.kpad, L.ktot, L.wtT, L.kpadT,
+                           L.cin, L.coutE);
+        CL_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+int reset_adam(claire_net* n) {
+    CL_TRY(launch_fill(n->mo, 0.f, n->nparam, n->s));
+    CL_TRY(launch_fill(n->ve, 0.f, n->nparam, n->s));
+    n->adam_t = 0;
+    n->have_grads = false;
+    return 0;
+}
+
+template <int EPI>
+int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
+         const ConvOut& out, hipStream_t s) {
+    const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64));
+    hipLaunchKernelGGL(k_conv<EPI>, grid, dim3(256), 0, s, in, wt, kpad, nrows, cout, l,
+                       (int)mtot, out);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+ConvIn one(const bf16* a, int ca) { return ConvIn{a, ca, 0, nullptr, 0}; }
+ConvIn cat_up(const bf16* up, int cu, const bf16* skip, int cs) {
+    return ConvIn{up, cu, 1, skip, cs};
+}
+
+// forward layer with LeakyReLU into y (bfloat16)
+int fwd(claire_net* n, int li, const ConvIn& in, int level, int batch, bf16* y) {
+    const NetLayer& L = n->L[li];
+    ConvOut o{};
+    o.y16 = y;
+    o.bias = n->p + L.off + (long long)L.cout * L.ktot;
+    return conv<EPI_ACT>(in, L.wt, L.kpad, L.nrows, L.cout, n->l - level,
+                         vox_level(n, level, batch), o, n->s);
+}
+
+int pool(claire_net* n, const bf16* x, int C, int level_out, int batch, bf16* y) {
+    const long long mo = vox_level(n, level_out, batch);
+    hipLaunchKernelGGL(k_pool, dim3(nblk(mo * C)), dim3(256), 0, n->s, x, C, n->l - level_out,
+                       (int)mo, y);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
+    const int c1 = n->c[0], c2 = n->c[1], c3 = n->c[2], c4 = n->c[3];
+    const long long mt = vox_level(n, 0, batch);
+    hipLaunchKernelGGL(k_features, dim3(nblk(mt)), dim3(256), 0, n->s, m0, m1, (int)mt, n->x0);
+    CL_LAUNCH_CHECK();
+    CL_TRY(fwd(n, ENC1A, one(n->x0, kInC), 0, batch, n->e1a));
+    CL_TRY(fwd(n, ENC1B, one(n->e1a, c1), 0, batch, n->s1));
+    CL_TRY(pool(n, n->s1, c1, 1, batch, n->p1));
+    CL_TRY(fwd(n, ENC2A, one(n->p1, c1), 1, batch, n->e2a));
+    CL_TRY(fwd(n, ENC2B, one(n->e2a, c2), 1, batch, n->s2));
+    CL_TRY(pool(n, n->s2, c2, 2, batch, n->p2));
+    CL_TRY(fwd(n, ENC3A, one(n->p2, c2), 2, batch, n->e3a));
+    CL_TRY(fwd(n, ENC3B, one(n->e3a, c3), 2, batch, n->s3));
+    CL_TRY(pool(n, n->s3, c3, 3, batch, n->p3));
+    CL_TRY(fwd(n, BOTA, one(n->p3, c3), 3, batch, n->ba));
+    CL_TRY(fwd(n, BOTB, one(n->ba, c4), 3, batch, n->bt));
+    CL_TRY(fwd(n, DEC3A, cat_up(n->bt, c4, n->s3, c3), 2, batch, n->d3a));
+    CL_TRY(fwd(n, DEC3B, one(n->d3a, c3), 2, batch, n->d3));
+    CL_TRY(fwd(n, DEC2A, cat_up(n->d3, c3, n->s2, c2), 1, batch, n->d2a));
+    CL_TRY(fwd(n, DEC2B, one(n->d2a, c2), 1, batch, n->d2));
+    CL_TRY(fwd(n, DEC1A, cat_up(n->d2, c2, n->s1, c1), 0, batch, n->d1a));
+    CL_TRY(fwd(n, DEC1B, one(n->d1a, c1), 0, batch, n->d1));
+    const NetLayer& H = n->L[HEAD];
+    ConvOut o{};
+    o.y32 = n->vout;
+    o.bias = n->p + H.off + (long long)H.cout * H.ktot;
+    return conv<EPI_LINEAR>(one(n->d1, c1), H.wt, H.kpad, H.nrows, H.cout, n->l, mt, o, n->s);
+}
+
+// weight and bias gradient of layer li from its input view and dz
+int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, int batch) {
+    const NetLayer& L = n->L[li];
+    const long long mt = vox_level(n, level, batch);
+    int splits, chunk;
+    wgrad_split(mt, splits, chunk);
+    const int ktiles = (L.kpad + 255) / 256;
+    const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level, (int)mt,
+                       L.kpad, ktiles, chunk, n->partial, L.nrows);
+    CL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, n->s, dz, L.coutE, (int)mt,
+                       chunk, n->pb);
+    CL_LAUNCH_CHECK();
+    const long long nw = (long long)L.cout * L.ktot;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + L.cout)), dim3(256), 0, n->s, n->partial,
+                       n->pb, splits, L.nrows, L.kpad, L.cout, L.ktot, L.coutE, n->g + L.off,
+                       n->g + L.off + nw);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+// backward data through layer li: dz_prev = bf16(conv^T(dz) * slope(yprev))
+int dgrad_act(claire_net* n, int li, const bf16* dz, const bf16* yprev, int level, int batch,
+              bf16* dz_prev) {
+    const NetLayer& L = n->L[li];
+    ConvOut o{};
+    o.y16 = dz_prev;
+    o.yprev = yprev;
+    return conv<EPI_DGRAD_ACT>(one(dz, L.coutE), L.wtT, L.kpadT, L.nrowsT, L.cin, n->l - level,
+                               vox_level(n, level, batch), o, n->s);
+}
+
+// backward data into float32, channels < csplit to a, the rest to b
+int dgrad_raw(claire_net* n, int li, const bf16* dz, int level, int batch, int csplit, float* a,
+              float* b) {
+    const NetLayer& L = n->L[li];
+    ConvOut o{};
+    o.y32 = a;
+    o.y32b = b;
+    o.csplit = csplit;
+    return conv<EPI_DGRAD_RAW>(one(dz, L.coutE), L.wtT, L.kpadT, L.nrowsT, L.cin, n->l - level,
+                               vox_level(n, level, batch), o, n->s);
+}
+
+int up_adjoint(claire_net* n, const float* dxa, const bf16* y, int C, int level_c, int batch,
+               bf16* dz) {
+    const long long mc = vox_level(n, level_c, batch);
+    hipLaunchKernelGGL(k_up_adjoint_slope, dim3(nblk(mc * C)), dim3(256), 0, n->s, dxa, y, C,
+                       n->l - level_c, (int)mc, dz);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int pool_adjoint(claire_net* n, const float* dxp, const float* dskip, const bf16* y, int C,
+                 int level_f, int batch, bf16* dz) {
+    const long long mf = vox_level(n, level_f, batch);
+    hipLaunchKernelGGL(k_pool_adjoint_slope, dim3(nblk(mf * C)), dim3(256), 0, n->s, dxp, dskip,
+                       y, C, n->l - level_f, (int)mf, dz);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int net_backward(claire_net* n, int batch) {
+    const int c1 = n->c[0], c2 = n->c[1], c3 = n->c[2], c4 = n->c[3];
+    bf16** A = n->dzA;
+    bf16** B = n->dzB;
+    CL_TRY(wgrad(n, HEAD, one(n->d1, c1), n->dzh, 0, batch));
+    CL_TRY(dgrad_act(n, HEAD, n->dzh, n->d1, 0, batch, A[0]));
+    CL_TRY(wgrad(n, DEC1B, one(n->d1a, c1), A[0], 0, batch));
+    CL_TRY(dgrad_act(n, DEC1B, A[0], n->d1a, 0, batch, B[0]));
+    CL_TRY(wgrad(n, DEC1A, cat_up(n->d2, c2, n->s1, c1), B[0], 0, batch));
+    CL_TRY(dgrad_raw(n, DEC1A, B[0], 0, batch, c2, n->dxA, n->dskip[0]));
+    CL_TRY(up_adjoint(n, n->dxA, n->d2, c2, 1, batch, A[1]));
+    CL_TRY(wgrad(n, DEC2B, one(n->d2a, c2), A[1], 1, batch));
+    CL_TRY(dgrad_act(n, DEC2B, A[1], n->d2a, 1, batch, B[1]));
+    CL_TRY(wgrad(n, DEC2A, cat_up(n->d3, c3, n->s2, c2), B[1], 1, batch));
+    CL_TRY(dgrad_raw(n, DEC2A, B[1], 1, batch, c3, n->dxA, n->dskip[1]));
+    CL_TRY(up_adjoint(n, n->dxA, n->d3, c3, 2, batch, A[2]));
+    CL_TRY(wgrad(n, DEC3B, one(n->d3a, c3), A[2], 2, batch));
+    CL_TRY(dgrad_act(n, DEC3B, A[2], n->d3a, 2, batch, B[2]));
+    CL_TRY(wgrad(n, DEC3A, cat_up(n->bt, c4, n->s3, c3), B[2], 2, batch));
+    CL_TRY(dgrad_raw(n, DEC3A, B[2], 2, batch, c4, n->dxA, n->dskip[2]));
+    CL_TRY(up_adjoint(n, n->dxA, n->bt, c4, 3, batch, A[3]));
+    CL_TRY(wgrad(n, BOTB, one(n->ba, c4), A[3], 3, batch));
+    CL_TRY(dgrad_act(n, BOTB, A[3], n->ba, 3, batch, B[3]));
+    CL_TRY(wgrad(n, BOTA, one(n->p3, c3), B[3], 3, batch));
+    CL_TRY(dgrad_raw(n, BOTA, B[3], 3, batch, c3, n->dxp, nullptr));
+    CL_TRY(pool_adjoint(n, n->dxp, n->dskip[2], n->s3, c3, 2, batch, A[2]));
+    CL_TRY(wgrad(n, ENC3B, one(n->e3a, c3), A[2], 2, batch));
+    CL_TRY(dgrad_act(n, ENC3B, A[2], n->e3a, 2, batch, B[2]));
+    CL_TRY(wgrad(n, ENC3A, one(n->p2, c2), B[2], 2, batch));
+    CL_TRY(dgrad_raw(n, ENC3A, B[2], 2, batch, c2, n->dxp, nullptr));
+    CL_TRY(pool_adjoint(n, n->dxp, n->dskip[1], n->s2, c2, 1, batch, A[1]));
+    CL_TRY(wgrad(n, ENC2B, one(n->e2a, c2), A[1], 1, batch));
+    CL_TRY(dgrad_act(n, ENC2B, A[1], n->e2a, 1, batch, B[1]));
+    CL_TRY(wgrad(n, ENC2A, one(n->p1, c1), B[1], 1, batch));
+    CL_TRY(dgrad_raw(n, ENC2A, B[1], 1, batch, c1, n->dxp, nullptr));
+    CL_TRY(pool_adjoint(n, n->dxp, n->dskip[0], n->s1, c1, 0, batch, A[0]));
+    CL_TRY(wgrad(n, ENC1B, one(n->e1a, c1), A[0], 0, batch));
+    CL_TRY(dgrad_act(n, ENC1B, A[0], n->e1a, 0, batch, B[0]));
+    CL_TRY(wgrad(n, ENC1A, one(n->x0, kInC), B[0], 0, batch));
+    return 0;
+}
+
+int check_net(const claire_net* n) {
+    if (!n) { set_error("net is NULL"); return CLAIRE_EINVAL; }
+    return 0;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+int check_ptr(const void* p, const char* name) {
+    if (!p) { set_error("%s is NULL", name); return CLAIRE_EINVAL; }
+    if (!aligned16(p)) { set_error("%s is not 16-byte aligned", name); return CLAIRE_EINVAL; }
+    return 0;
+}
+
+int check_batch(const claire_net* n, int batch) {
+    if (batch < 1 || batch > n->max_batch) {
+        set_error("batch %d out of range [1, %d]", batch, n->max_batch);
+        return CLAIRE_EINVAL;
+    }
+    return 0;
+}
+
+// Operands of one stand-alone layer: bfloat16 copies of x (and dz) and the
+// packed forward / backward-data weights.
+struct LayerScratch {
+    bf16 *x16 = nullptr, *dz16 = nullptr, *wt = nullptr, *wtT = nullptr;
+    void release(hipStream_t s) {
+        (void)hipStreamSynchronize(s);
+        dfree(x16); dfree(dz16); dfree(wt); dfree(wtT);
+    }
+};
+
+int layer_setup(LayerScratch& S, const NetLayer& L, const float* x, const float* w,
+                const float* dz, long long mt, hipStream_t s) {
+    CL_TRY(dalloc(&S.x16, mt * L.cin));
+    CL_TRY(dalloc(&S.wt, (long long)L.nrows * L.kpad));
+    CL_TRY(dalloc(&S.wtT, (long long)L.nrowsT * L.kpadT));
+    CL_TRY(zero16(S.wt, (long long)L.nrows * L.kpad, s));
+    CL_TRY(zero16(S.wtT, (long long)L.nrowsT * L.kpadT, s));
+    hipLaunchKernelGGL(k_round16, dim3(nblk(mt * L.cin)), dim3(256), 0, s, x, mt * L.cin, S.x16);
+    CL_LAUNCH_CHECK();
+    const int nw = L.cout * L.ktot;
+    hipLaunchKernelGGL(k_adam_pack, dim3(nblk(nw)), dim3(256), 0, s, const_cast<float*>(w),
+                       nullptr, nullptr, nullptr, nw, 0, 0, 0.f, 0.f, 0.f, 1.f, 1.f, 0.f, S.wt,
+                       L.kpad, L.ktot, S.wtT, L.kpadT, L.cin, L.coutE);
+    CL_LAUNCH_CHECK();
+    if (dz) {
+        CL_TRY(dalloc(&S.dz16, mt * L.cout));
+        hipLaunchKernelGGL(k_round16, dim3(nblk(mt * L.cout)), dim3(256), 0, s, dz,
+                           mt * L.cout, S.dz16);
+        CL_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+NetLayer layer_geometry(int cin, int cout) {
+    NetLayer L;
+    L.cin = cin;
+    L.cout = cout;
+    L.coutE = roundup(cout, 8);
+    L.ktot = 27 * cin;
+    L.kpad = roundup(L.ktot, 32);
+    L.nrows = roundup(cout, 16);
+    L.kpadT = roundup(27 * L.coutE, 32);
+    L.nrowsT = roundup(cin, 16);
+    L.off = 0;
+    return L;
+}
+
+int check_layer_sizes(int batch, int res, int cin, int cout) {
+    if (res < 1 || res > 256 || (res & (res - 1)) || batch < 1 || cin < 8 || cin % 8 ||
+        cin > 512 || cout < 1 || cout > 512 || (long long)batch * res * res * res > (1LL << 24)) {
+        set_error("bad convolution sizes");
+        return CLAIRE_EINVAL;
+    }
+    return 0;
+}
+
+}  // namespace
+}  // namespace claire
+
+extern "C" {
+
+int claire_net_create(claire_net** out, int res, const int channels[4], int max_batch,
+                      unsigned long long seed, void* stream) {
+    if (!out) { set_error("out is NULL"); return CLAIRE_EINVAL; }
+    *out = nullptr;
+    if (res < 8 || res > 256 || (res & (res - 1))) {
+        set_error("res = %d: must be a power of two in [8, 256]", res);
+        return CLAIRE_EINVAL;
+    }
+    if (!channels) { set_error("channels is NULL"); return CLAIRE_EINVAL; }
+    for (int k = 0; k < 4; ++k)
+        if (channels[k] < 8 || channels[k] > 256 || channels[k] % 8) {
+            set_error("channels[%d] = %d: must be a multiple of 8 in [8, 256]", k, channels[k]);
+            return CLAIRE_EINVAL;
+        }
+    if (max_batch < 1 || (long long)max_batch * res * res * res > (1LL << 26)) {
+        set_error("max_batch = %d: need 1 <= max_batch and max_batch res^3 <= 2^26", max_batch);
+        return CLAIRE_EINVAL;
+    }
+    claire_net* n = new (std::nothrow) claire_net();
+    if (!n) { set_error("host allocation failed"); return CLAIRE_ENOMEM; }
+    n->R = res;
+    n->l = lg2(res);
+    for (int k = 0; k < 4; ++k) n->c[k] = channels[k];
+    n->max_batch = max_batch;
+    n->s = reinterpret_cast<hipStream_t>(stream);
+    int rc = net_alloc(n);
+    if (rc < 0) {
+        net_release(n);
+        delete n;
+        return rc;
+    }
+    // He-uniform weights (bound sqrt(6 / fan_in), a tenth of it for the
+    // output layer), zero biases; splitmix64 stream from the seed
+    std::vector<float> h((size_t)n->nparam, 0.f);
+    uint64_t st = seed;
+    for (int i = 0; i < kLayers; ++i) {
+        const NetLayer& L = n->L[i];
+        double a = std::sqrt(6.0 / L.ktot);
+        if (i == HEAD) a *= 0.1;
+        const long long nw = (long long)L.cout * L.ktot;
+        for (long long k = 0; k < nw; ++k) {
+            const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+            h[(size_t)(L.off + k)] = (float)((2.0 * u - 1.0) * a);
+        }
+    }
+    hipError_t e = hipMemcpyAsync(n->p, h.data(), sizeof(float) * h.size(),
+                                  hipMemcpyHostToDevice, n->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->s);
+    if (e != hipSuccess) {
+        hip_fail(e, "upload of initial weights", __FILE__, __LINE__);
+        net_release(n);
+        delete n;
+        return CLAIRE_EDEVICE;
+    }
+    if ((rc = reset_adam(n)) < 0 || (rc = net_pack(n, false, 0.0)) < 0) {
+        net_release(n);
+        delete n;
+        return rc;
+    }
+    *out = n;
+    return 0;
+}
+
+int claire_net_destroy(claire_net* n) {
+    if (!n) return 0;
+    (void)hipStreamSynchronize(n->s);
+    net_release(n);
+    delete n;
+    return 0;
+}
+
+long long claire_net_param_count(const claire_net* n) { return n ? n->nparam : -1; }
+
+int claire_net_set_params(claire_net* n, const float* params) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_ptr(params, "params"));
+    CL_HIP(hipMemcpyAsync(n->p, params, sizeof(float) * (size_t)n->nparam,
+                          hipMemcpyDeviceToDevice, n->s));
+    CL_TRY(reset_adam(n));
+    return net_pack(n, false, 0.0);
+}
+
+int claire_net_get_params(const claire_net* n, float* params) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_ptr(params, "params"));
+    CL_HIP(hipMemcpyAsync(params, n->p, sizeof(float) * (size_t)n->nparam,
+                          hipMemcpyDeviceToDevice, n->s));
+    return 0;
+}
+
+int claire_net_get_grads(const claire_net* n, float* grads) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_ptr(grads, "grads"));
+    if (!n->have_grads) { set_error("no gradient computed yet"); return CLAIRE_ESTATE; }
+    CL_HIP(hipMemcpyAsync(grads, n->g, sizeof(float) * (size_t)n->nparam,
+                          hipMemcpyDeviceToDevice, n->s));
+    return 0;
+}
+
+int claire_net_set_grads(claire_net* n, const float* grads) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_ptr(grads, "grads"));
+    CL_HIP(hipMemcpyAsync(n->g, grads, sizeof(float) * (size_t)n->nparam,
+                          hipMemcpyDeviceToDevice, n->s));
+    n->have_grads = true;
+    return 0;
+}
+
+int claire_net_forward(claire_net* n, const float* m0, const float* m1, int batch, float* v) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_batch(n, batch));
+    CL_TRY(check_ptr(m0, "m0"));
+    CL_TRY(check_ptr(m1, "m1"));
+    CL_TRY(check_ptr(v, "v"));
+    CL_TRY(net_forward(n, m0, m1, batch));
+    const long long mt = vox_level(n, 0, batch);
+    hipLaunchKernelGGL(k_out_transpose, dim3(nblk(mt)), dim3(256), 0, n->s, n->vout, n->l,
+                       (int)mt, v);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int claire_net_loss_grad(claire_net* n, const float* m0, const float* m1, const float* v_target,
+                         int batch, double* loss, float* v) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_batch(n, batch));
+    CL_TRY(check_ptr(m0, "m0"));
+    CL_TRY(check_ptr(m1, "m1"));
+    CL_TRY(check_ptr(v_target, "v_target"));
+    if (v) CL_TRY(check_ptr(v, "v"));
+    CL_TRY(net_forward(n, m0, m1, batch));
+    const long long mt = vox_level(n, 0, batch);
+    const double N = (double)mt * kOutC;
+    hipLaunchKernelGGL(k_mse, dim3(nblk(mt)), dim3(256), 0, n->s, n->vout, v_target, n->l,
+                       (int)mt, (float)(2.0 / N), n->dzh, n->red.partial);
+    CL_LAUNCH_CHECK();
+    CL_TRY(red_fold_sum(n->red, (int)nblk(mt), 1, 0, 0, n->s));
+    if (v) {
+        hipLaunchKernelGGL(k_out_transpose, dim3(nblk(mt)), dim3(256), 0, n->s, n->vout, n->l,
+                           (int)mt, v);
+        CL_LAUNCH_CHECK();
+    }
+    CL_TRY(net_backward(n, batch));
+    n->have_grads = true;
+    CL_TRY(red_fetch(n->red, n->s));
+    if (loss) *loss = n->red.host[0] / N;
+    return 0;
+}
+
+int claire_net_adam_step(claire_net* n, double lr) {
+    CL_TRY(check_net(n));
+    if (!n->have_grads) { set_error("no gradient computed yet"); return CLAIRE_ESTATE; }
+    if (!(lr > 0.0)) { set_error("lr must be positive"); return CLAIRE_EINVAL; }
+    return net_pack(n, true, lr);
+}
+
+int claire_net_train_step(claire_net* n, const float* m0, const float* m1, const float* v_target,
+                          int batch, double lr, double* loss) {
+    CL_TRY(claire_net_loss_grad(n, m0, m1, v_target, batch, loss, nullptr));
+    return claire_net_adam_step(n, lr);
+}
+
+int claire_net_warm_start(claire_net* n, const float* m0, const float* m1, int nx, float* v0) {
+    CL_TRY(check_net(n));
+    CL_TRY(check_ptr(m0, "m0"));
+    CL_TRY(check_ptr(m1, "m1"));
+    CL_TRY(check_ptr(v0, "v0"));
+    if (nx < n->R || nx > 1024 || (nx & (nx - 1))) {
+        set_error("n = %d: must be a power of two in [%d, 1024]", nx, n->R);
+        return CLAIRE_EINVAL;
+    }
+    const long long R3 = (long long)n->R * n->R * n->R;
+    const long long big = 3LL * nx * nx * nx;
+    if (big > n->ws_cap) {
+        (void)hipStreamSynchronize(n->s);
+        dfree(n->ws_a); dfree(n->ws_b); dfree(n->ws_v); dfree(n->ws_t0); dfree(n->ws_t1);
+        n->ws_a = n->ws_b = n->ws_v = n->ws_t0 = n->ws_t1 = nullptr;
+        n->ws_cap = 0;
+        CL_TRY(dalloc(&n->ws_a, R3));
+        CL_TRY(dalloc(&n->ws_b, R3));
+        CL_TRY(dalloc(&n->ws_v, 3 * R3));
+        CL_TRY(dalloc(&n->ws_t0, big));
+        CL_TRY(dalloc(&n->ws_t1, big));
+        n->ws_cap = big;
+    }
+    CL_TRY(resample(m0, nx, n->ws_a, n->R, 1, n->ws_t0, n->ws_t1, n->s));
+    CL_TRY(resample(m1, nx, n->ws_b, n->R, 1, n->ws_t0, n->ws_t1, n->s));
+    CL_TRY(claire_net_forward(n, n->ws_a, n->ws_b, 1, n->ws_v));
+    return resample(n->ws_v, n->R, v0, nx, 3, n->ws_t0, n->ws_t1, n->s);
+}
+
+int claire_resample(const float* src, int n_src, float* dst, int n_dst, int ncomp, void* stream) {
+    CL_TRY(check_ptr(src, "src"));
+    CL_TRY(check_ptr(dst, "dst"));
+    auto ok = [](int v) { return v >= 1 && v <= 1024 && (v & (v - 1)) == 0; };
+    if (!ok(n_src) || !ok(n_dst)) {
+        set_error("extents must be powers of two in [1, 1024]");
+        return CLAIRE_EINVAL;
+    }
+    if (ncomp < 1 || ncomp > 16) { set_error("ncomp must be in [1, 16]"); return CLAIRE_EINVAL; }
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int nm = n_src > n_dst ? n_src : n_dst;
+    const long long big = (long long)ncomp * nm * nm * nm;
+    float *t0 = nullptr, *t1 = nullptr;
+    int rc = 0;
+    if ((rc = dalloc(&t0, big)) >= 0 && (rc = dalloc(&t1, big)) >= 0)
+        rc = resample(src, n_src, dst, n_dst, ncomp, t0, t1, s);
+    (void)hipStreamSynchronize(s);
+    dfree(t0);
+    dfree(t1);
+    return rc < 0 ? rc : 0;
+}
+
+int claire_conv3d(const float* x, const float* w, const float* b, int batch, int res, int cin,
+                  int cout, int act, float* y, void* stream) {
+    CL_TRY(check_ptr(x, "x"));
+    CL_TRY(check_ptr(w, "w"));
+    CL_TRY(check_ptr(y, "y"));
+    CL_TRY(check_layer_sizes(batch, res, cin, cout));
+    if (act != 0 && act != 1) { set_error("act must be 0 or 1"); return CLAIRE_EINVAL; }
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const long long mt = (long long)batch * res * res * res;
+    const NetLayer L = layer_geometry(cin, cout);
+    LayerScratch S;
+    int rc = layer_setup(S, L, x, w, nullptr, mt, s);
+    if (rc >= 0) {
+        ConvOut o{};
+        o.bias = b;
+        o.y32 = y;
+        rc = act ? conv<EPI_ACT32>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt, o, s)
+                 : conv<EPI_LINEAR>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt, o, s);
+    }
+    S.release(s);
+    return rc < 0 ? rc : 0;
+}
+
+int claire_conv3d_backward(const float* x, const float* w, const float* dz, int batch, int res,
+                           int cin, int cout, float* dx, float* dw, float* db, void* stream) {
+    CL_TRY(check_ptr(x, "x"));
+    CL_TRY(check_ptr(w, "w"));
+    CL_TRY(check_ptr(dz, "dz"));
+    CL_TRY(check_ptr(dx, "dx"));
+    CL_TRY(check_ptr(dw, "dw"));
+    CL_TRY(check_ptr(db, "db"));
+    CL_TRY(check_layer_sizes(batch, res, cin, cout));
+    if (cout % 8) { set_error("cout must be a multiple of 8"); return CLAIRE_EINVAL; }
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const long long mt = (long long)batch * res * res * res;
+    const int l = lg2(res);
+    const NetLayer L = layer_geometry(cin, cout);
+    LayerScratch S;
+    float *partial = nullptr, *pb = nullptr;
+    int splits, chunk;
+    wgrad_split(mt, splits, chunk);
+    int rc = layer_setup(S, L, x, w, dz, mt, s);
+    if (rc >= 0) rc = dalloc(&partial, (long long)splits * L.nrows * L.kpad);
+    if (rc >= 0) rc = dalloc(&pb, (long long)splits * L.coutE);
+    if (rc >= 0) {
+        ConvOut o{};
+        o.y32 = dx;
+        o.csplit = cin;
+        rc = conv<EPI_DGRAD_RAW>(one(S.dz16, cout), S.wtT, L.kpadT, L.nrowsT, cin, l, mt, o, s);
+    }
+    if (rc >= 0) {
+        const int ktiles = (L.kpad + 255) / 256;
+        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits),
+                           dim3(256), 0, s, one(S.x16, cin), S.dz16, cout, l, (int)mt, L.kpad,
+                           ktiles, chunk, partial, L.nrows);
+        hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout, (int)mt,
+                           chunk, pb);
+        const long long nw = (long long)cout * L.ktot;
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + cout)), dim3(256), 0, s, partial, pb,
+                           splits, L.nrows, L.kpad, cout, L.ktot, cout, dw, db);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "weight gradient", __FILE__, __LINE__);
+    }
+    S.release(s);
+    dfree(partial);
+    dfree(pb);
+    return rc < 0 ? rc : 0;
+}
+
+}  // extern "C"

@@ -1,6 +1,7 @@
-"""The C-ABI library loads and exports every entry point of include/claire.h
-(no compute calls: this runs without a GPU)."""
+"""The C-ABI library loads and exports every entry point declared in
+include/*.h (no compute calls: this runs without a GPU)."""
 import ctypes
+import glob
 import os
 import re
 
@@ -8,18 +9,22 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "claire.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(claire_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(claire_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for required in ("claire_transport", "claire_gradient", "claire_hessian_matvec",
-                     "claire_solve", "claire_ctx_create", "claire_last_error"):
+                     "claire_solve", "claire_ctx_create", "claire_last_error",
+                     "claire_net_create", "claire_net_train_step", "claire_net_warm_start"):
         assert required in names
 
 
@@ -54,6 +59,7 @@ def test_library_refuses_to_load_when_missing(monkeypatch):
 
 def test_binding_imports_without_gpu():
     # the torch binding must import (and stay syntactically valid) on the CPU
-    from paper_2401_17493_amd import claire
+    from paper_2401_17493_amd import claire, warmstart
     assert claire.FIELD_GRAD_STATE == 3 and claire.KERNEL_COPY == 3
     assert hasattr(claire.Context, "time_kernel")
+    assert hasattr(warmstart.Net, "train_step") and hasattr(warmstart, "resample")
