@@ -7,16 +7,20 @@ H1 seminorm, alpha = 1e-3, n_t = 4, gradient tolerance 5e-2, from v = 0,
 inputs resident in HBM. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                  [--precision mixed|fp32|both]
+                  [--precision mixed|fp32|both] [--warmstart WEIGHTS|none]
 
 ``value`` is the time-to-solution (seconds) of the mixed-precision solve
 (float16 storage of grad m and the incremental sources in the Hessian matvec,
-float32 arithmetic); with --precision both (default) the float32 solve is
-timed too and the line reports both, with the differences of the two
-solutions. The line also carries the Hessian matvec throughput, the HBM
-roofline of the dominant kernel (average launch duration measured here with
-HIP events) and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+float32 arithmetic) started from the learned warm start: the timed region
+holds the network's inference (restriction to its working resolution,
+forward pass, prolongation), the extra state/adjoint solve at v = 0 that
+fixes the stopping test at ||g||_inf <= gtol ||g(0)||_inf, and the solve.
+The cold mixed and float32 solves (from v = 0, same tolerance) are timed too
+and reported beside it, with the differences between the solutions. Without
+trained weights (--warmstart none) ``value`` is the cold mixed solve. The line
+also carries the Hessian matvec throughput, the HBM roofline of the dominant
+kernel (average launch duration measured here with HIP events) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -31,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GN-Krylov time-to-solution at 256^3 (s, gtol 5e-2) + Hessian matvecs/s"
+WEIGHTS = os.path.join(ROOT, "paper_2401_17493_amd", "weights", "warmstart_r64.npz")
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per voxel of one launch of each timed kernel (float32):
@@ -119,6 +124,8 @@ def main():
                     choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["mixed", "fp32", "both"])
+    ap.add_argument("--warmstart", default=WEIGHTS,
+                    help="trained warm-start weights (.npz) or 'none'")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up at v = v*/2 and launch only the roofline kernel and the copy "
                          "kernel (for hardware-counter runs); prints their timings")
@@ -156,38 +163,56 @@ def main():
         ctx.close()
         return
     precisions = {"mixed": [1], "fp32": [0], "both": [1, 0]}[args.precision]
+    net = None
+    if args.warmstart != "none" and os.path.exists(args.warmstart) and 1 in precisions:
+        from paper_2401_17493_amd.warmstart import Net
+        net = Net.load(args.warmstart)
+    # (label, precision, warm start)
+    modes = ([("mixed+warm", 1, True)] if net is not None else []) + \
+        [("mixed" if p else "fp32", p, False) for p in precisions]
     runs = {}
-    for prec in precisions:
+    for label, prec, warm in modes:
         o = dict(opts, precision=prec)
+        if warm:
+            o["tol_from_zero"] = 1
+
+        def one_solve():
+            v0 = net.warm_start(m0, m1) if warm else None
+            return ctx.solve(v0, **o)
         for _ in range(args.warmup):
-            ctx.solve(**o)
+            one_solve()
         torch.cuda.synchronize()
         times, stats, v = [], None, None
         for _ in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            v, stats = ctx.solve(**o)
+            v, stats = one_solve()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             print("step (%s): solve %.3f s, %d GN iterations, %d matvecs" %
-                  ("mixed" if prec else "fp32", times[-1], stats["gn_iters"], stats["matvecs"]),
+                  (label, times[-1], stats["gn_iters"], stats["matvecs"]),
                   file=sys.stderr, flush=True)
-        # Hessian matvec throughput at the solution, HIP events on the context stream
-        ctx.set_precision(prec)
-        ctx.set_velocity(v)
-        vt = (0.5 * vstar).contiguous()
-        hv = torch.empty_like(vt)
-        ctx.hessian_matvec(vt, hv)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(ctx.stream)
-        for _ in range(args.matvecs):
+        rec = dict(tts=sum(times) / len(times), stats=stats, v=v, prec=prec)
+        if not warm:
+            # Hessian matvec throughput at the solution, HIP events on the context stream
+            ctx.set_precision(prec)
+            ctx.set_velocity(v)
+            vt = (0.5 * vstar).contiguous()
+            hv = torch.empty_like(vt)
             ctx.hessian_matvec(vt, hv)
-        e1.record(ctx.stream)
-        e1.synchronize()
-        runs[prec] = dict(tts=sum(times) / len(times), stats=stats, v=v,
-                          ms_matvec=e0.elapsed_time(e1) / args.matvecs)
-    head = runs[precisions[0]]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            for _ in range(args.matvecs):
+                ctx.hessian_matvec(vt, hv)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            rec["ms_matvec"] = e0.elapsed_time(e1) / args.matvecs
+        runs[label] = rec
+    if net is not None:
+        net.close()
+        runs["mixed+warm"]["ms_matvec"] = runs["mixed"]["ms_matvec"]
+    head = runs[modes[0][0]]
     tts, stats, ms_matvec = head["tts"], head["stats"], head["ms_matvec"]
     ctx.set_precision(0)
     ctx.set_velocity(head["v"])
@@ -233,7 +258,10 @@ def main():
                    "gtol": opts["gtol"], "preconditioner": "(alpha L)^-1",
                    "precision": "mixed: float16 grad m and incremental sources in the "
                                 "Hessian matvec, float32 arithmetic/FFTs, float64 reductions"
-                   if precisions[0] == 1 else "float32 fields and FFTs, float64 reductions",
+                   if head["prec"] == 1 else "float32 fields and FFTs, float64 reductions",
+                   "initial_guess": "learned warm start (%s), stopping test against "
+                                    "||g(v=0)||_inf" % os.path.basename(args.warmstart)
+                   if modes[0][2] else "v = 0",
                    "parallelism": "single GPU"},
         "hessian_matvecs_per_s": round(1000.0 / ms_matvec, 2),
         "ms_per_matvec": round(ms_matvec, 4),
@@ -246,15 +274,21 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "copy_kernel_GBs": round(copy_gbs, 1)},
     }
-    if len(precisions) == 2:
-        mixed, plain = runs[1], runs[0]
-        vm, vp = mixed["v"], plain["v"]
-        out["fp32_solve"] = solve_rec(plain)
-        out["mixed_vs_fp32"] = {
-            "speedup": round(plain["tts"] / mixed["tts"], 3),
-            "v_rel_maxnorm": float((vm - vp).abs().max() / vp.abs().max()),
-            "J_rel": abs(mixed["stats"]["J"] - plain["stats"]["J"]) / plain["stats"]["J"],
-            "rel_grad": [mixed["stats"]["rel_grad"], plain["stats"]["rel_grad"]]}
+    def compare(a, b):
+        va, vb = a["v"], b["v"]
+        return {"speedup": round(b["tts"] / a["tts"], 3),
+                "v_rel_maxnorm": float((va - vb).abs().max() / vb.abs().max()),
+                "J_rel": abs(a["stats"]["J"] - b["stats"]["J"]) / b["stats"]["J"],
+                "rel_grad": [a["stats"]["rel_grad"], b["stats"]["rel_grad"]]}
+    if "mixed+warm" in runs:
+        out["mixed_solve"] = solve_rec(runs["mixed"])
+        if "fp32" in runs:
+            out["warm_vs_fp32"] = compare(runs["mixed+warm"], runs["fp32"])
+        out["warm_vs_mixed"] = compare(runs["mixed+warm"], runs["mixed"])
+    if "fp32" in runs:
+        out["fp32_solve"] = solve_rec(runs["fp32"])
+        if "mixed" in runs:
+            out["mixed_vs_fp32"] = compare(runs["mixed"], runs["fp32"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, host_inputs)
     print(json.dumps(out), flush=True)

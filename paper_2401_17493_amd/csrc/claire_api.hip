@@ -391,9 +391,9 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     const int limit = fixed ? o.fixed_pcg_iters : o.max_pcg;
     CL_TRY(launch_fill(c->vt, 0.f, n3, s));
     CL_TRY(launch_scale_copy(c->grad, c->r, -1.f, n3, s));
-    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
+    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s, nullptr,
+                          c->r, &c->red, 0));   // z and <z, r> -> slot 0
     CL_TRY(copy_d2d(c->sd, c->z, n3, s));
-    CL_TRY(red_dot(c->red, c->r, c->z, n3, 0, s));
     for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
     CL_TRY(red_fetch(c->red, s));
     double rz = c->red.host[0];
@@ -419,8 +419,8 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(pcg_update(c->red, c->sd, c->hs, c->vt, c->r, (float)kappa, n, 1, 3, s));
         if (res.its == limit) break;
         // preconditioned residual and <z, r>: one host round trip with the above
-        CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s));
-        CL_TRY(red_dot(c->red, c->z, c->r, n3, 2, s));
+        CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s,
+                              nullptr, c->r, &c->red, 2));   // z and <z, r> -> slot 2
         CL_TRY(red_fetch(c->red, s));
         if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
         const double rz_new = c->red.host[2];

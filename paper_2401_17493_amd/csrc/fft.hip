@@ -203,13 +203,16 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
 }
 
 // ---------------------------------------------------------------- pass 5
-// rows of nh bins -> rows of n3 reals (x n3, unnormalised), + optional add.
-template <int E>
+// rows of nh bins -> rows of n3 reals (x n3, unnormalised), + optional add;
+// DOT: also the block's share of <out, dotw> in float64 -> partial[block].
+template <int E, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ in,
                                                      float* __restrict__ out,
                                                      const float* __restrict__ add, int l3,
                                                      int RB, long long n, long long nspec,
-                                                     const float2* __restrict__ tw, int logT) {
+                                                     const float2* __restrict__ tw, int logT,
+                                                     const float* __restrict__ dotw,
+                                                     double* __restrict__ partial) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* tw_s = reinterpret_cast<float2*>(smem_raw);
     float2* buf = tw_s + (1 << logT);
@@ -238,10 +241,22 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     lds_fft<+1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
     float2* dst = reinterpret_cast<float2*>(out + blockIdx.y * n) + row0 * M;
     const float2* ad = add ? reinterpret_cast<const float2*>(add + blockIdx.y * n) + row0 * M : nullptr;
+    const float2* dw = DOT ? reinterpret_cast<const float2*>(dotw + blockIdx.y * n) + row0 * M
+                           : nullptr;
+    double dot = 0.0;
     for (int e = tid; e < RB * M; e += kThreads) {
         float2 val = buf[e];
         if (ad) { const float2 a = ad[e]; val.x += a.x; val.y += a.y; }
         dst[e] = val;
+        if (DOT) {
+            const float2 d = dw[e];
+            dot += (double)val.x * d.x + (double)val.y * d.y;
+        }
+    }
+    if (DOT) {
+        __shared__ double sh[4];
+        const double t = block_sum_256(dot, sh);
+        if (tid == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -503,15 +518,23 @@ int fwd_x3(const Geo& g, const C* tw, int T, const float* in, C* spec, int ncomp
 }
 
 int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, const float* add,
-           int ncomp, hipStream_t s) {
+           int ncomp, hipStream_t s, const float* dot_with = nullptr, Reducer* red = nullptr,
+           int slot = 0) {
     const long long rows = (long long)g.n1 * g.n2;
     const int RB = row_block(g.n3, rows, 4096);
     const int logT = ilog2(w.tw_n);
     const size_t sh = sizeof(float2) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
-    CL_TRY(allow_lds(k_c2r_x3<16>, sh));
-    hipLaunchKernelGGL(k_c2r_x3<16>, grid, dim3(kThreads), sh, s, spec, out, add, g.l3, RB, g.n,
-                       g.nspec, w.tw, logT);
+    if (dot_with) {
+        CL_TRY(allow_lds(k_c2r_x3<16, true>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<16, true>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
+                           RB, g.n, g.nspec, w.tw, logT, dot_with, red->partial);
+        CL_LAUNCH_CHECK();
+        return red_fold_sum(*red, (int)(grid.x * grid.y), 1, 0, slot, s);
+    }
+    CL_TRY(allow_lds(k_c2r_x3<16, false>, sh));
+    hipLaunchKernelGGL((k_c2r_x3<16, false>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
+                       RB, g.n, g.nspec, w.tw, logT, nullptr, nullptr);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -526,10 +549,20 @@ int cols_launch(const Geo& g, const C* tw, int logT, C* spec, int CW, size_t sh,
     return 0;
 }
 
+// Column-tile budgets (complex values per workgroup tile) of the x2 pass and
+// the fused x1 pass in float: the tile width is budget / n; the elements per
+// thread (and so the registers, and the occupancy) follow from it.
+#ifndef CLAIRE_FFT_COL_ELEMS
+#define CLAIRE_FFT_COL_ELEMS 8192
+#endif
+#ifndef CLAIRE_FFT_X1_ELEMS
+#define CLAIRE_FFT_X1_ELEMS 2048
+#endif
+
 template <int DIR, typename C>
 int cols_x2(const Geo& g, const C* tw, int T, C* spec, int ncomp, hipStream_t s) {
-    // float tiles hold up to 8192 values, double tiles 2048
-    constexpr int elems = sizeof(C) == 8 ? 8192 : 2048;
+    // float tiles hold up to CLAIRE_FFT_COL_ELEMS values, double tiles 2048
+    constexpr int elems = sizeof(C) == 8 ? CLAIRE_FFT_COL_ELEMS : 2048;
     const int CW = tile_cols(g.n2, g.nh, elems);
     const int logT = ilog2(T);
     const size_t sh = sizeof(C) * ((1 << logT) + (size_t)g.n2 * CW);
@@ -543,12 +576,16 @@ int cols_x2(const Geo& g, const C* tw, int T, C* spec, int ncomp, hipStream_t s)
 template <int MODE>
 int fused_x1(const Geo& g, const SpectralWork& w, const float2* in, float2* out, Mult m,
              int ncomp, hipStream_t s) {
-    const int CW = tile_cols(g.n1, g.nh, 8192);
+    const int CW = tile_cols(g.n1, g.nh, CLAIRE_FFT_X1_ELEMS);
     const int logT = ilog2(w.tw_n);
     const int tiles = (MODE == SPEC_GRAD || MODE == SPEC_DIV) ? 2 : 1;
     const size_t sh = sizeof(float2) * ((1 << logT) + (size_t)tiles * g.n1 * CW);
     dim3 grid((g.nh + CW - 1) / CW, g.n2, ncomp);
-    if (g.n1 * CW <= 16 * kThreads) {
+    if (g.n1 * CW <= 8 * kThreads) {
+        CL_TRY(allow_lds(k_x1_fused<MODE, 8>, sh));
+        hipLaunchKernelGGL((k_x1_fused<MODE, 8>), grid, dim3(kThreads), sh, s, in, out, g.l1, CW,
+                           g.nh, g.nspec, m, w.tw, logT);
+    } else if (g.n1 * CW <= 16 * kThreads) {
         CL_TRY(allow_lds(k_x1_fused<MODE, 16>, sh));
         hipLaunchKernelGGL((k_x1_fused<MODE, 16>), grid, dim3(kThreads), sh, s, in, out, g.l1, CW,
                            g.nh, g.nspec, m, w.tw, logT);
@@ -611,7 +648,12 @@ void spectral_free(SpectralWork& w) {
 }
 
 int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in, float* out,
-                   double alpha, int p, hipStream_t s, const float* add) {
+                   double alpha, int p, hipStream_t s, const float* add, const float* dot_with,
+                   Reducer* red, int slot) {
+    if (dot_with && (mode != SPEC_REG_INV || !red)) {
+        set_error("fused dot product only with SPEC_REG_INV and a reducer");
+        return CLAIRE_EINVAL;
+    }
     Mult m;
     m.n1 = g.n1;
     m.n2 = g.n2;
@@ -648,7 +690,7 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(fused_x1<SPEC_REG_INV>(g, w, S, S, m, 3, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
-        CL_TRY(inv_x3(g, w, S, out, add, 3, s));
+        CL_TRY(inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot));
         break;
     default:
         set_error("unknown spectral mode %d", (int)mode);

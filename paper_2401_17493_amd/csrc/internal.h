@@ -67,10 +67,12 @@ enum SpecMode {
 
 // out = F^{-1}[ sigma F[in] ] for the mode above; in and out are real fields
 // (SoA). `add` (nullable, same shape as out) is added to the result. in and
-// out must not overlap.
+// out must not overlap. With dot_with (SPEC_REG_INV only), <out, dot_with>
+// is also summed into red->result[slot].
 int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in,
                    float* out, double alpha, int p, hipStream_t s,
-                   const float* add = nullptr);
+                   const float* add = nullptr, const float* dot_with = nullptr,
+                   Reducer* red = nullptr, int slot = 0);
 
 // ------------------------------------------------------ semi-Lagrangian
 // Single-field gathers accept an optional per-brick box table of their
