@@ -49,11 +49,19 @@ def kernel_bytes_per_voxel(kernel, nt):
             "assemble": 16 * (nt + 1) + 24, "copy": 24}[kernel]
 
 
-def source_digest():
-    """Hash of the HIP sources: counter data taken for another build is stale."""
+# HIP sources that define each timed kernel (its code and launch)
+KERNEL_SOURCES = {"inc_state_step": ["sl.hip", "internal.h"],
+                  "adjoint_step": ["sl.hip", "internal.h"],
+                  "assemble": ["sl.hip", "internal.h"],
+                  "copy": ["blas.hip", "internal.h"]}
+
+
+def source_digest(kernel):
+    """Hash of the kernel's HIP sources: counter data taken for another
+    version of the kernel is stale."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2401_17493_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -67,7 +75,7 @@ def load_traffic(kernel, workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_digest") != source_digest():
+    if rec.get("source_digest") != source_digest(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 

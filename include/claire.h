@@ -46,7 +46,11 @@ enum claire_status {
     CLAIRE_WNOTCONV = 1,     /* Gauss--Newton stopped at max_gn iterations */
     CLAIRE_WLINESEARCH = 2,  /* Armijo line search found no acceptable step */
     CLAIRE_WPCGMAX = 3,      /* PCG hit max_pcg before its forcing tolerance */
-    CLAIRE_WDETBOUND = 4     /* det F(1) <= 0 somewhere (map not diffeomorphic) */
+    CLAIRE_WDETBOUND = 4,    /* det F(1) <= 0 somewhere (map not diffeomorphic) */
+    CLAIRE_WNEGCURV = 5      /* PCG met nonpositive curvature <s, Hs> <= 0 and stopped
+                                early (truncated CG: the current step, or the
+                                preconditioned steepest-descent direction on the
+                                first matvec) */
 };
 
 /* Options of the Gauss--Newton--Krylov solve (Section 2.5.5, Algorithms 1-2,

@@ -406,8 +406,14 @@ def pcg(matvec, precond, g, *, fixed_iters=0, max_iters=100, forcing="superlinea
     """Solve H v~ = -g by preconditioned CG (Algorithm 2), v~^0 = 0.
 
     Stops after ``fixed_iters`` matvecs if that is positive, else when
-    ||r||_inf <= eta ||g||_inf or after ``max_iters`` matvecs.
-    Returns (v~, matvecs, residual inf-norm history, hit_max).
+    ||r||_inf <= eta ||g||_inf or after ``max_iters`` matvecs. Nonpositive
+    curvature <s, Hs> <= 0 along a direction (the discrete Gauss--Newton
+    Hessian is only positive semidefinite up to discretisation error) stops
+    the iteration as in truncated CG: the current v~ is returned, or the
+    direction s itself (the preconditioned steepest-descent direction) when
+    it happens on the first matvec.
+    Returns (v~, matvecs, residual inf-norm history, hit_max); ``pcg.neg_curv``
+    tells whether the last call stopped on nonpositive curvature.
     """
     tol = forcing_tolerance(float(np.abs(g).max()), forcing)
     limit = fixed_iters if fixed_iters > 0 else max_iters
@@ -419,10 +425,17 @@ def pcg(matvec, precond, g, *, fixed_iters=0, max_iters=100, forcing="superlinea
     hist = [float(np.abs(r).max())]
     its = 0
     converged = False
+    pcg.neg_curv = False
     while its < limit:
         hs = matvec(s)
         its += 1
-        kappa = rz / _dot(s, hs)
+        shs = _dot(s, hs)
+        if shs <= 0.0:
+            pcg.neg_curv = True
+            if its == 1:
+                vt = s.copy()
+            break
+        kappa = rz / shs
         vt = vt + kappa * s
         r = r - kappa * hs
         hist.append(float(np.abs(r).max()))
@@ -436,7 +449,7 @@ def pcg(matvec, precond, g, *, fixed_iters=0, max_iters=100, forcing="superlinea
         mu = rz_new / rz
         s = z + mu * s
         rz = rz_new
-    hit_max = fixed_iters <= 0 and not converged
+    hit_max = fixed_iters <= 0 and not converged and not pcg.neg_curv
     return vt, its, hist, hit_max
 
 

@@ -22,7 +22,7 @@ KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
 WARNINGS = {1: "gauss-newton max iterations", 2: "line search failed",
-            3: "pcg max iterations", 4: "det F <= 0"}
+            3: "pcg max iterations", 4: "det F <= 0", 5: "pcg nonpositive curvature"}
 
 
 class ClaireError(RuntimeError):

@@ -371,6 +371,7 @@ int ensure_solver_buffers(claire_ctx* c) {
 struct PcgResult {
     int its = 0;
     bool hit_max = false;
+    bool neg_curv = false;   // stopped on <s, Hs> <= 0
 };
 
 // PCG (Algorithm 2) on H v~ = -g with M = alpha L; v~^0 = 0. Stopping per
@@ -407,11 +408,17 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         ++res.its;
         CL_TRY(red_fetch(c->red, s));
         const double shs = c->red.host[0];
-        if (!(shs > 0.0) || !std::isfinite(shs)) {
-            // zero curvature along s: the residual is already zero in that direction
-            if (shs == 0.0) break;
-            set_error("PCG curvature <s, Hs> = %g is not positive", shs);
+        if (!std::isfinite(shs)) {
+            set_error("PCG curvature <s, Hs> = %g is not finite", shs);
             return CLAIRE_ENONFINITE;
+        }
+        if (shs <= 0.0) {
+            // nonpositive curvature (the discrete Gauss--Newton Hessian is
+            // semidefinite only up to discretisation error): truncated CG --
+            // keep the current step, or take s itself on the first direction
+            if (res.its == 1) CL_TRY(copy_d2d(c->vt, c->sd, n3, s));
+            res.neg_curv = true;
+            break;
         }
         const double kappa = rz / shs;
         // v~ += kappa s, r -= kappa Hs, with max|r| -> slot 1 and the residual's
@@ -430,7 +437,7 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }
-    if (!fixed && !converged && res.its >= limit) {
+    if (!fixed && !converged && !res.neg_curv && res.its >= limit) {
         // the last residual was not tested inside the loop
         CL_TRY(red_absmax(c->red, c->r, n3, 1, s));
         CL_TRY(red_fetch(c->red, s));
@@ -481,6 +488,7 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
             S.matvecs += pr.its;
             S.pde_solves += 2 * pr.its;
             if (pr.hit_max) { ++S.pcg_max_hits; note(CLAIRE_WPCGMAX); }
+            if (pr.neg_curv) note(CLAIRE_WNEGCURV);
             // Armijo line search on J(v + gamma v~). The regulariser is
             // quadratic: J_reg(v + gamma v~) = J_reg + gamma <aLv, v~> + gamma^2/2 <aLv~, v~>.
             CL_TRY(red_dot(c->red, c->grad, c->vt, n3, 3, s));

@@ -1,0 +1,132 @@
+"""The 512^3 configuration (134M voxels, nt = 8, H1, alpha 1e-3, band-limited
+v* with |k| <= 16) on one GPU, checked through properties that hold at any
+size (the FP64 oracle cannot hold this problem):
+
+* spectral gradient of a trigonometric polynomial equals its closed form;
+* transport by a velocity that moves whole voxels per time step equals a
+  periodic shift of the image (Section 2.5.2: every departure point is a grid
+  point and the cubic Lagrange weights are (0, 1, 0, 0); the float32 product
+  h_t v / h misses the integer by ~1e-7, hence a 1e-5 bar);
+* a constant image stays constant under transport by the workload's velocity;
+* the Hessian matvec is linear: H(2 v~) equals 2 H(v~) bit for bit (every
+  operation is linear and scaling by 2 commutes with float rounding), in the
+  float32 and the mixed path;
+* the solve runs and lowers the objective (the workload's own velocity is not
+  diffeomorphic on the grid at this band limit, so gtol is out of reach).
+"""
+import numpy as np
+import pytest
+
+from synthetic import WORKLOADS, bandlimited_velocity, ellipsoid_phantom, noise
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = WORKLOADS["ellipsoids512"]
+N = W["n"]
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_17493_amd import claire
+    return claire
+
+
+@pytest.fixture(scope="module")
+def data(C):
+    seed = W["seed"]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa
+    clean = dev(ellipsoid_phantom(N, seed))
+    vstar = dev(bandlimited_velocity(N, seed + 1000, W["kmax"], W["vmax"]))
+    m0 = clean + dev(noise(N, seed + 2000, W["noise"]))
+    m1 = C.transport(clean, vstar, W["nt"]) + dev(noise(N, seed + 3000, W["noise"]))
+    torch.cuda.synchronize()
+    return m0.contiguous(), m1.contiguous(), vstar
+
+
+def test_spectral_gradient_512(C):
+    n = N[0]
+    x = torch.arange(n, device="cuda", dtype=torch.float64) * (2 * np.pi / n)
+    c1, c2, c3 = torch.meshgrid(x, x, x, indexing="ij")
+    f = torch.sin(3 * c1) * torch.cos(5 * c2) + torch.sin(17 * c3 - c1)
+    g = [3 * torch.cos(3 * c1) * torch.cos(5 * c2) - torch.cos(17 * c3 - c1),
+         -5 * torch.sin(3 * c1) * torch.sin(5 * c2),
+         17 * torch.cos(17 * c3 - c1)]
+    with C.Context(N, 1, 1e-3, 1) as ctx:
+        out = ctx.spectral(C.OP_GRAD, f.float().contiguous())
+        err = max(float((out[a].double() - g[a]).abs().max()) for a in range(3)) / 17.0
+    del c1, c2, c3
+    print("512^3 spectral gradient: rel err %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_whole_voxel_transport_is_a_shift_512(C, data):
+    m0, _, _ = data
+    n, nt = N[0], W["nt"]
+    h = 2 * np.pi / n
+    shift = (2, -1, 3)                       # voxels per time step along x1, x2, x3
+    v = torch.empty((3,) + N, device="cuda")
+    for a in range(3):
+        v[a] = shift[a] * h * nt             # displacement v h_t / h = shift per step
+    out = C.transport(m0, v.contiguous(), nt)
+    # m(1)(x) = m0(x - nt shift): departure points lie upstream
+    ref = torch.roll(m0, shifts=tuple(s * nt for s in shift), dims=(0, 1, 2))
+    err = float((out - ref).abs().max() / ref.abs().max())
+    print("512^3 whole-voxel transport: rel err %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_constant_image_stays_constant_512(C, data):
+    _, _, vstar = data
+    m = torch.full(N, 0.7, device="cuda")
+    out = C.transport(m, vstar, W["nt"])
+    err = float((out - 0.7).abs().max())
+    print("512^3 constant transport: max err %.2e" % err)
+    assert err <= 1e-5        # nt = 8 steps of 64-term float32 sums of weights
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hessian_matvec_linear_512(C, data, precision):
+    m0, m1, vstar = data
+    with C.Context(N, W["nt"], W["alphas"][-1], W["reg_order"]) as ctx:
+        ctx.set_images(m0, m1)
+        ctx.set_precision(precision)
+        ctx.set_velocity((0.5 * vstar).contiguous())
+        vt = (0.3 * vstar).contiguous()
+        h1 = ctx.hessian_matvec(vt)
+        h2 = ctx.hessian_matvec((2 * vt).contiguous())
+        torch.cuda.synchronize()
+        assert torch.isfinite(h1).all()
+        assert torch.equal(h2, 2 * h1)
+        # Gauss--Newton: <v~, H v~> > 0
+        assert float((vt.double() * h1.double()).sum()) > 0
+
+
+def test_solve_512(C, data):
+    """The 512^3 workload's own velocity is not diffeomorphic on the grid (v*
+    with |k| <= 16 at max speed 1 has velocity gradients ~16: det F(v*) takes
+    non-positive values), so the solve is not expected to reach gtol; it must
+    run through (nonpositive curvature ends PCG as truncated CG instead of
+    failing) and lower the objective at every accepted step."""
+    m0, m1, vstar = data
+    with C.Context(N, W["nt"], W["alphas"][-1], W["reg_order"]) as ctx:
+        ctx.set_images(m0, m1)
+        ctx.set_velocity(vstar)
+        _, dstar = ctx.detdefgrad()
+        v = None
+        Js = []
+        for _ in range(2):
+            v, st = ctx.solve(v, gtol=W["gtol"], precision=1, max_gn=5, compute_det=1)
+            Js.append((st["J0"], st["J"]))
+            print("512^3 mixed solve, 5 GN steps: %d matvecs, %.2f s, J %.4f -> %.4f, rel_grad "
+                  "%.3f, det [%.3g, %.3g], status %d" % (
+                      st["matvecs"], st["seconds"], st["J0"], st["J"], st["rel_grad"],
+                      st["det_min"], st["det_max"], st["status"]))
+    print("det F(v*): min %.3g, max %.3g, %d voxels <= 0" % (dstar["min"], dstar["max"],
+                                                            dstar["nonpositive"]))
+    assert dstar["nonpositive"] > 0
+    for J0, J in Js:
+        assert np.isfinite(J) and J < J0
+    assert Js[1][1] < Js[0][1]

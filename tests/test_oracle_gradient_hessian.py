@@ -168,3 +168,26 @@ def test_gn_solve_invariants(p):
     assert stats.J < stats.J0 and stats.rel_mismatch < 0.5
     assert O.deformation_determinant(g, v, nt).min() > 0
     assert stats.pde_solves == 2 + 2 * stats.gn_iters + 2 * stats.matvecs + stats.ls_trials
+
+
+def test_pcg_stops_on_nonpositive_curvature():
+    """Truncated CG: <s, Hs> <= 0 stops PCG with the current iterate; on the
+    first direction the preconditioned steepest-descent direction is taken."""
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((3, 4, 4, 4))
+    ident = lambda r: r.copy()          # noqa: E731
+    # negative definite: the first curvature is negative
+    vt, its, _, hit = O.pcg(lambda s: -2.0 * s, ident, g)
+    assert its == 1 and O.pcg.neg_curv and not hit
+    assert np.array_equal(vt, -g)
+    # indefinite diagonal: positive curvature first, negative later
+    d = np.where(rng.random(g.shape) < 0.5, 1.0, -3.0)
+    d[0, 0, 0, 0] = 50.0
+    g2 = np.where(d > 0, 1.0, 1e-3) * rng.standard_normal(g.shape)
+    vt, its, _, _ = O.pcg(lambda s: d * s, ident, g2, fixed_iters=40)
+    assert O.pcg.neg_curv and 2 <= its < 40
+    vt_prev, _, _, _ = O.pcg(lambda s: d * s, ident, g2, fixed_iters=its - 1)
+    assert np.array_equal(vt, vt_prev)
+    # positive definite: unaffected
+    O.pcg(lambda s: 2.0 * s, ident, g)
+    assert not O.pcg.neg_curv
