@@ -133,7 +133,7 @@ __device__ __forceinline__ void stockham_stage(C* buf, int logN, int nb, int bs,
 }
 
 template <int DIR, int E, bool BMAJOR, typename C>
-__device__ void lds_fft(C* buf, int logN, int nb, int bs, int es, const C* tw, int logT, int tid) {
+__device__ __forceinline__ void lds_fft(C* buf, int logN, int nb, int bs, int es, const C* tw, int logT, int tid) {
     int logNs = 0;
     if (logN & 1) {
         stockham_stage<2, DIR, E, BMAJOR>(buf, logN, nb, bs, es, 0, tw, logT, tid);
@@ -203,15 +203,16 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
 }
 
 // ---------------------------------------------------------------- pass 5
-// rows of nh bins -> rows of n3 reals (x n3, unnormalised), + optional add;
-// DOT: also the block's share of <out, dotw> in float64 -> partial[block].
-template <int E, bool DOT>
+// rows of nh bins -> rows of n3 reals (x n3, unnormalised). AUX = 0: plain;
+// AUX = 1: + aux (addend); AUX = 2: also the block's share of <out, aux> in
+// float64 -> partial[block]. A thread's aux loads are all issued before its
+// first store.
+template <int E, int AUX>
 __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ in,
                                                      float* __restrict__ out,
-                                                     const float* __restrict__ add, int l3,
+                                                     const float* __restrict__ aux, int l3,
                                                      int RB, long long n, long long nspec,
                                                      const float2* __restrict__ tw, int logT,
-                                                     const float* __restrict__ dotw,
                                                      double* __restrict__ partial) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* tw_s = reinterpret_cast<float2*>(smem_raw);
@@ -240,20 +241,30 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     __syncthreads();
     lds_fft<+1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
     float2* dst = reinterpret_cast<float2*>(out + blockIdx.y * n) + row0 * M;
-    const float2* ad = add ? reinterpret_cast<const float2*>(add + blockIdx.y * n) + row0 * M : nullptr;
-    const float2* dw = DOT ? reinterpret_cast<const float2*>(dotw + blockIdx.y * n) + row0 * M
-                           : nullptr;
     double dot = 0.0;
-    for (int e = tid; e < RB * M; e += kThreads) {
-        float2 val = buf[e];
-        if (ad) { const float2 a = ad[e]; val.x += a.x; val.y += a.y; }
-        dst[e] = val;
-        if (DOT) {
-            const float2 d = dw[e];
-            dot += (double)val.x * d.x + (double)val.y * d.y;
+    if (AUX == 0) {
+        for (int e = tid; e < RB * M; e += kThreads) dst[e] = buf[e];
+    } else {
+        // all of this thread's aux loads in flight at once
+        const float2* ax = reinterpret_cast<const float2*>(aux + blockIdx.y * n) + row0 * M;
+        float2 pre[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RB * M) pre[i] = ax[e];
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RB * M) {
+                float2 val = buf[e];
+                if (AUX == 1) { val.x += pre[i].x; val.y += pre[i].y; }
+                dst[e] = val;
+                if (AUX == 2) dot += (double)val.x * pre[i].x + (double)val.y * pre[i].y;
+            }
         }
     }
-    if (DOT) {
+    if (AUX == 2) {
         __shared__ double sh[4];
         const double t = block_sum_256(dot, sh);
         if (tid == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = t;
@@ -526,15 +537,21 @@ int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, 
     const size_t sh = sizeof(float2) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
     if (dot_with) {
-        CL_TRY(allow_lds(k_c2r_x3<16, true>, sh));
-        hipLaunchKernelGGL((k_c2r_x3<16, true>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
-                           RB, g.n, g.nspec, w.tw, logT, dot_with, red->partial);
+        CL_TRY(allow_lds(k_c2r_x3<16, 2>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<16, 2>), grid, dim3(kThreads), sh, s, spec, out, dot_with,
+                           g.l3, RB, g.n, g.nspec, w.tw, logT, red->partial);
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)(grid.x * grid.y), 1, 0, slot, s);
     }
-    CL_TRY(allow_lds(k_c2r_x3<16, false>, sh));
-    hipLaunchKernelGGL((k_c2r_x3<16, false>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
-                       RB, g.n, g.nspec, w.tw, logT, nullptr, nullptr);
+    if (add) {
+        CL_TRY(allow_lds(k_c2r_x3<16, 1>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<16, 1>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
+                           RB, g.n, g.nspec, w.tw, logT, nullptr);
+    } else {
+        CL_TRY(allow_lds(k_c2r_x3<16, 0>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<16, 0>), grid, dim3(kThreads), sh, s, spec, out, nullptr,
+                           g.l3, RB, g.n, g.nspec, w.tw, logT, nullptr);
+    }
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -650,8 +667,8 @@ void spectral_free(SpectralWork& w) {
 int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in, float* out,
                    double alpha, int p, hipStream_t s, const float* add, const float* dot_with,
                    Reducer* red, int slot) {
-    if (dot_with && (mode != SPEC_REG_INV || !red)) {
-        set_error("fused dot product only with SPEC_REG_INV and a reducer");
+    if (dot_with && (mode != SPEC_REG_INV || !red || add)) {
+        set_error("fused dot product only with SPEC_REG_INV, a reducer and no addend");
         return CLAIRE_EINVAL;
     }
     Mult m;
