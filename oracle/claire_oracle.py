@@ -172,6 +172,38 @@ def spectral_divergence(grid, v):
     return _ifft(acc, grid.n)
 
 
+# 8th-order central differences (Section 2.5.3, "Differentiation": the
+# first-derivative stencil of the paper's GPU implementation), periodic:
+# d_i u(x_l) ~ (3 u_{l-4} - 32 u_{l-3} + 168 u_{l-2} - 672 u_{l-1}
+#               + 672 u_{l+1} - 168 u_{l+2} + 32 u_{l+3} - 3 u_{l+4}) / (840 h_i)
+FD8_WEIGHTS = ((1, 672.0), (2, -168.0), (3, 32.0), (4, -3.0))
+
+
+def fd8_derivative(grid, u, axis):
+    """FD8 first derivative of u along `axis` (0, 1, 2)."""
+    acc = 0.0
+    for s, c in FD8_WEIGHTS:
+        acc = acc + c * (np.roll(u, -s, axis=axis) - np.roll(u, s, axis=axis))
+    return acc / (840.0 * grid.h[axis])
+
+
+def fd8_gradient(grid, u):
+    return np.stack([fd8_derivative(grid, u, a) for a in range(3)])
+
+
+def fd8_divergence(grid, v):
+    return sum(fd8_derivative(grid, v[a], a) for a in range(3))
+
+
+def gradient(grid, u, deriv="spectral"):
+    """grad u with the chosen first-derivative discretisation."""
+    return fd8_gradient(grid, u) if deriv == "fd8" else spectral_gradient(grid, u)
+
+
+def divergence(grid, v, deriv="spectral"):
+    return fd8_divergence(grid, v) if deriv == "fd8" else spectral_divergence(grid, v)
+
+
 def apply_L(grid, u, p):
     """L u with L = (-Laplacian)^p (Section 2.2, regularisation operator)."""
     return _ifft(laplacian_power_symbol(grid, p) * _fft(u), grid.n)
@@ -307,9 +339,10 @@ def objective_parts(grid, m_final, m1, v, alpha, p):
     return dist, reg
 
 
-def setup_velocity(grid, m0, m1, v, alpha, nt, p):
+def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral"):
     """State, objective, adjoint and reduced gradient at v (Algorithm 1 lines
-    3-6; eqs. e:transport, e:varopt-claire, e:adjoint, e:rgrad)."""
+    3-6; eqs. e:transport, e:varopt-claire, e:adjoint, e:rgrad). ``deriv``
+    selects the gradient/divergence discretisation ("spectral" or "fd8")."""
     st = VelocityState(grid=grid, nt=nt, alpha=alpha, p=p,
                        v=np.asarray(v, dtype=np.float64),
                        m0=np.asarray(m0, dtype=np.float64),
@@ -320,8 +353,8 @@ def setup_velocity(grid, m0, m1, v, alpha, nt, p):
     st.m = solve_state(st.m0, st.d_plus, nt)
     st.J_dist, st.J_reg = objective_parts(grid, st.m[-1], st.m1, st.v, alpha, p)
     st.J = st.J_dist + st.J_reg
-    st.grad_m = [spectral_gradient(grid, mj) for mj in st.m]
-    st.div_v = spectral_divergence(grid, st.v)
+    st.grad_m = [gradient(grid, mj, deriv) for mj in st.m]
+    st.div_v = divergence(grid, st.v, deriv)
     st.div_v_dep = interpolate(st.div_v, st.d_minus)
     lam = [None] * (nt + 1)
     lam[nt] = -(st.m[-1] - st.m1)                       # final condition (e:adjfinal)
@@ -469,7 +502,7 @@ class SolveStats:
 
 def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
              max_gn=50, max_pcg=100, fixed_pcg=0, forcing="superlinear",
-             c1=1e-4, max_ls=16):
+             c1=1e-4, max_ls=16, deriv="spectral"):
     """Inexact Gauss--Newton--Krylov with Armijo line search (Algorithm 1),
     run once per regularisation weight in ``alphas`` (parameter continuation,
     Section 2.6: each level starts from the previous level's velocity and
@@ -485,7 +518,7 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
     m1 = np.asarray(m1, dtype=np.float64)
     mismatch0 = np.sqrt(np.sum((m0 - m1) ** 2))
     for li, alpha in enumerate(alphas):
-        st = setup_velocity(grid, m0, m1, v, alpha, nt, p)
+        st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv)
         stats.pde_solves += 2
         if li == 0:
             stats.J0 = st.J
@@ -523,7 +556,7 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
                 stats.warnings.append("linesearch")
                 break
             v = v_trial
-            st = setup_velocity(grid, m0, m1, v, alpha, nt, p)
+            st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv)
             stats.pde_solves += 2
             k += 1
             stats.gn_iters += 1
@@ -537,14 +570,14 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
 # ----------------------------------------------------------------------------
 # deformation gradient (eq. e:def-grad, appendix)
 # ----------------------------------------------------------------------------
-def deformation_gradient(grid, v, nt):
+def deformation_gradient(grid, v, nt, deriv="spectral"):
     """F(1) from d_t F + (v.grad) F = (grad v) F, F(0) = I, by SL with RK2 along
     the characteristics of v. Returns F as [3][3][n1][n2][n3] with
     (grad v)_{ab} = d_b v_a."""
     ht = 1.0 / nt
     v = np.asarray(v, dtype=np.float64)
     d_plus = departure_displacement(grid, v, nt, +1)
-    G = np.stack([spectral_gradient(grid, v[a]) for a in range(3)])   # [a][b]
+    G = np.stack([gradient(grid, v[a], deriv) for a in range(3)])   # [a][b]
     G_dep = interpolate(G.reshape((9,) + grid.n), d_plus).reshape(G.shape)
     F = np.zeros((3, 3) + grid.n)
     for a in range(3):
@@ -565,6 +598,6 @@ def det3(F):
             + F[0, 2] * (F[1, 0] * F[2, 1] - F[1, 1] * F[2, 0]))
 
 
-def deformation_determinant(grid, v, nt):
+def deformation_determinant(grid, v, nt, deriv="spectral"):
     """det F(1), the surrogate for det grad y (appendix, deformation gradient)."""
-    return det3(deformation_gradient(grid, v, nt))
+    return det3(deformation_gradient(grid, v, nt, deriv))

@@ -114,3 +114,65 @@ def test_fft_convention_matches_brute_force_dft():
     uh = np.einsum("kz,abz->abk", E, u)
     du = np.einsum("zk,abk->abz", np.conj(E).T, 1j * k3 * uh).real / n[2]
     assert np.abs(O.spectral_gradient(g, u)[2] - du).max() < 1e-12
+
+
+# ---------------------------------------------------------------- FD8
+def test_fd8_exact_on_polynomials_up_to_degree_8():
+    """The 8th-order central stencil differentiates polynomials of degree <= 8
+    exactly (away from the periodic wrap); at degree 9 it is off by its
+    leading truncation term."""
+    n = 32
+    g = O.Grid((n, n, n))
+    x = np.arange(n, dtype=np.float64) * g.h[0]
+    X1, X2, X3 = np.meshgrid(x, x, x, indexing="ij")
+    inner = (slice(5, n - 5),) * 3
+    c = 1.3
+    for deg in range(1, 9):
+        u = (X2 - c) ** deg
+        du = O.fd8_derivative(g, u, 1)
+        exact = deg * (X2 - c) ** (deg - 1)
+        scale = np.abs(exact[inner]).max()
+        assert np.abs(du[inner] - exact[inner]).max() <= 1e-10 * scale, deg
+    # degree 9: the error is the leading truncation term -h^8 f^(9) / 630
+    u = (X3 - c) ** 9
+    du = O.fd8_derivative(g, u, 2)
+    exact = 9 * (X3 - c) ** 8
+    lead = -(g.h[2] ** 8) * 362880.0 / 630.0
+    assert np.allclose(du[inner] - exact[inner], lead, rtol=1e-5, atol=0)
+
+
+def test_fd8_modified_wavenumber():
+    """On exp(i k x) the stencil acts as i s(k h) / h with
+    s(t) = (1344 sin t - 336 sin 2t + 64 sin 3t - 6 sin 4t) / 840."""
+    n = (16, 24, 32)
+    g = O.Grid(n)
+    x = np.arange(n[2]) * g.h[2]
+    for k in (1, 3, 7, 15):
+        u = np.broadcast_to(np.sin(k * x), n).copy()
+        t = k * g.h[2]
+        s = (1344 * np.sin(t) - 336 * np.sin(2 * t) + 64 * np.sin(3 * t) - 6 * np.sin(4 * t)) / 840
+        expect = (s / g.h[2]) * np.broadcast_to(np.cos(k * x), n)
+        assert np.allclose(O.fd8_derivative(g, u, 2), expect, atol=1e-12)
+
+
+def test_fd8_eighth_order_convergence():
+    errs = []
+    for n in (16, 32):
+        g = O.Grid((n, n, n))
+        x = np.arange(n) * g.h[0]
+        X1 = np.meshgrid(x, x, x, indexing="ij")[0]
+        errs.append(np.abs(O.fd8_derivative(g, np.sin(2 * X1), 0) - 2 * np.cos(2 * X1)).max())
+    assert 200 < errs[0] / errs[1] < 300       # 2^8 = 256
+
+
+def test_fd8_divergence_is_minus_adjoint_of_gradient():
+    rng = np.random.default_rng(4)
+    g = O.Grid((8, 12, 16))
+    u = rng.standard_normal(g.n)
+    v = rng.standard_normal((3,) + g.n)
+    lhs = g.inner(O.fd8_divergence(g, v), u)
+    rhs = -sum(g.inner(v[a], O.fd8_gradient(g, u)[a]) for a in range(3))
+    assert np.isclose(lhs, rhs, rtol=1e-12)
+    # dispatch
+    assert np.array_equal(O.gradient(g, u, "fd8"), O.fd8_gradient(g, u))
+    assert np.array_equal(O.divergence(g, v, "spectral"), O.spectral_divergence(g, v))
