@@ -79,7 +79,15 @@ typedef struct claire_opts {
                                    extra state + adjoint solve per level) instead of the
                                    gradient at the initial guess, so a warm-started solve
                                    stops at the same gradient norm as one from v = 0 */
+    int derivative;             /* first derivatives (grad m, div v, grad v):
+                                   CLAIRE_DERIV_SPECTRAL (default) or CLAIRE_DERIV_FD8 */
 } claire_opts;
+
+/* First-derivative discretisations (Section 2.5.3): Fourier differentiation,
+ * or the 8th-order central finite differences of the paper's GPU code,
+ * (3, -32, 168, -672, 0, 672, -168, 32, -3) / (840 h), periodic. Higher-order
+ * operators (alpha L and its inverse) are spectral in both. */
+enum { CLAIRE_DERIV_SPECTRAL = 0, CLAIRE_DERIV_FD8 = 1 };
 
 /* Statistics of a solve (row labels of the paper's result tables). */
 typedef struct claire_stats {
@@ -151,6 +159,12 @@ int claire_ctx_hessian_matvec(claire_ctx *ctx, const float *vt, float *Hvt);
  * set_velocity again). */
 int claire_ctx_set_precision(claire_ctx *ctx, int precision);
 
+/* Select the first-derivative discretisation (CLAIRE_DERIV_SPECTRAL or
+ * CLAIRE_DERIV_FD8, Section 2.5.3) of grad m^j and div v in later
+ * set_velocity calls and of grad v in detdefgrad. Invalidates the cached
+ * setup. */
+int claire_ctx_set_derivative(claire_ctx *ctx, int derivative);
+
 /* Regularisation preconditioner z = (alpha L)^{-1} r, k = 0 mode passed
  * through (Sections 2.5.5-2.5.6). r, z: [3][n]; may alias. */
 int claire_ctx_precond(claire_ctx *ctx, const float *r, float *z);
@@ -176,8 +190,11 @@ int claire_ctx_detdefgrad(claire_ctx *ctx, double *det_out, double stats[4]);
  *   CLAIRE_OP_DIV      in [3][n] -> out [n]     divergence
  *   CLAIRE_OP_REG      in [3][n] -> out [3][n]  alpha L
  *   CLAIRE_OP_REG_INV  in [3][n] -> out [3][n]  (alpha L)^{-1}, k = 0 passed through
+ *   CLAIRE_OP_FD8_GRAD in [n]    -> out [3][n]  grad by FD8 central differences
+ *   CLAIRE_OP_FD8_DIV  in [3][n] -> out [n]     divergence by FD8
  * in and out must not overlap. */
-enum { CLAIRE_OP_GRAD = 0, CLAIRE_OP_DIV = 1, CLAIRE_OP_REG = 2, CLAIRE_OP_REG_INV = 3 };
+enum { CLAIRE_OP_GRAD = 0, CLAIRE_OP_DIV = 1, CLAIRE_OP_REG = 2, CLAIRE_OP_REG_INV = 3,
+       CLAIRE_OP_FD8_GRAD = 4, CLAIRE_OP_FD8_DIV = 5 };
 int claire_ctx_spectral(claire_ctx *ctx, int op, const float *in, float *out);
 
 /* Tricubic Lagrange interpolation (Section 2.5.4, p = 3):

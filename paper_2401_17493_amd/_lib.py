@@ -34,6 +34,7 @@ class ClaireOpts(ctypes.Structure):
         ("n_levels", c_int),
         ("compute_det", c_int),
         ("tol_from_zero", c_int),
+        ("derivative", c_int),
     ]
 
 
@@ -73,6 +74,7 @@ SIGNATURES = {
     "claire_ctx_hessian_matvec": (c_int, [c_void_p, c_void_p, c_void_p]),
     "claire_ctx_precond": (c_int, [c_void_p, c_void_p, c_void_p]),
     "claire_ctx_set_precision": (c_int, [c_void_p, c_int]),
+    "claire_ctx_set_derivative": (c_int, [c_void_p, c_int]),
     "claire_ctx_solve": (c_int, [c_void_p, ctypes.POINTER(ClaireOpts), c_void_p,
                                  ctypes.POINTER(ClaireStats)]),
     "claire_ctx_detdefgrad": (c_int, [c_void_p, c_void_p, c_double_p]),

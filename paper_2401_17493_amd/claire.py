@@ -17,7 +17,8 @@ import torch
 
 from . import _lib as L
 
-OP_GRAD, OP_DIV, OP_REG, OP_REG_INV = 0, 1, 2, 3
+OP_GRAD, OP_DIV, OP_REG, OP_REG_INV, OP_FD8_GRAD, OP_FD8_DIV = 0, 1, 2, 3, 4, 5
+DERIV_SPECTRAL, DERIV_FD8 = 0, 1
 KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE = range(5)
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
@@ -127,6 +128,10 @@ class Context:
         """0: float32 matvec storage; 1: float16 storage in the Hessian matvec."""
         _check(self.lib.claire_ctx_set_precision(self._h, int(precision)))
 
+    def set_derivative(self, derivative: int):
+        """DERIV_SPECTRAL or DERIV_FD8 for grad m^j, div v (and grad v in detdefgrad)."""
+        _check(self.lib.claire_ctx_set_derivative(self._h, int(derivative)))
+
     def set_images(self, m0: torch.Tensor, m1: torch.Tensor):
         _check(self.lib.claire_ctx_set_images(self._h, _ptr(m0, self.n, "m0"),
                                               _ptr(m1, self.n, "m1")))
@@ -179,7 +184,8 @@ class Context:
 
     def spectral(self, op: int, x: torch.Tensor) -> torch.Tensor:
         shapes = {OP_GRAD: (self.n, self.vshape), OP_DIV: (self.vshape, self.n),
-                  OP_REG: (self.vshape, self.vshape), OP_REG_INV: (self.vshape, self.vshape)}
+                  OP_REG: (self.vshape, self.vshape), OP_REG_INV: (self.vshape, self.vshape),
+                  OP_FD8_GRAD: (self.n, self.vshape), OP_FD8_DIV: (self.vshape, self.n)}
         sin, sout = shapes[op]
         out = self._new(sout)
         _check(self.lib.claire_ctx_spectral(self._h, int(op), _ptr(x, sin, "in"),

@@ -100,6 +100,7 @@ struct claire_ctx {
     float* vtrial = nullptr;
     float* als = nullptr;    // alpha L s, kept by recursion inside PCG
 
+    int deriv = CLAIRE_DERIV_SPECTRAL;   // first-derivative discretisation
     bool have_images = false;
     bool state_valid = false;      // dp, dm, m valid for the content of v
     bool have_velocity = false;    // full setup done: gm, A, g, J valid
@@ -205,6 +206,16 @@ int ensure_half_buffers(claire_ctx* c) {
 
 // Full per-velocity setup; the state is reused when state_valid says the
 // backtrace and m^j already belong to c->v (accepted line-search trial).
+// First derivatives with the context's discretisation (Section 2.5.3).
+int ctx_grad(claire_ctx* c, const float* u, float* out) {
+    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_grad(c->g, u, out, c->s);
+    return spectral_apply(c->g, c->sw, SPEC_GRAD, u, out, c->alpha, c->p, c->s);
+}
+int ctx_div(claire_ctx* c, const float* v, float* out) {
+    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_div(c->g, v, out, c->s);
+    return spectral_apply(c->g, c->sw, SPEC_DIV, v, out, c->alpha, c->p, c->s);
+}
+
 int run_setup(claire_ctx* c) {
     const Geo& g = c->g;
     const long long n = g.n;
@@ -217,10 +228,9 @@ int run_setup(claire_ctx* c) {
     CL_TRY(red_dot(c->red, c->regv, c->v, 3 * n, 1, c->s));
     // grad m^j (Section 2.5.3; stored, not recomputed per matvec)
     for (int j = 0; j <= nt; ++j)
-        CL_TRY(spectral_apply(g, c->sw, SPEC_GRAD, c->m + (long long)j * n,
-                              c->gm + (long long)j * 3 * n, c->alpha, c->p, c->s));
+        CL_TRY(ctx_grad(c, c->m + (long long)j * n, c->gm + (long long)j * 3 * n));
     // div v and the adjoint step factor
-    CL_TRY(spectral_apply(g, c->sw, SPEC_DIV, c->v, c->divv, c->alpha, c->p, c->s));
+    CL_TRY(ctx_div(c, c->v, c->divv));
     CL_TRY(launch_make_A(g, c->divv, c->dm, c->A, ht, c->s, c->box_m));
     // adjoint (eq. e:adjoint): lam^nt = -(m^nt - m1), lam^j = A lam^{j+1}(y-)
     CL_TRY(launch_final_adjoint(g, c->m + nt * n, c->m1, c->lam + nt * n, c->s));
@@ -594,6 +604,7 @@ void claire_opts_default(claire_opts* o) {
     o->n_levels = 0;
     o->compute_det = 0;
     o->tol_from_zero = 0;
+    o->derivative = CLAIRE_DERIV_SPECTRAL;
 }
 
 const char* claire_last_error(void) { return g_err; }
@@ -716,12 +727,31 @@ int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
         set_error("invalid solver limits");
         return CLAIRE_EINVAL;
     }
+    if (o.derivative != CLAIRE_DERIV_SPECTRAL && o.derivative != CLAIRE_DERIV_FD8) {
+        set_error("derivative must be CLAIRE_DERIV_SPECTRAL or CLAIRE_DERIV_FD8");
+        return CLAIRE_EINVAL;
+    }
     const int saved = c->precision;
+    const int saved_deriv = c->deriv;
     c->precision = o.precision;
+    c->deriv = o.derivative;
     const int rc = run_solve(c, o, v_inout, stats);
     c->precision = saved;
+    if (c->deriv != saved_deriv) c->have_velocity = false;   // setup used the other operators
+    c->deriv = saved_deriv;
     if (saved == 1 && o.precision != 1) c->have_velocity = false;   // half copies not made
     return rc;
+}
+
+int claire_ctx_set_derivative(claire_ctx* c, int derivative) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    if (derivative != CLAIRE_DERIV_SPECTRAL && derivative != CLAIRE_DERIV_FD8) {
+        set_error("derivative must be CLAIRE_DERIV_SPECTRAL or CLAIRE_DERIV_FD8");
+        return CLAIRE_EINVAL;
+    }
+    if (derivative != c->deriv) c->have_velocity = false;   // redo the setup
+    c->deriv = derivative;
+    return 0;
 }
 
 int claire_ctx_set_precision(claire_ctx* c, int precision) {
@@ -766,8 +796,7 @@ int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {
     }
     const double ht = 1.0 / c->nt;
     for (int a = 0; a < 3 && rc >= 0; ++a)
-        rc = spectral_apply(g, c->sw, SPEC_GRAD, c->v + (long long)a * n, G + (long long)a * 3 * n,
-                            c->alpha, c->p, c->s);
+        rc = ctx_grad(c, c->v + (long long)a * n, G + (long long)a * 3 * n);
     for (int q = 0; q < 9 && rc >= 0; ++q)
         rc = launch_interp(g, G + (long long)q * n, 1, c->dp, Gy + (long long)q * n, c->s, c->box_p);
     if (rc >= 0) rc = launch_defgrad_update(g, nullptr, Gy, G, F, ht, c->s);
@@ -797,6 +826,8 @@ int claire_ctx_spectral(claire_ctx* c, int op, const float* in, float* out) {
     CL_TRY(check_ptr(in, "in"));
     CL_TRY(check_ptr(out, "out"));
     if (in == out) { set_error("in and out must not overlap"); return CLAIRE_EINVAL; }
+    if (op == CLAIRE_OP_FD8_GRAD) return launch_fd8_grad(c->g, in, out, c->s);
+    if (op == CLAIRE_OP_FD8_DIV) return launch_fd8_div(c->g, in, out, c->s);
     SpecMode m;
     switch (op) {
     case CLAIRE_OP_GRAD: m = SPEC_GRAD; break;

@@ -74,6 +74,11 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
                    const float* add = nullptr, const float* dot_with = nullptr,
                    Reducer* red = nullptr, int slot = 0);
 
+// ----------------------------------------------- finite differences
+// FD8 gradient (1 -> 3 fields) and divergence (3 -> 1), periodic.
+int launch_fd8_grad(const Geo& g, const float* u, float* out, hipStream_t s);
+int launch_fd8_div(const Geo& g, const float* v, float* out, hipStream_t s);
+
 // ------------------------------------------------------ semi-Lagrangian
 // Single-field gathers accept an optional per-brick box table of their
 // departure field (from launch_brick_boxes); NULL computes the boxes inline.
