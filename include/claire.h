@@ -81,7 +81,23 @@ typedef struct claire_opts {
                                    stops at the same gradient norm as one from v = 0 */
     int derivative;             /* first derivatives (grad m, div v, grad v):
                                    CLAIRE_DERIV_SPECTRAL (default) or CLAIRE_DERIV_FD8 */
+    int precond;                /* PCG preconditioner (Section 2.5.6):
+                                   CLAIRE_PRECOND_REG (default) or CLAIRE_PRECOND_TWOLEVEL */
 } claire_opts;
+
+/* Preconditioners of the reduced Hessian (Section 2.5.6): the inverse of the
+ * regularisation operator, (alpha L)^{-1} with the k = 0 mode passed through;
+ * or the two-level zero-velocity preconditioner
+ *   P = R^{-1/2} [Q_P F_L K0_c^{-1} Q_R F_L + F_H] R^{-1/2},
+ * R = alpha L (k = 0 mode passed through), F_L / F_H spectral cut-off
+ * filters below / at or above the Nyquist of the grid of half the extents,
+ * Q_R / Q_P spectral restriction to / prolongation from that grid, and
+ * K0_c = R_c^{-1/2} (alpha L + grad m(1) grad m(1)^T) R_c^{-1/2} on it
+ * (k = 0 handled as the identity on the mean), the zero-velocity Hessian at
+ * the current state m(t = 1), inverted by CG to a tenth of the outer PCG
+ * forcing eta (Section 2.6 settings), at most 200 iterations. Needs every
+ * extent >= 16. */
+enum { CLAIRE_PRECOND_REG = 0, CLAIRE_PRECOND_TWOLEVEL = 1 };
 
 /* First-derivative discretisations (Section 2.5.3): Fourier differentiation,
  * or the 8th-order central finite differences of the paper's GPU code,
@@ -104,6 +120,7 @@ typedef struct claire_stats {
     double det_min, det_mean, det_max; /* det F(1), when compute_det = 1 */
     long long det_nonpositive;  /* voxels with det F(1) <= 0 */
     double seconds;             /* wall time of the solve (host clock) */
+    int inner_iters;            /* coarse CG iterations of the two-level preconditioner */
 } claire_stats;
 
 typedef struct claire_ctx claire_ctx;
@@ -168,6 +185,17 @@ int claire_ctx_set_derivative(claire_ctx *ctx, int derivative);
 /* Regularisation preconditioner z = (alpha L)^{-1} r, k = 0 mode passed
  * through (Sections 2.5.5-2.5.6). r, z: [3][n]; may alias. */
 int claire_ctx_precond(claire_ctx *ctx, const float *r, float *z);
+
+/* Two-level zero-velocity preconditioner z = P r (CLAIRE_PRECOND_TWOLEVEL
+ * above) at the state of the last set_velocity: the coarse operator uses its
+ * grad m(t = 1). The inner CG on K0_c runs from zero until its residual's
+ * 2-norm falls to inner_rtol times the right-hand side's, or for max_inner
+ * iterations (1..1000); *inner_iters (host, may be NULL) receives the count.
+ * r, z: [3][n], must not overlap. Allocates the coarse workspace (about
+ * 4 n floats) on first use; synchronises the stream once per
+ * inner iteration. Needs every extent >= 16. */
+int claire_ctx_precond_twolevel(claire_ctx *ctx, const float *r, float *z, double inner_rtol,
+                                int max_inner, int *inner_iters);
 
 /* Gauss--Newton--Krylov solve (Algorithm 1 with Algorithm 2 inside) from the
  * initial guess in v_inout ([3][n]); the solution overwrites it. opts and

@@ -35,6 +35,7 @@ class ClaireOpts(ctypes.Structure):
         ("compute_det", c_int),
         ("tol_from_zero", c_int),
         ("derivative", c_int),
+        ("precond", c_int),
     ]
 
 
@@ -54,6 +55,7 @@ class ClaireStats(ctypes.Structure):
         ("det_max", c_double),
         ("det_nonpositive", ctypes.c_longlong),
         ("seconds", c_double),
+        ("inner_iters", c_int),
     ]
 
     def as_dict(self):
@@ -73,6 +75,8 @@ SIGNATURES = {
     "claire_ctx_objective": (c_int, [c_void_p, c_void_p, c_double_p]),
     "claire_ctx_hessian_matvec": (c_int, [c_void_p, c_void_p, c_void_p]),
     "claire_ctx_precond": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "claire_ctx_precond_twolevel": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int,
+                                            c_void_p]),
     "claire_ctx_set_precision": (c_int, [c_void_p, c_int]),
     "claire_ctx_set_derivative": (c_int, [c_void_p, c_int]),
     "claire_ctx_solve": (c_int, [c_void_p, ctypes.POINTER(ClaireOpts), c_void_p,

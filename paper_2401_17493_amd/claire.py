@@ -19,6 +19,7 @@ from . import _lib as L
 
 OP_GRAD, OP_DIV, OP_REG, OP_REG_INV, OP_FD8_GRAD, OP_FD8_DIV = 0, 1, 2, 3, 4, 5
 DERIV_SPECTRAL, DERIV_FD8 = 0, 1
+PRECOND_REG, PRECOND_TWOLEVEL = 0, 1
 KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE = range(5)
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
@@ -161,6 +162,17 @@ class Context:
         _check(self.lib.claire_ctx_precond(self._h, _ptr(r, self.vshape, "r"),
                                            _ptr(out, self.vshape, "z")))
         return out
+
+    def precond_twolevel(self, r: torch.Tensor, inner_rtol: float, max_inner: int = 200,
+                         out: Optional[torch.Tensor] = None):
+        """Two-level zero-velocity preconditioner z = P r at the last
+        set_velocity's state; returns (z, inner CG iterations)."""
+        out = self._new(self.vshape) if out is None else out
+        its = ctypes.c_int(0)
+        _check(self.lib.claire_ctx_precond_twolevel(
+            self._h, _ptr(r, self.vshape, "r"), _ptr(out, self.vshape, "z"), float(inner_rtol),
+            int(max_inner), ctypes.byref(its)))
+        return out, its.value
 
     def solve(self, v0: Optional[torch.Tensor] = None, **opts):
         o = default_opts(reg_order=self.reg_order, **opts)

@@ -89,6 +89,7 @@ struct claire_ctx {
     bool half_valid = false; // gm16 belongs to the current setup
     SpectralWork sw;
     Reducer red;
+    TwoLevel tl;             // two-level preconditioner, allocated on first use
     int* flag = nullptr;     // device int (non-finite check)
 
     // solver vectors (allocated on first solve)
@@ -172,6 +173,7 @@ void ctx_release(claire_ctx* c) {
     dfree(c->box_m);
     spectral_free(c->sw);
     reducer_free(c->red);
+    twolevel_free(c->tl);
 }
 
 int copy_d2d(float* dst, const float* src, long long count, hipStream_t s) {
@@ -380,18 +382,22 @@ int ensure_solver_buffers(claire_ctx* c) {
 
 struct PcgResult {
     int its = 0;
+    int inner = 0;           // coarse CG iterations of the two-level preconditioner
     bool hit_max = false;
     bool neg_curv = false;   // stopped on <s, Hs> <= 0
 };
 
-// PCG (Algorithm 2) on H v~ = -g with M = alpha L; v~^0 = 0. Stopping per
-// Section 2.5.5: ||r||_inf <= eta ||g||_inf, or a fixed number of matvecs.
+// PCG (Algorithm 2) on H v~ = -g; v~^0 = 0. Stopping per Section 2.5.5:
+// ||r||_inf <= eta ||g||_inf, or a fixed number of matvecs.
 //
-// The regularisation part of H s needs no FFT here: with z = (alpha L)^{-1} r
-// (mean passed through), alpha L z = r - mean(r), so the directions
-// s_{l+1} = z_{l+1} + mu s_l satisfy
+// With M = alpha L the regularisation part of H s needs no FFT: with
+// z = (alpha L)^{-1} r (mean passed through), alpha L z = r - mean(r), so the
+// directions s_{l+1} = z_{l+1} + mu s_l satisfy
 //   alpha L s_{l+1} = (r_{l+1} - mean(r_{l+1})) + mu alpha L s_l,
 // which is carried along in c->als; only the data part of H s is computed.
+// With the two-level preconditioner (Section 2.5.6) the matvec computes
+// alpha L s itself, and the coarse operator takes grad m(1) of the current
+// iterate, restricted once per PCG solve; its inner CG runs to a tenth of eta.
 int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     const long long n = c->g.n, n3 = 3 * n;
     const hipStream_t s = c->s;
@@ -400,21 +406,38 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     const double tol = eta * gn;
     const bool fixed = o.fixed_pcg_iters > 0;
     const int limit = fixed ? o.fixed_pcg_iters : o.max_pcg;
+    const bool two = o.precond == CLAIRE_PRECOND_TWOLEVEL;
+    res = PcgResult();
+    if (two) {
+        CL_TRY(twolevel_init(c->tl, c->g));
+        CL_TRY(twolevel_setup(c->tl, c->g, c->sw, c->gm + (long long)c->nt * n3, s));
+    }
+    // z = M^{-1} r and <z, r> -> slot
+    auto precond = [&](int slot) -> int {
+        if (!two)
+            return spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s,
+                                  nullptr, c->r, &c->red, slot);
+        int its = 0;
+        CL_TRY(twolevel_apply(c->tl, c->g, c->sw, c->r, c->z, c->alpha, c->p, 0.1 * eta,
+                              kMaxInner, &its, s));
+        res.inner += its;
+        return red_dot(c->red, c->z, c->r, n3, slot, s);
+    };
     CL_TRY(launch_fill(c->vt, 0.f, n3, s));
     CL_TRY(launch_scale_copy(c->grad, c->r, -1.f, n3, s));
-    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s, nullptr,
-                          c->r, &c->red, 0));   // z and <z, r> -> slot 0
+    CL_TRY(precond(0));   // z and <z, r> -> slot 0
     CL_TRY(copy_d2d(c->sd, c->z, n3, s));
     for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
     CL_TRY(red_fetch(c->red, s));
     double rz = c->red.host[0];
     double mean[3] = {c->red.host[3] / n, c->red.host[4] / n, c->red.host[5] / n};
-    CL_TRY(launch_fill(c->als, 0.f, n3, s));
-    CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
-    res = PcgResult();
+    if (!two) {
+        CL_TRY(launch_fill(c->als, 0.f, n3, s));
+        CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
+    }
     bool converged = false;
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, c->als, 0));   // also <s, Hs> -> slot 0
+        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
         ++res.its;
         CL_TRY(red_fetch(c->red, s));
         const double shs = c->red.host[0];
@@ -436,15 +459,14 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(pcg_update(c->red, c->sd, c->hs, c->vt, c->r, (float)kappa, n, 1, 3, s));
         if (res.its == limit) break;
         // preconditioned residual and <z, r>: one host round trip with the above
-        CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG_INV, c->r, c->z, c->alpha, c->p, s,
-                              nullptr, c->r, &c->red, 2));   // z and <z, r> -> slot 2
+        CL_TRY(precond(2));   // z and <z, r> -> slot 2
         CL_TRY(red_fetch(c->red, s));
         if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
         const double rz_new = c->red.host[2];
         const double mu = rz_new / rz;
         for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
         CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
-        CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
+        if (!two) CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }
     if (!fixed && !converged && !res.neg_curv && res.its >= limit) {
@@ -496,6 +518,7 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
             PcgResult pr;
             CL_TRY(run_pcg(c, o, pr));
             S.matvecs += pr.its;
+            S.inner_iters += pr.inner;
             S.pde_solves += 2 * pr.its;
             if (pr.hit_max) { ++S.pcg_max_hits; note(CLAIRE_WPCGMAX); }
             if (pr.neg_curv) note(CLAIRE_WNEGCURV);
@@ -605,6 +628,7 @@ void claire_opts_default(claire_opts* o) {
     o->compute_det = 0;
     o->tol_from_zero = 0;
     o->derivative = CLAIRE_DERIV_SPECTRAL;
+    o->precond = CLAIRE_PRECOND_REG;
 }
 
 const char* claire_last_error(void) { return g_err; }
@@ -708,6 +732,26 @@ int claire_ctx_precond(claire_ctx* c, const float* r, float* z) {
     return spectral_apply(c->g, c->sw, SPEC_REG_INV, r, z, c->alpha, c->p, c->s);
 }
 
+int claire_ctx_precond_twolevel(claire_ctx* c, const float* r, float* z, double inner_rtol,
+                                int max_inner, int* inner_iters) {
+    CL_TRY(need(c, true));
+    CL_TRY(check_ptr(r, "r"));
+    CL_TRY(check_ptr(z, "z"));
+    if (r == z) { set_error("r and z must not overlap"); return CLAIRE_EINVAL; }
+    if (!(inner_rtol >= 0.0) || max_inner < 1 || max_inner > 1000) {
+        set_error("need inner_rtol >= 0 and 1 <= max_inner <= 1000");
+        return CLAIRE_EINVAL;
+    }
+    CL_TRY(twolevel_init(c->tl, c->g));
+    CL_TRY(twolevel_setup(c->tl, c->g, c->sw, c->gm + (long long)c->nt * 3 * c->g.n, c->s));
+    int its = 0;
+    CL_TRY(twolevel_apply(c->tl, c->g, c->sw, r, z, c->alpha, c->p, inner_rtol, max_inner, &its,
+                          c->s));
+    CL_HIP(hipStreamSynchronize(c->s));
+    if (inner_iters) *inner_iters = its;
+    return 0;
+}
+
 int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
                      claire_stats* stats) {
     CL_TRY(need(c, false));
@@ -731,6 +775,11 @@ int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
         set_error("derivative must be CLAIRE_DERIV_SPECTRAL or CLAIRE_DERIV_FD8");
         return CLAIRE_EINVAL;
     }
+    if (o.precond != CLAIRE_PRECOND_REG && o.precond != CLAIRE_PRECOND_TWOLEVEL) {
+        set_error("precond must be CLAIRE_PRECOND_REG or CLAIRE_PRECOND_TWOLEVEL");
+        return CLAIRE_EINVAL;
+    }
+    if (o.precond == CLAIRE_PRECOND_TWOLEVEL) CL_TRY(twolevel_init(c->tl, c->g));
     const int saved = c->precision;
     const int saved_deriv = c->deriv;
     c->precision = o.precision;

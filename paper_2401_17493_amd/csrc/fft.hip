@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         }
     };
 
-    if (MODE == SPEC_REG_INV) {
+    if (MODE == SPEC_REG_INV || MODE == SPEC_REG_ISQRT) {
         const int comp = blockIdx.z;
         load_tile(A, in + comp * nspec);
         __syncthreads();
@@ -420,7 +420,9 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         for (int e = tid; e < N * CW; e += kThreads) {
             const int r = e / CW, c = e - r * CW;
             const float sym = (float)reg_symbol(m.p, signed_k(r, m.n1), k2, c0 + c);
-            const float f = (sym == 0.f) ? norm : norm / (alpha * sym);
+            const float f = (sym == 0.f) ? norm
+                            : (MODE == SPEC_REG_INV ? norm / (alpha * sym)
+                                                    : norm / sqrtf(alpha * sym));
             A[e] = cscale(A[e], f);
         }
         __syncthreads();
@@ -629,6 +631,91 @@ int reg_x1(const Geo& g, const SpectralWork& w, const double2* in, float2* out, 
     return 0;
 }
 
+// x1 column pass (rows spaced n2 nh apart, one tile row per x2 index)
+template <int DIR>
+int cols_x1(const Geo& g, const float2* tw, int T, float2* spec, int ncomp, hipStream_t s) {
+    const int CW = tile_cols(g.n1, g.nh, CLAIRE_FFT_COL_ELEMS);
+    const int logT = ilog2(T);
+    const size_t sh = sizeof(float2) * ((1 << logT) + (size_t)g.n1 * CW);
+    dim3 grid((g.nh + CW - 1) / CW, g.n2, ncomp);
+    const int per = (g.n1 * CW + kThreads - 1) / kThreads;
+    const long long stride = (long long)g.n2 * g.nh, ystride = g.nh;
+    auto go = [&](auto kern) -> int {
+        CL_TRY(allow_lds(kern, sh));
+        hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, s, spec, g.l1, CW, stride, ystride,
+                           g.nh, g.nspec, tw, logT);
+        CL_LAUNCH_CHECK();
+        return 0;
+    };
+    if (per <= 8) return go(k_c2c_cols<DIR, 8, float2>);
+    if (per <= 16) return go(k_c2c_cols<DIR, 16, float2>);
+    return go(k_c2c_cols<DIR, 32, float2>);
+}
+
+__device__ __forceinline__ float isqrt_symbol(double alpha, int p, int k1, int k2, int k3) {
+    const double sym = alpha * reg_symbol(p, k1, k2, k3);
+    return sym == 0.0 ? 1.f : (float)(1.0 / sqrt(sym));
+}
+
+// kept by the cut-off filter: |k_a| < n_a^c / 2 on every axis (k3 >= 0)
+__device__ __forceinline__ bool kept(int k1, int k2, int k3, int c1, int c2, int c3) {
+    return abs(k1) < (c1 >> 1) && abs(k2) < (c2 >> 1) && k3 < (c3 >> 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_spec_restrict(const float2* __restrict__ F,
+                                                            float2* __restrict__ C, int f1,
+                                                            int f2, int fh, long long fspec,
+                                                            int c1, int c2, int c3, int ch,
+                                                            long long cspec, int ncomp,
+                                                            double alpha, int p, int isqrt,
+                                                            float inv_nf) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= cspec * ncomp) return;
+    const int comp = (int)(idx / cspec);
+    const long long e = idx - comp * cspec;
+    const int i3 = (int)(e % ch);
+    const int i2 = (int)((e / ch) % c2);
+    const int i1 = (int)(e / ((long long)ch * c2));
+    const int k1 = signed_k(i1, c1), k2 = signed_k(i2, c2), k3 = i3;
+    float2 out = make_float2(0.f, 0.f);
+    if (kept(k1, k2, k3, c1, c2, c3)) {
+        const int j1 = (k1 + f1) % f1, j2 = (k2 + f2) % f2;
+        const float2 v = F[comp * fspec + ((long long)j1 * f2 + j2) * fh + k3];
+        const float sg = (isqrt ? isqrt_symbol(alpha, p, k1, k2, k3) : 1.f) * inv_nf;
+        out = make_float2(v.x * sg, v.y * sg);
+    }
+    C[idx] = out;
+}
+
+__global__ __launch_bounds__(kThreads) void k_spec_combine(float2* __restrict__ F,
+                                                           const float2* __restrict__ S, int f1,
+                                                           int f2, int fh, long long fspec,
+                                                           int c1, int c2, int c3, int ch,
+                                                           long long cspec, int ncomp,
+                                                           double alpha, int p, float inv_nf,
+                                                           float inv_nc) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= fspec * ncomp) return;
+    const int comp = (int)(idx / fspec);
+    const long long e = idx - comp * fspec;
+    const int i3 = (int)(e % fh);
+    const int i2 = (int)((e / fh) % f2);
+    const int i1 = (int)(e / ((long long)fh * f2));
+    const int k1 = signed_k(i1, f1), k2 = signed_k(i2, f2), k3 = i3;
+    const float sg = isqrt_symbol(alpha, p, k1, k2, k3);
+    float2 out;
+    if (kept(k1, k2, k3, c1, c2, c3)) {
+        const int j1 = (k1 + c1) % c1, j2 = (k2 + c2) % c2;
+        const float2 v = S[comp * cspec + ((long long)j1 * c2 + j2) * ch + k3];
+        out = make_float2(v.x * sg * inv_nc, v.y * sg * inv_nc);
+    } else {
+        const float2 v = F[idx];
+        const float f = sg * sg * inv_nf;
+        out = make_float2(v.x * f, v.y * f);
+    }
+    F[idx] = out;
+}
+
 }  // namespace
 
 int spectral_init(SpectralWork& w, const Geo& g) {
@@ -709,10 +796,53 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot));
         break;
+    case SPEC_REG_ISQRT:
+        CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
+        CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
+        CL_TRY(fused_x1<SPEC_REG_ISQRT>(g, w, S, S, m, 3, s));
+        CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
+        CL_TRY(inv_x3(g, w, S, out, add, 3, s));
+        break;
     default:
         set_error("unknown spectral mode %d", (int)mode);
         return CLAIRE_EINVAL;
     }
+    return 0;
+}
+
+int spectral_forward(const Geo& g, const SpectralWork& w, const float* in, float2* spec,
+                     int ncomp, hipStream_t s) {
+    CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, spec, ncomp, s));
+    CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, spec, ncomp, s));
+    return cols_x1<-1>(g, w.tw, w.tw_n, spec, ncomp, s);
+}
+
+int spectral_inverse(const Geo& g, const SpectralWork& w, float2* spec, float* out, int ncomp,
+                     hipStream_t s) {
+    CL_TRY(cols_x1<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
+    CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
+    return inv_x3(g, w, spec, out, nullptr, ncomp, s);
+}
+
+int spectral_restrict_modes(const Geo& gf, const Geo& gc, const float2* F, float2* C, int ncomp,
+                            double alpha, int p, bool isqrt, hipStream_t s) {
+    const long long total = gc.nspec * ncomp;
+    hipLaunchKernelGGL(k_spec_restrict, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, F, C, gf.n1, gf.n2, gf.nh, gf.nspec, gc.n1, gc.n2,
+                       gc.n3, gc.nh, gc.nspec, ncomp, alpha, p, isqrt ? 1 : 0,
+                       (float)(1.0 / (double)gf.n));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int spectral_combine_modes(const Geo& gf, const Geo& gc, float2* F, const float2* S, int ncomp,
+                           double alpha, int p, hipStream_t s) {
+    const long long total = gf.nspec * ncomp;
+    hipLaunchKernelGGL(k_spec_combine, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, F, S, gf.n1, gf.n2, gf.nh, gf.nspec, gc.n1, gc.n2,
+                       gc.n3, gc.nh, gc.nspec, ncomp, alpha, p, (float)(1.0 / (double)gf.n),
+                       (float)(1.0 / (double)gc.n));
+    CL_LAUNCH_CHECK();
     return 0;
 }
 

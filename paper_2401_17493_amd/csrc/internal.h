@@ -63,6 +63,7 @@ enum SpecMode {
     SPEC_DIV = 1,      // 3 inputs -> 1 output:  sum_a i k_a u_a
     SPEC_REG = 2,      // 3 -> 3: alpha |k|^{2p}
     SPEC_REG_INV = 3,  // 3 -> 3: 1/(alpha |k|^{2p}), 1 at k = 0
+    SPEC_REG_ISQRT = 4,  // 3 -> 3: (alpha |k|^{2p})^{-1/2}, 1 at k = 0
 };
 
 // out = F^{-1}[ sigma F[in] ] for the mode above; in and out are real fields
@@ -78,6 +79,23 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
 // FD8 gradient (1 -> 3 fields) and divergence (3 -> 1), periodic.
 int launch_fd8_grad(const Geo& g, const float* u, float* out, hipStream_t s);
 int launch_fd8_div(const Geo& g, const float* v, float* out, hipStream_t s);
+
+// Split transforms (unnormalised both ways: inverse(forward(u)) = n u) of
+// ncomp fields into / out of half-complex spectra [ncomp][n1][n2][n3/2+1]
+// (float32), and the spectral grid transfer of the two-level preconditioner
+// between a grid and the grid of half its extents (cut-off below the coarse
+// Nyquist |k_a| < n_a/4).
+int spectral_forward(const Geo& g, const SpectralWork& w, const float* in, float2* spec,
+                     int ncomp, hipStream_t s);
+int spectral_inverse(const Geo& g, const SpectralWork& w, float2* spec, float* out, int ncomp,
+                     hipStream_t s);
+// C = sigma F / n_f on the kept modes (zero elsewhere); sigma = (alpha
+// |k|^{2p})^{-1/2} (1 at k = 0) when isqrt, else 1
+int spectral_restrict_modes(const Geo& gf, const Geo& gc, const float2* F, float2* C, int ncomp,
+                            double alpha, int p, bool isqrt, hipStream_t s);
+// in place over F: kept modes sigma S / n_c, the others sigma^2 F / n_f
+int spectral_combine_modes(const Geo& gf, const Geo& gc, float2* F, const float2* S, int ncomp,
+                           double alpha, int p, hipStream_t s);
 
 // ------------------------------------------------------ semi-Lagrangian
 // Single-field gathers accept an optional per-brick box table of their
@@ -165,6 +183,37 @@ int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t 
 // of r -> slots ssum..ssum+2
 int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
                float kappa, long long n, int smax, int ssum, hipStream_t st);
+
+// ------------------------------------------- two-level preconditioner
+// Coarse grid (half the extents) of the two-level zero-velocity
+// preconditioner, its transforms, the restricted grad m(1) and the vectors of
+// the inner CG (each [3][n_c]).
+struct TwoLevel {
+    Geo gc{};
+    SpectralWork swc;
+    Reducer red;
+    float* gm = nullptr;   // Q_R F_L grad m(1)
+    float* b = nullptr;    // restricted right-hand side
+    float* x = nullptr;    // inner CG iterate
+    float* r = nullptr;
+    float* p = nullptr;
+    float* q = nullptr;
+    float* y = nullptr;    // scratch of the coarse operator
+    bool ready = false;
+};
+constexpr int kMaxInner = 200;
+
+int twolevel_init(TwoLevel& T, const Geo& gf);
+void twolevel_free(TwoLevel& T);
+// restrict grad m(1) ([3][n] on the fine grid) to the coarse grid
+int twolevel_setup(TwoLevel& T, const Geo& gf, SpectralWork& swf, const float* gradm,
+                   hipStream_t s);
+// z = P r ([3][n] each, may not alias); the inner CG stops at ||r_c|| <=
+// inner_rtol ||b_c|| or after max_inner iterations (count in *inner_its).
+// Synchronises the stream once per inner iteration.
+int twolevel_apply(TwoLevel& T, const Geo& gf, SpectralWork& swf, const float* r, float* z,
+                   double alpha, int pw, double inner_rtol, int max_inner, int* inner_its,
+                   hipStream_t s);
 
 // ------------------------------------------------------- vector updates
 // y = a*x + y
