@@ -72,3 +72,34 @@ def test_symmetric_with_exact_coarse_solve():
     lhs, rhs = float(np.sum(P(a) * b)), float(np.sum(a * P(b)))
     assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
     assert float(np.sum(P(a) * a)) > 0
+
+
+def test_coarse_operator_is_the_coarse_hessian_at_zero_velocity():
+    """At v = 0 every characteristic stays at its grid point, m(t) = m0, the
+    incremental state is m~(1) = -grad m0 . v~ and the incremental adjoint is
+    constant in time, so the Gauss--Newton Hessian is exactly
+    H0 = alpha L + grad m0 (grad m0)^T (the zero-velocity Hessian). The coarse
+    operator of the preconditioner, scaled back by R_c^{1/2} on both sides,
+    must therefore equal the full Hessian matvec (semi-Lagrangian transport,
+    incremental state and adjoint) on the coarse grid with the restricted
+    template: R_c^{1/2} K0_c R_c^{1/2} w = H_c w."""
+    grid, m0, m1, _ = blob_problem(n=(16, 32, 16), kmax=3)
+    gc = O.Grid((8, 16, 8))
+    for p in (1, 2):
+        alpha = 1e-2
+        st = O.setup_velocity(grid, m0, m1, np.zeros((3,) + grid.n), alpha, 4, p)
+        P = O.TwoLevelPreconditioner(st, inner_rtol=1e-8)
+        m0c = O.spectral_restrict(grid, m0, gc)
+        m1c = O.spectral_restrict(grid, m1, gc)
+        stc = O.setup_velocity(gc, m0c, m1c, np.zeros((3,) + gc.n), alpha, 4, p)
+        rng = np.random.default_rng(3 + p)
+        w = rng.standard_normal((3,) + gc.n)
+
+        def R_half(u):   # R^{1/2} u = R^{-1/2} (alpha L u + mean u)
+            mean = u.mean(axis=(1, 2, 3), keepdims=True)
+            return O.reg_inverse_sqrt(gc, O.regularization_operator(gc, u, alpha, p) + mean,
+                                      alpha, p)
+
+        lhs = R_half(P.coarse_operator(R_half(w)))
+        rhs = O.hessian_matvec(stc, w)
+        assert np.abs(lhs - rhs).max() <= 1e-10 * np.abs(rhs).max()
