@@ -132,6 +132,8 @@ def main():
                     choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["mixed", "fp32", "both"])
+    ap.add_argument("--precond", default="reg", choices=["reg", "twolevel"],
+                    help="PCG preconditioner: (alpha L)^-1 or the two-level zero-velocity scheme")
     ap.add_argument("--warmstart", default=WEIGHTS,
                     help="trained warm-start weights (.npz) or 'none'")
     ap.add_argument("--kernels-only", action="store_true",
@@ -154,7 +156,8 @@ def main():
     n, nt = w["n"], w["nt"]
     alpha = w["alphas"][-1]
     levels = list(w["alphas"]) if len(w["alphas"]) > 1 else None
-    opts = dict(gtol=w.get("gtol", 5e-2), compute_det=1)
+    opts = dict(gtol=w.get("gtol", 5e-2), compute_det=1,
+                precond={"reg": C.PRECOND_REG, "twolevel": C.PRECOND_TWOLEVEL}[args.precond])
     if levels:
         opts["alpha_levels"] = levels
 
@@ -197,8 +200,8 @@ def main():
             v, stats = one_solve()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-            print("step (%s): solve %.3f s, %d GN iterations, %d matvecs" %
-                  (label, times[-1], stats["gn_iters"], stats["matvecs"]),
+            print("step (%s): solve %.3f s, %d GN iterations, %d matvecs, %d inner" %
+                  (label, times[-1], stats["gn_iters"], stats["matvecs"], stats["inner_iters"]),
                   file=sys.stderr, flush=True)
         rec = dict(tts=sum(times) / len(times), stats=stats, v=v, prec=prec)
         if not warm:
@@ -239,7 +242,8 @@ def main():
 
     def solve_rec(r):
         st = r["stats"]
-        rec = {k: st[k] for k in ("gn_iters", "matvecs", "pde_solves", "linesearch_trials",
+        rec = {k: st[k] for k in ("gn_iters", "matvecs", "inner_iters", "pde_solves",
+                                  "linesearch_trials",
                                   "rel_grad", "rel_mismatch", "J0", "J", "det_min", "det_max",
                                   "det_nonpositive")}
         rec.update(time_to_solution_s=round(r["tts"], 4),
@@ -263,7 +267,9 @@ def main():
         "config": {"workload": args.workload, "grid": list(n), "nt": nt,
                    "alpha": alpha if not levels else levels,
                    "regularization": "H%d seminorm" % w["reg_order"],
-                   "gtol": opts["gtol"], "preconditioner": "(alpha L)^-1",
+                   "gtol": opts["gtol"],
+                   "preconditioner": "(alpha L)^-1" if args.precond == "reg" else
+                   "two-level zero-velocity H0 (coarse grid n/2, inner CG to 0.1 eta)",
                    "precision": "mixed: float16 grad m and incremental sources in the "
                                 "Hessian matvec, float32 arithmetic/FFTs, float64 reductions"
                    if head["prec"] == 1 else "float32 fields and FFTs, float64 reductions",
