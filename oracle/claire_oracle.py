@@ -25,7 +25,10 @@ that each step can be read against the paper:
   stopping rules, Section 2.5.5 and Algorithms 1--2 (appendix);
 * regularisation preconditioner, Section 2.5.6;
 * parameter continuation, Section 2.6;
-* deformation gradient transport, eq. (e:def-grad) (appendix).
+* deformation gradient transport, eq. (e:def-grad) (appendix);
+* near-incompressible model (appendix, "(Near-)Incompressible
+  Diffeomorphisms"): reduced gradient with the data term projected by
+  I - grad M Delta^{-1} div, M = (alpha (beta (-Delta^{-1} + id))^{-1} + id)^{-1}.
 
 Readings where the paper is silent or inconsistent (all listed in the design
 notes of the repository):
@@ -224,6 +227,58 @@ def regularization_operator(grid, v, alpha, p):
 
 
 # ----------------------------------------------------------------------------
+# near-incompressible model (appendix): div v = w with the penalty
+# beta/2 <w, (-Delta^{-1} + id) w> on the second control w; w and the
+# constraint's multiplier eliminated
+# ----------------------------------------------------------------------------
+def inverse_laplacian(grid, u):
+    """Delta^{-1} u of a scalar field: multiplier -1/|k|^2, 0 at k = 0 (the
+    mean has no preimage; every use below applies it to a divergence, whose
+    mean is zero)."""
+    kk = laplacian_power_symbol(grid, 1)
+    mult = np.where(kk == 0.0, 0.0, -1.0 / np.where(kk == 0.0, 1.0, kk))
+    return _ifft(mult * _fft(u), grid.n)
+
+
+def _penalty_operator(grid, u, beta):
+    """beta (-Delta^{-1} + id) u (the operator of the penalty on w)."""
+    return beta * (-inverse_laplacian(grid, u) + u)
+
+
+def ni_operator_M(grid, u, alpha, beta):
+    """M u with M = (alpha (beta (-Delta^{-1} + id))^{-1} + id)^{-1}, a
+    Fourier multiplier: invert the penalty operator's symbol, scale by alpha,
+    add one, invert again (at k = 0, -Delta^{-1} contributes 0)."""
+    kk = laplacian_power_symbol(grid, 1)
+    pen = beta * (np.where(kk == 0.0, 0.0, 1.0 / np.where(kk == 0.0, 1.0, kk)) + 1.0)
+    return _ifft(_fft(u) / (alpha / pen + 1.0), grid.n)
+
+
+def ni_project(grid, b, alpha, beta):
+    """b - grad M Delta^{-1} div b: the operator the near-incompressible
+    reduced gradient applies to the data term int_0^1 lambda grad m dt
+    (appendix), composed in the printed order from the spectral divergence,
+    Delta^{-1}, M and the spectral gradient."""
+    q = ni_operator_M(grid, inverse_laplacian(grid, spectral_divergence(grid, b)), alpha, beta)
+    return b - spectral_gradient(grid, q)
+
+
+def divergence_penalty(grid, v, beta):
+    """beta/2 <div v, (-Delta^{-1} + id) div v>: the penalty on w = div v left
+    in the objective once w is eliminated. With it, the appendix's reduced
+    gradient is K grad J~ with K = I - grad M Delta^{-1} div (the factor M
+    is exactly what turns the gradient of this objective into the projected
+    form), so J~ is the merit function of the line search."""
+    d = spectral_divergence(grid, v)
+    return 0.5 * grid.inner(d, _penalty_operator(grid, d, beta))
+
+
+def divergence_penalty_gradient(grid, v, beta):
+    """L2 gradient of divergence_penalty: -grad beta (-Delta^{-1} + id) div v."""
+    return -spectral_gradient(grid, _penalty_operator(grid, spectral_divergence(grid, v), beta))
+
+
+# ----------------------------------------------------------------------------
 # interpolation (Section 2.5.4, p = 3)
 # ----------------------------------------------------------------------------
 def interpolate(f, d):
@@ -329,6 +384,10 @@ class VelocityState:
     J: float = 0.0
     J_dist: float = 0.0
     J_reg: float = 0.0
+    beta: float = 0.0           # near-incompressible penalty (0: plain model)
+    J_div: float = 0.0          # divergence penalty part of J
+    data: np.ndarray = None     # int_0^1 lambda grad m dt (trapezoid)
+    grad_J: np.ndarray = None   # L2 gradient of J (equals g when beta = 0)
 
 
 def objective_parts(grid, m_final, m1, v, alpha, p):
@@ -339,11 +398,14 @@ def objective_parts(grid, m_final, m1, v, alpha, p):
     return dist, reg
 
 
-def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral"):
+def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0):
     """State, objective, adjoint and reduced gradient at v (Algorithm 1 lines
     3-6; eqs. e:transport, e:varopt-claire, e:adjoint, e:rgrad). ``deriv``
-    selects the gradient/divergence discretisation ("spectral" or "fd8")."""
-    st = VelocityState(grid=grid, nt=nt, alpha=alpha, p=p,
+    selects the gradient/divergence discretisation ("spectral" or "fd8") of
+    the transport and adjoint equations. ``beta`` > 0 selects the
+    near-incompressible model (appendix): J gains divergence_penalty and the
+    reduced gradient is alpha L v + ni_project(data)."""
+    st = VelocityState(grid=grid, nt=nt, alpha=alpha, p=p, beta=beta,
                        v=np.asarray(v, dtype=np.float64),
                        m0=np.asarray(m0, dtype=np.float64),
                        m1=np.asarray(m1, dtype=np.float64))
@@ -363,16 +425,26 @@ def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral"):
                                   st.div_v_dep, nt)
     st.lam = lam
     c = trapezoid_weights(nt)
-    data = sum(c[j] * lam[j] * st.grad_m[j] for j in range(nt + 1))
-    st.g = regularization_operator(grid, st.v, alpha, p) + ht * data
+    st.data = ht * sum(c[j] * lam[j] * st.grad_m[j] for j in range(nt + 1))
+    reg = regularization_operator(grid, st.v, alpha, p)
+    if beta > 0.0:
+        st.J_div = divergence_penalty(grid, st.v, beta)
+        st.J += st.J_div
+        st.g = reg + ni_project(grid, st.data, alpha, beta)
+        st.grad_J = reg + st.data + divergence_penalty_gradient(grid, st.v, beta)
+    else:
+        st.g = reg + st.data
+        st.grad_J = st.g
     return st
 
 
-def objective(grid, m0, m1, v, alpha, nt, p):
-    """J(v): backtrace, state solve and objective only (line-search trial)."""
+def objective(grid, m0, m1, v, alpha, nt, p, beta=0.0):
+    """J(v): backtrace, state solve and objective only (line-search trial);
+    with beta > 0 the divergence penalty of the near-incompressible model is
+    included."""
     m_final = transport(grid, m0, v, nt)
     dist, reg = objective_parts(grid, m_final, m1, v, alpha, p)
-    return dist + reg
+    return dist + reg + (divergence_penalty(grid, v, beta) if beta > 0.0 else 0.0)
 
 
 # ----------------------------------------------------------------------------
@@ -412,8 +484,12 @@ def hessian_matvec(st, vt):
     vt = np.asarray(vt, dtype=np.float64)
     lt = incremental_adjoint(st, incremental_state(st, vt))
     c = trapezoid_weights(st.nt)
-    data = sum(c[j] * lt[j] * st.grad_m[j] for j in range(st.nt + 1))
-    return regularization_operator(st.grid, vt, st.alpha, st.p) + data / st.nt
+    data = sum(c[j] * lt[j] * st.grad_m[j] for j in range(st.nt + 1)) / st.nt
+    if st.beta > 0.0:
+        # derivative of the near-incompressible reduced gradient: the
+        # projection is linear and independent of v
+        data = ni_project(st.grid, data, st.alpha, st.beta)
+    return regularization_operator(st.grid, vt, st.alpha, st.p) + data
 
 
 def precondition(grid, r, alpha, p):
@@ -622,7 +698,7 @@ class SolveStats:
 
 def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
              max_gn=50, max_pcg=100, fixed_pcg=0, forcing="superlinear",
-             c1=1e-4, max_ls=16, deriv="spectral", precond="reg"):
+             c1=1e-4, max_ls=16, deriv="spectral", precond="reg", beta=0.0):
     """Inexact Gauss--Newton--Krylov with Armijo line search (Algorithm 1),
     run once per regularisation weight in ``alphas`` (parameter continuation,
     Section 2.6: each level starts from the previous level's velocity and
@@ -632,9 +708,16 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
     zero-velocity preconditioner (Section 2.5.6) with its inner CG run to a
     tenth of the outer relative tolerance (Section 2.6 settings).
 
+    ``beta`` > 0: near-incompressible model (appendix). The reduced gradient
+    and the Hessian carry the projection of the data term; the Armijo test
+    uses the objective with the divergence penalty and its directional
+    derivative <grad J, v~>. Not combined with the two-level preconditioner.
+
     Parity of the whole solve is unpinned beyond its invariants (monotone J,
     stopping rule, det grad y > 0): the tests compare it with the HIP path.
     """
+    if beta > 0.0 and precond == "twolevel":
+        raise ValueError("the two-level preconditioner is not combined with beta > 0")
     v = np.zeros((3,) + grid.n) if v0 is None else np.array(v0, dtype=np.float64)
     stats = SolveStats()
     st = None
@@ -642,7 +725,7 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
     m1 = np.asarray(m1, dtype=np.float64)
     mismatch0 = np.sqrt(np.sum((m0 - m1) ** 2))
     for li, alpha in enumerate(alphas):
-        st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv)
+        st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv, beta)
         stats.pde_solves += 2
         if li == 0:
             stats.J0 = st.J
@@ -670,12 +753,12 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
             stats.pde_solves += 2 * its
             if hit_max:
                 stats.warnings.append("pcg_max")
-            slope = grid.inner(st.g, vt)
+            slope = grid.inner(st.grad_J, vt)
             gamma = 1.0
             accepted = False
             for _ in range(max_ls):
                 v_trial = v + gamma * vt
-                j_trial = objective(grid, m0, m1, v_trial, alpha, nt, p)
+                j_trial = objective(grid, m0, m1, v_trial, alpha, nt, p, beta)
                 stats.ls_trials += 1
                 stats.pde_solves += 1
                 if j_trial <= st.J + c1 * gamma * slope:
@@ -686,7 +769,7 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
                 stats.warnings.append("linesearch")
                 break
             v = v_trial
-            st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv)
+            st = setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv, beta)
             stats.pde_solves += 2
             k += 1
             stats.gn_iters += 1
