@@ -83,6 +83,10 @@ typedef struct claire_opts {
                                    CLAIRE_DERIV_SPECTRAL (default) or CLAIRE_DERIV_FD8 */
     int precond;                /* PCG preconditioner (Section 2.5.6):
                                    CLAIRE_PRECOND_REG (default) or CLAIRE_PRECOND_TWOLEVEL */
+    double beta;                /* > 0: near-incompressible model (appendix) with this
+                                   weight of the divergence penalty (the paper's runs use
+                                   1e-4); 0 (default): the plain model. Needs reg_order 1;
+                                   not combined with CLAIRE_PRECOND_TWOLEVEL */
 } claire_opts;
 
 /* Preconditioners of the reduced Hessian (Section 2.5.6): the inverse of the
@@ -176,6 +180,21 @@ int claire_ctx_hessian_matvec(claire_ctx *ctx, const float *vt, float *Hvt);
  * set_velocity again). */
 int claire_ctx_set_precision(claire_ctx *ctx, int precision);
 
+/* Near-incompressible model (appendix, "(Near-)Incompressible
+ * Diffeomorphisms"): div v = w with the penalty beta/2 <w, (-Delta^{-1} + id) w>
+ * on the second control w, w eliminated. For later set_velocity /
+ * hessian_matvec / objective calls (beta = 0: the plain model):
+ *   g   = alpha L v + K b,  b = int_0^1 lambda grad m dt,
+ *   K   = I - grad M Delta^{-1} div,  M = (alpha (beta (-Delta^{-1} + id))^{-1} + id)^{-1},
+ *   H v~ = alpha L v~ + K int_0^1 lambda~ grad m dt,
+ *   J   = 1/2 ||m(1) - m1||^2 + alpha/2 <L v, v> + beta/2 <div v, (-Delta^{-1} + id) div v>
+ * (g = K grad J; J is the line-search merit function). The operators of the
+ * model are spectral (odd derivatives with the Nyquist mode zeroed) whatever
+ * the derivative option. beta >= 0; beta > 0 needs reg_order 1 (the paper's
+ * H1 seminorm). Allocates two [3][n] float32 fields on first use.
+ * Invalidates the cached setup. */
+int claire_ctx_set_beta(claire_ctx *ctx, double beta);
+
 /* Select the first-derivative discretisation (CLAIRE_DERIV_SPECTRAL or
  * CLAIRE_DERIV_FD8, Section 2.5.3) of grad m^j and div v in later
  * set_velocity calls and of grad v in detdefgrad. Invalidates the cached
@@ -220,9 +239,14 @@ int claire_ctx_detdefgrad(claire_ctx *ctx, double *det_out, double stats[4]);
  *   CLAIRE_OP_REG_INV  in [3][n] -> out [3][n]  (alpha L)^{-1}, k = 0 passed through
  *   CLAIRE_OP_FD8_GRAD in [n]    -> out [3][n]  grad by FD8 central differences
  *   CLAIRE_OP_FD8_DIV  in [3][n] -> out [n]     divergence by FD8
+ *   CLAIRE_OP_NI_PROJECT in [3][n] -> out [3][n] K = I - grad M Delta^{-1} div
+ *   CLAIRE_OP_NI_PENALTY in [3][n] -> out [3][n] -grad beta (-Delta^{-1} + id) div
+ * (the last two: near-incompressible model at the context's alpha and beta,
+ * see claire_ctx_set_beta; CLAIRE_EINVAL when beta = 0).
  * in and out must not overlap. */
 enum { CLAIRE_OP_GRAD = 0, CLAIRE_OP_DIV = 1, CLAIRE_OP_REG = 2, CLAIRE_OP_REG_INV = 3,
-       CLAIRE_OP_FD8_GRAD = 4, CLAIRE_OP_FD8_DIV = 5 };
+       CLAIRE_OP_FD8_GRAD = 4, CLAIRE_OP_FD8_DIV = 5, CLAIRE_OP_NI_PROJECT = 6,
+       CLAIRE_OP_NI_PENALTY = 7 };
 int claire_ctx_spectral(claire_ctx *ctx, int op, const float *in, float *out);
 
 /* Tricubic Lagrange interpolation (Section 2.5.4, p = 3):

@@ -405,6 +405,8 @@ def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0):
     the transport and adjoint equations. ``beta`` > 0 selects the
     near-incompressible model (appendix): J gains divergence_penalty and the
     reduced gradient is alpha L v + ni_project(data)."""
+    if beta > 0.0 and p != 1:
+        raise ValueError("the near-incompressible model uses the H1 seminorm (p = 1)")
     st = VelocityState(grid=grid, nt=nt, alpha=alpha, p=p, beta=beta,
                        v=np.asarray(v, dtype=np.float64),
                        m0=np.asarray(m0, dtype=np.float64),

@@ -36,6 +36,7 @@ class ClaireOpts(ctypes.Structure):
         ("tol_from_zero", c_int),
         ("derivative", c_int),
         ("precond", c_int),
+        ("beta", c_double),
     ]
 
 
@@ -79,6 +80,7 @@ SIGNATURES = {
                                             c_void_p]),
     "claire_ctx_set_precision": (c_int, [c_void_p, c_int]),
     "claire_ctx_set_derivative": (c_int, [c_void_p, c_int]),
+    "claire_ctx_set_beta": (c_int, [c_void_p, c_double]),
     "claire_ctx_solve": (c_int, [c_void_p, ctypes.POINTER(ClaireOpts), c_void_p,
                                  ctypes.POINTER(ClaireStats)]),
     "claire_ctx_detdefgrad": (c_int, [c_void_p, c_void_p, c_double_p]),

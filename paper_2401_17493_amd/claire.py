@@ -18,6 +18,7 @@ import torch
 from . import _lib as L
 
 OP_GRAD, OP_DIV, OP_REG, OP_REG_INV, OP_FD8_GRAD, OP_FD8_DIV = 0, 1, 2, 3, 4, 5
+OP_NI_PROJECT, OP_NI_PENALTY = 6, 7
 DERIV_SPECTRAL, DERIV_FD8 = 0, 1
 PRECOND_REG, PRECOND_TWOLEVEL = 0, 1
 KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE = range(5)
@@ -129,6 +130,10 @@ class Context:
         """0: float32 matvec storage; 1: float16 storage in the Hessian matvec."""
         _check(self.lib.claire_ctx_set_precision(self._h, int(precision)))
 
+    def set_beta(self, beta: float):
+        """Near-incompressible model weight (0: plain model) for later setups."""
+        _check(self.lib.claire_ctx_set_beta(self._h, float(beta)))
+
     def set_derivative(self, derivative: int):
         """DERIV_SPECTRAL or DERIV_FD8 for grad m^j, div v (and grad v in detdefgrad)."""
         _check(self.lib.claire_ctx_set_derivative(self._h, int(derivative)))
@@ -197,7 +202,9 @@ class Context:
     def spectral(self, op: int, x: torch.Tensor) -> torch.Tensor:
         shapes = {OP_GRAD: (self.n, self.vshape), OP_DIV: (self.vshape, self.n),
                   OP_REG: (self.vshape, self.vshape), OP_REG_INV: (self.vshape, self.vshape),
-                  OP_FD8_GRAD: (self.n, self.vshape), OP_FD8_DIV: (self.vshape, self.n)}
+                  OP_FD8_GRAD: (self.n, self.vshape), OP_FD8_DIV: (self.vshape, self.n),
+                  OP_NI_PROJECT: (self.vshape, self.vshape),
+                  OP_NI_PENALTY: (self.vshape, self.vshape)}
         sin, sout = shapes[op]
         out = self._new(sout)
         _check(self.lib.claire_ctx_spectral(self._h, int(op), _ptr(x, sin, "in"),

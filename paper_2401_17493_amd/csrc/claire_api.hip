@@ -101,6 +101,12 @@ struct claire_ctx {
     float* vtrial = nullptr;
     float* als = nullptr;    // alpha L s, kept by recursion inside PCG
 
+    // near-incompressible model (beta > 0), buffers allocated on demand
+    double beta = 0;
+    float* ni_tmp = nullptr; // [3][n] data term int lambda grad m dt before projection
+    float* gradJ = nullptr;  // [3][n] L2 gradient of J (Armijo slope)
+    double Jdiv = 0;         // divergence penalty part of J
+
     int deriv = CLAIRE_DERIV_SPECTRAL;   // first-derivative discretisation
     bool have_images = false;
     bool state_valid = false;      // dp, dm, m valid for the content of v
@@ -164,7 +170,7 @@ int ctx_alloc(claire_ctx* c) {
 void ctx_release(claire_ctx* c) {
     float* bufs[] = {c->m0, c->m1, c->v, c->dp, c->dm, c->m, c->gm, c->divv, c->A, c->grad,
                      c->regv, c->lam, c->w0, c->w1, c->tmp3, c->vt, c->r, c->z, c->sd, c->hs,
-                     c->vtrial, c->als};
+                     c->vtrial, c->als, c->ni_tmp, c->gradJ};
     for (float* b : bufs) dfree(b);
     __half* hbufs[] = {c->gm16, c->f16};
     for (__half* b : hbufs) dfree(b);
@@ -195,6 +201,12 @@ int run_state(claire_ctx* c) {
         CL_TRY(launch_interp(g, c->m + (long long)j * g.n, 1, c->dp, c->m + (long long)(j + 1) * g.n,
                              c->s, c->box_p));
     c->state_valid = true;
+    return 0;
+}
+
+int ensure_ni_buffers(claire_ctx* c) {
+    if (!c->ni_tmp) CL_TRY(dalloc(&c->ni_tmp, 3 * c->g.n));
+    if (!c->gradJ) CL_TRY(dalloc(&c->gradJ, 3 * c->g.n));
     return 0;
 }
 
@@ -247,12 +259,28 @@ int run_setup(claire_ctx* c) {
         c->half_valid = true;
     }
     // reduced gradient (eq. e:rgrad), trapezoid in time
-    CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->regv, c->grad, c->s));
+    if (c->beta > 0.0) {
+        // near-incompressible model (appendix): g = alpha L v + K b with
+        // K = I - grad M Delta^{-1} div and b the data term; J gains the
+        // divergence penalty 1/2 <P v, v>, P = -grad beta (-Delta^{-1} + id) div
+        CL_TRY(ensure_ni_buffers(c));
+        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, nullptr, c->ni_tmp, c->s));
+        CL_TRY(spectral_ni(g, c->sw, NI_PROJECT, c->ni_tmp, c->grad, c->alpha, c->beta, c->s,
+                           c->regv));
+        CL_TRY(spectral_ni(g, c->sw, NI_PENALTY, c->v, c->gradJ, c->alpha, c->beta, c->s,
+                           nullptr, c->v, &c->red, 3));   // P v and <P v, v> -> slot 3
+        // L2 gradient of J for the Armijo slope: b + alpha L v + P v
+        CL_TRY(launch_axpy(c->ni_tmp, c->gradJ, 1.f, 3 * n, c->s));
+        CL_TRY(launch_axpy(c->regv, c->gradJ, 1.f, 3 * n, c->s));
+    } else {
+        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, c->regv, c->grad, c->s));
+    }
     CL_TRY(red_absmax(c->red, c->grad, 3 * n, 2, c->s));
     CL_TRY(red_fetch(c->red, c->s));
     c->Jdist = 0.5 * c->cell * c->red.host[0];
     c->Jreg = 0.5 * c->cell * c->red.host[1];
-    c->J = c->Jdist + c->Jreg;
+    c->Jdiv = c->beta > 0.0 ? 0.5 * c->cell * c->red.host[3] : 0.0;
+    c->J = c->Jdist + c->Jreg + c->Jdiv;
     c->gnorm = c->red.host[2];
     if (!std::isfinite(c->J) || !std::isfinite(c->gnorm)) {
         set_error("non-finite objective or gradient");
@@ -269,6 +297,16 @@ int run_setup(claire_ctx* c) {
 // reduction slot.
 int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
                      int dot_slot);
+
+// out = reg_part + K ni_tmp (near-incompressible projection of the data term
+// in ni_tmp), and <vt, out> -> dot_slot when >= 0
+int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part,
+                     int dot_slot) {
+    CL_TRY(spectral_ni(c->g, c->sw, NI_PROJECT, c->ni_tmp, out, c->alpha, c->beta, c->s,
+                       reg_part));
+    if (dot_slot >= 0) CL_TRY(red_dot(c->red, vt, out, 3 * c->g.n, dot_slot, c->s));
+    return 0;
+}
 
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
                int dot_slot = -1) {
@@ -302,6 +340,11 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
     if (!reg_part) {
         CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
         reg_part = c->tmp3;
+    }
+    if (c->beta > 0.0) {
+        // near-incompressible model: the data term projected by K
+        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, nullptr, c->ni_tmp, c->s));
+        return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
     }
     if (dot_slot >= 0)
         CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot));
@@ -347,6 +390,10 @@ int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* re
     if (!reg_part) {
         CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
         reg_part = c->tmp3;
+    }
+    if (c->beta > 0.0) {
+        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, nullptr, c->ni_tmp, c->s));
+        return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
     }
     if (dot_slot >= 0)
         CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, reg_part, out, c->s, vt,
@@ -524,15 +571,28 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
             if (pr.neg_curv) note(CLAIRE_WNEGCURV);
             // Armijo line search on J(v + gamma v~). The regulariser is
             // quadratic: J_reg(v + gamma v~) = J_reg + gamma <aLv, v~> + gamma^2/2 <aLv~, v~>.
-            CL_TRY(red_dot(c->red, c->grad, c->vt, n3, 3, s));
+            // With beta > 0 the merit function carries the divergence penalty
+            // 1/2 <P v, v> (quadratic too) and the slope is <grad J, v~>.
+            const bool ni = c->beta > 0.0;
+            CL_TRY(red_dot(c->red, ni ? c->gradJ : c->grad, c->vt, n3, 3, s));
             CL_TRY(red_dot(c->red, c->regv, c->vt, n3, 4, s));
             CL_TRY(spectral_apply(g, c->sw, SPEC_REG, c->vt, c->tmp3, c->alpha, c->p, s));
             CL_TRY(red_dot(c->red, c->tmp3, c->vt, n3, 5, s));
+            if (ni) {
+                // <P v, v~> = <v, P v~> (P symmetric) and <P v~, v~>
+                CL_TRY(spectral_ni(g, c->sw, NI_PENALTY, c->vt, c->ni_tmp, c->alpha, c->beta, s));
+                CL_TRY(red_dot(c->red, c->ni_tmp, c->v, n3, 6, s));
+                CL_TRY(red_dot(c->red, c->ni_tmp, c->vt, n3, 7, s));
+            }
             CL_TRY(red_fetch(c->red, s));
             const double slope = c->cell * c->red.host[3];
-            const double ra = c->cell * c->red.host[4];
-            const double rb = c->cell * c->red.host[5];
-            const double J = c->J, Jreg = c->Jreg;
+            double ra = c->cell * c->red.host[4];
+            double rb = c->cell * c->red.host[5];
+            if (ni) {
+                ra += c->cell * c->red.host[6];
+                rb += c->cell * c->red.host[7];
+            }
+            const double J = c->J, Jreg = c->Jreg + c->Jdiv;
             double gamma = 1.0;
             bool accepted = false;
             for (int t = 0; t < o.max_linesearch; ++t) {
@@ -629,6 +689,7 @@ void claire_opts_default(claire_opts* o) {
     o->tol_from_zero = 0;
     o->derivative = CLAIRE_DERIV_SPECTRAL;
     o->precond = CLAIRE_PRECOND_REG;
+    o->beta = 0.0;
 }
 
 const char* claire_last_error(void) { return g_err; }
@@ -712,8 +773,14 @@ int claire_ctx_objective(claire_ctx* c, const float* v, double* J) {
     CL_TRY(run_trial_mismatch(c, &jd));
     CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG, c->v, c->tmp3, c->alpha, c->p, c->s));
     CL_TRY(red_dot(c->red, c->tmp3, c->v, 3 * c->g.n, 1, c->s));
+    if (c->beta > 0.0) {
+        CL_TRY(ensure_ni_buffers(c));
+        CL_TRY(spectral_ni(c->g, c->sw, NI_PENALTY, c->v, c->ni_tmp, c->alpha, c->beta, c->s,
+                           nullptr, c->v, &c->red, 2));
+    }
     CL_TRY(red_fetch(c->red, c->s));
-    *J = jd + 0.5 * c->cell * c->red.host[1];
+    *J = jd + 0.5 * c->cell * c->red.host[1] +
+         (c->beta > 0.0 ? 0.5 * c->cell * c->red.host[2] : 0.0);
     return 0;
 }
 
@@ -779,17 +846,44 @@ int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
         set_error("precond must be CLAIRE_PRECOND_REG or CLAIRE_PRECOND_TWOLEVEL");
         return CLAIRE_EINVAL;
     }
+    if (!(o.beta >= 0.0)) { set_error("beta must be >= 0"); return CLAIRE_EINVAL; }
+    if (o.beta > 0.0 && c->p != 1) {
+        set_error("the near-incompressible model (beta > 0) uses the H1 seminorm (reg_order 1)");
+        return CLAIRE_EINVAL;
+    }
+    if (o.beta > 0.0 && o.precond == CLAIRE_PRECOND_TWOLEVEL) {
+        set_error("the two-level preconditioner is not combined with beta > 0");
+        return CLAIRE_EINVAL;
+    }
     if (o.precond == CLAIRE_PRECOND_TWOLEVEL) CL_TRY(twolevel_init(c->tl, c->g));
+    if (o.beta > 0.0) CL_TRY(ensure_ni_buffers(c));
     const int saved = c->precision;
     const int saved_deriv = c->deriv;
+    const double saved_beta = c->beta;
     c->precision = o.precision;
     c->deriv = o.derivative;
+    c->beta = o.beta;
     const int rc = run_solve(c, o, v_inout, stats);
     c->precision = saved;
     if (c->deriv != saved_deriv) c->have_velocity = false;   // setup used the other operators
     c->deriv = saved_deriv;
+    if (c->beta != saved_beta) c->have_velocity = false;
+    c->beta = saved_beta;
     if (saved == 1 && o.precision != 1) c->have_velocity = false;   // half copies not made
     return rc;
+}
+
+int claire_ctx_set_beta(claire_ctx* c, double beta) {
+    if (!c) { set_error("ctx is NULL"); return CLAIRE_EINVAL; }
+    if (!(beta >= 0.0)) { set_error("beta must be >= 0"); return CLAIRE_EINVAL; }
+    if (beta > 0.0 && c->p != 1) {
+        set_error("the near-incompressible model (beta > 0) uses the H1 seminorm (reg_order 1)");
+        return CLAIRE_EINVAL;
+    }
+    if (beta > 0.0) CL_TRY(ensure_ni_buffers(c));
+    if (beta != c->beta) c->have_velocity = false;   // redo the setup
+    c->beta = beta;
+    return 0;
 }
 
 int claire_ctx_set_derivative(claire_ctx* c, int derivative) {
@@ -877,6 +971,14 @@ int claire_ctx_spectral(claire_ctx* c, int op, const float* in, float* out) {
     if (in == out) { set_error("in and out must not overlap"); return CLAIRE_EINVAL; }
     if (op == CLAIRE_OP_FD8_GRAD) return launch_fd8_grad(c->g, in, out, c->s);
     if (op == CLAIRE_OP_FD8_DIV) return launch_fd8_div(c->g, in, out, c->s);
+    if (op == CLAIRE_OP_NI_PROJECT || op == CLAIRE_OP_NI_PENALTY) {
+        if (!(c->beta > 0.0)) {
+            set_error("the near-incompressible operators need beta > 0 (claire_ctx_set_beta)");
+            return CLAIRE_EINVAL;
+        }
+        return spectral_ni(c->g, c->sw, op == CLAIRE_OP_NI_PROJECT ? NI_PROJECT : NI_PENALTY,
+                           in, out, c->alpha, c->beta, c->s);
+    }
     SpecMode m;
     switch (op) {
     case CLAIRE_OP_GRAD: m = SPEC_GRAD; break;

@@ -469,6 +469,80 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     }
 }
 
+// Coupled multipliers of the near-incompressible model (3 -> 3): the three
+// component tiles of one x1 column block sit in LDS together, so each mode
+// mixes its components in one pass. With q = k_d . F (k_d the odd-derivative
+// wavenumbers, Nyquist 0; |k|^2 the full symbol):
+//   NI_PROJECT: F - M k_d q / |k|^2, M = beta a / (alpha + beta a),
+//               a = 1/|k|^2 + 1 (grad M Delta^{-1} div subtracted);
+//   NI_PENALTY: beta a k_d q (the operator -grad beta (-Delta^{-1} + id) div);
+// both 0 on the coupled part at k = 0.
+template <int CM, int E>
+__global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ data, int l1,
+                                                         int CW, int nh, long long nspec,
+                                                         Mult m, float beta,
+                                                         const float2* __restrict__ tw,
+                                                         int logT) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw_s = reinterpret_cast<float2*>(smem_raw);
+    float2* T = tw_s + (1 << logT);
+    const int tid = threadIdx.x;
+    const int N = 1 << l1;
+    const int tile = N * CW;
+    const int k2i = blockIdx.y;
+    const int c0 = blockIdx.x * CW;
+    const int cw = min(CW, nh - c0);
+    const long long stride = (long long)m.n2 * nh;
+    const long long off = (long long)k2i * nh + c0;
+    const float norm = (float)m.norm;
+    const float alpha = (float)m.alpha;
+    load_twiddles(tw_s, tw, 1 << logT, tid);
+    for (int a = 0; a < 3; ++a) {
+        const float2* src = data + a * nspec;
+        stage<E>(T + a * tile, tile, tid, [&](int e) {
+            const int r = e / CW, c = e - r * CW;
+            return (c < cw) ? src[off + r * stride + c] : make_float2(0.f, 0.f);
+        });
+    }
+    __syncthreads();
+    for (int a = 0; a < 3; ++a) lds_fft<-1, E, true>(T + a * tile, l1, CW, 1, CW, tw_s, logT, tid);
+    const int k2 = signed_k(k2i, m.n2);
+    const float kd2 = deriv_k(k2i, m.n2);
+    for (int e = tid; e < tile; e += kThreads) {
+        const int r = e / CW, c = e - r * CW;
+        const int k1 = signed_k(r, m.n1), k3 = c0 + c;
+        const float kd1 = deriv_k(r, m.n1), kd3 = deriv_k(k3, m.n3);
+        const float kk = (float)(k1 * k1 + k2 * k2 + k3 * k3);
+        const float2 t0 = T[e], t1 = T[tile + e], t2 = T[2 * tile + e];
+        const float2 q = make_float2(kd1 * t0.x + kd2 * t1.x + kd3 * t2.x,
+                                     kd1 * t0.y + kd2 * t1.y + kd3 * t2.y);
+        float s1, s2 = 0.f;
+        if (CM == NI_PROJECT) {
+            s1 = norm;
+            if (kk > 0.f) {
+                const float ba = beta * (1.f / kk + 1.f);
+                s2 = -norm * (ba / (alpha + ba)) / kk;
+            }
+        } else {
+            s1 = 0.f;
+            if (kk > 0.f) s2 = norm * beta * (1.f / kk + 1.f);
+        }
+        T[e] = make_float2(s1 * t0.x + s2 * kd1 * q.x, s1 * t0.y + s2 * kd1 * q.y);
+        T[tile + e] = make_float2(s1 * t1.x + s2 * kd2 * q.x, s1 * t1.y + s2 * kd2 * q.y);
+        T[2 * tile + e] = make_float2(s1 * t2.x + s2 * kd3 * q.x, s1 * t2.y + s2 * kd3 * q.y);
+    }
+    __syncthreads();
+    for (int a = 0; a < 3; ++a) {
+        float2* buf = T + a * tile;
+        lds_fft<+1, E, true>(buf, l1, CW, 1, CW, tw_s, logT, tid);
+        float2* dst = data + a * nspec;
+        for (int e = tid; e < tile; e += kThreads) {
+            const int r = e / CW, c = e - r * CW;
+            if (c < cw) dst[off + r * stride + c] = buf[e];
+        }
+    }
+}
+
 // ------------------------------------------------------------- host side
 // Kernels whose dynamic LDS exceeds the 64 KiB default opt in to the larger
 // gfx950 allocation (160 KiB per CU).
@@ -615,6 +689,25 @@ int fused_x1(const Geo& g, const SpectralWork& w, const float2* in, float2* out,
     }
     CL_LAUNCH_CHECK();
     return 0;
+}
+
+template <int CM>
+int coupled_x1(const Geo& g, const SpectralWork& w, float2* spec, Mult m, double beta,
+               hipStream_t s) {
+    const int CW = tile_cols(g.n1, g.nh, CLAIRE_FFT_X1_ELEMS);
+    const int logT = ilog2(w.tw_n);
+    const size_t sh = sizeof(float2) * ((1 << logT) + (size_t)3 * g.n1 * CW);
+    dim3 grid((g.nh + CW - 1) / CW, g.n2, 1);
+    auto go = [&](auto kern) -> int {
+        CL_TRY(allow_lds(kern, sh));
+        hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, s, spec, g.l1, CW, g.nh, g.nspec, m,
+                           (float)beta, w.tw, logT);
+        CL_LAUNCH_CHECK();
+        return 0;
+    };
+    if (g.n1 * CW <= 8 * kThreads) return go(k_x1_coupled<CM, 8>);
+    if (g.n1 * CW <= 16 * kThreads) return go(k_x1_coupled<CM, 16>);
+    return go(k_x1_coupled<CM, 32>);
 }
 
 int reg_x1(const Geo& g, const SpectralWork& w, const double2* in, float2* out, Mult m,
@@ -808,6 +901,33 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         return CLAIRE_EINVAL;
     }
     return 0;
+}
+
+int spectral_ni(const Geo& g, SpectralWork& w, NiMode mode, const float* in, float* out,
+                double alpha, double beta, hipStream_t s, const float* add,
+                const float* dot_with, Reducer* red, int slot) {
+    if (dot_with && (!red || add)) {
+        set_error("fused dot product needs a reducer and no addend");
+        return CLAIRE_EINVAL;
+    }
+    if (!(beta > 0.0)) {
+        set_error("the near-incompressible operators need beta > 0");
+        return CLAIRE_EINVAL;
+    }
+    Mult m;
+    m.n1 = g.n1;
+    m.n2 = g.n2;
+    m.n3 = g.n3;
+    m.alpha = alpha;
+    m.p = 1;
+    m.norm = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+    float2* S = w.spec;
+    CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
+    CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
+    if (mode == NI_PROJECT) CL_TRY(coupled_x1<NI_PROJECT>(g, w, S, m, beta, s));
+    else CL_TRY(coupled_x1<NI_PENALTY>(g, w, S, m, beta, s));
+    CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
+    return inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot);
 }
 
 int spectral_forward(const Geo& g, const SpectralWork& w, const float* in, float2* spec,

@@ -75,6 +75,19 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
                    const float* add = nullptr, const float* dot_with = nullptr,
                    Reducer* red = nullptr, int slot = 0);
 
+// Near-incompressible model (3 -> 3, components coupled per Fourier mode;
+// k_d the odd-derivative wavenumbers, Nyquist 0):
+//   NI_PROJECT: out = (I - grad M Delta^{-1} div) in,
+//               M = (alpha (beta (-Delta^{-1} + id))^{-1} + id)^{-1};
+//   NI_PENALTY: out = -grad beta (-Delta^{-1} + id) div in.
+// `add` (nullable) is added to the result; with dot_with, <out, dot_with> is
+// summed into red->result[slot] (not together with add). in and out must not
+// overlap. beta > 0.
+enum NiMode { NI_PROJECT = 0, NI_PENALTY = 1 };
+int spectral_ni(const Geo& g, SpectralWork& w, NiMode mode, const float* in, float* out,
+                double alpha, double beta, hipStream_t s, const float* add = nullptr,
+                const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
+
 // ----------------------------------------------- finite differences
 // FD8 gradient (1 -> 3 fields) and divergence (3 -> 1), periodic.
 int launch_fd8_grad(const Geo& g, const float* u, float* out, hipStream_t s);

@@ -1,0 +1,132 @@
+"""Near-incompressible model (appendix) on the GPU against the FP64 oracle:
+the projection K = I - grad M Delta^{-1} div and the penalty operator
+-grad beta (-Delta^{-1} + id) div alone (non-cubic shapes, input with Nyquist
+content), the setup (g = alpha L v + K b and J with the divergence penalty),
+the Hessian matvec in float32 and mixed precision, the objective entry, one
+Gauss--Newton step and a full solve.
+
+Bars as for the plain model: 1e-5 max-norm relative for operators, setup and
+float32 matvec; 1e-3 for the mixed matvec; 1e-4 for v and J after GN steps.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import blob_problem, f32, rel_err
+from synthetic import bandlimited_velocity, noise
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_17493_amd import claire
+    return claire
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [(16, 32, 64), (32, 32, 32), (64, 16, 8)])
+@pytest.mark.parametrize("alpha,beta", [(1e-3, 1e-4), (1e-2, 1e-2)])
+def test_ni_operators(C, n, alpha, beta):
+    grid = O.Grid(n)
+    u = f32(bandlimited_velocity(n, 21, max(1, min(n) // 4), 1.0) + noise((3,) + n, 22, 0.05))
+    with C.Context(n, 1, alpha, 1) as ctx:
+        ctx.set_beta(beta)
+        kp = host(ctx.spectral(C.OP_NI_PROJECT, dev(u)))
+        pen = host(ctx.spectral(C.OP_NI_PENALTY, dev(u)))
+    ek = rel_err(kp, O.ni_project(grid, u, alpha, beta))
+    ep = rel_err(pen, O.divergence_penalty_gradient(grid, u, beta))
+    print("NI %s alpha %g beta %g: project %.2e, penalty %.2e" % (n, alpha, beta, ek, ep))
+    assert ek <= TOL and ep <= TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_setup_and_matvec_ni(C, precision):
+    nt, alpha, beta = 4, 1e-2, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v = f32(0.5 * vstar)
+    vt = f32(bandlimited_velocity(grid.n, 77, 4, 0.5))
+    st = O.setup_velocity(grid, m0, m1, v, alpha, nt, 1, beta=beta)
+    ref = O.hessian_matvec(st, vt)
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_beta(beta)
+        ctx.set_precision(precision)
+        ctx.set_velocity(dev(v))
+        g, J = ctx.gradient()
+        hv = host(ctx.hessian_matvec(dev(vt)))
+        Jobj = ctx.objective(dev(v))
+        errs = dict(g=rel_err(host(g), st.g), J=abs(J - st.J) / st.J,
+                    Jobj=abs(Jobj - st.J) / st.J, Hv=rel_err(hv, ref))
+    print("NI setup, precision %d:" % precision, {k: "%.2e" % e for k, e in errs.items()},
+          "J_div / J = %.3f" % (st.J_div / st.J))
+    assert st.J_div > 1e-3 * st.J                       # the penalty is exercised
+    assert max(errs["g"], errs["J"], errs["Jobj"]) <= TOL
+    assert errs["Hv"] <= (TOL if precision == 0 else 1e-3)
+
+
+def test_errors_ni(C):
+    with C.Context((16, 16, 16), 2, 1e-2, 2) as ctx:
+        with pytest.raises(C.ClaireError) as e:
+            ctx.set_beta(1e-4)                              # H2 seminorm
+        assert e.value.code == -1
+    with C.Context((16, 16, 16), 2, 1e-2, 1) as ctx:
+        with pytest.raises(C.ClaireError) as e:
+            ctx.spectral(C.OP_NI_PROJECT, torch.zeros((3, 16, 16, 16), device="cuda"))
+        assert e.value.code == -1                           # beta = 0
+        grid, m0, m1, _ = blob_problem(n=(16, 16, 16), kmax=3)
+        ctx.set_images(dev(m0), dev(m1))
+        with pytest.raises(C.ClaireError) as e:
+            ctx.solve(beta=1e-4, precond=C.PRECOND_TWOLEVEL)
+        assert e.value.code == -1
+        with pytest.raises(C.ClaireError) as e:
+            ctx.solve(beta=-1.0)
+        assert e.value.code == -1
+
+
+def test_one_gn_step_ni(C):
+    nt, alpha, beta = 4, 1e-2, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v_ref, _, s_ref = O.gn_solve(grid, m0, m1, nt, 1, [alpha], max_gn=1, fixed_pcg=10, beta=beta)
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v, st = ctx.solve(max_gn=1, fixed_pcg_iters=10, beta=beta)
+        vh = host(v)
+    e = rel_err(vh, v_ref)
+    print("NI GN step: v %.2e, J %.2e, trials %d/%d" % (
+        e, abs(st["J"] - s_ref.J) / s_ref.J, st["linesearch_trials"], s_ref.ls_trials))
+    assert st["matvecs"] == 10 and st["linesearch_trials"] == s_ref.ls_trials
+    assert e < 1e-4
+    assert abs(st["J0"] - s_ref.J0) <= TOL * s_ref.J0
+    assert abs(st["J"] - s_ref.J) <= 1e-4 * s_ref.J
+
+
+@pytest.mark.parametrize("alpha,beta", [(1e-2, 1e-2), (1e-3, 1e-4)])
+def test_full_solve_ni(C, alpha, beta):
+    nt = 4
+    grid, m0, m1, vstar = blob_problem()
+    v_ref, _, s_ref = O.gn_solve(grid, m0, m1, nt, 1, [alpha], beta=beta)
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v, st = ctx.solve(beta=beta)
+        vh = host(v)
+    print("NI solve alpha %g beta %g: GN %d/%d, matvecs %d/%d, J %.7g/%.7g, v %.2e" % (
+        alpha, beta, st["gn_iters"], s_ref.gn_iters, st["matvecs"], s_ref.matvecs, st["J"],
+        s_ref.J, rel_err(vh, v_ref)))
+    assert st["status"] == 0 and st["rel_grad"] <= 5e-2
+    assert st["gn_iters"] == s_ref.gn_iters and st["matvecs"] == s_ref.matvecs
+    assert rel_err(vh, v_ref) < 1e-4
+    assert abs(st["J"] - s_ref.J) <= 1e-4 * s_ref.J
