@@ -36,6 +36,32 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
                                                                        : CLAIRE_EDEVICE;
 }
 
+namespace {
+bool pow2(int v) { return v >= 8 && v <= 1024 && (v & (v - 1)) == 0; }
+
+// even, in [8, 1024], no prime factor other than 2, 3 and 5
+bool smooth_even(int v) {
+    if (v < 8 || v > 1024 || (v & 1)) return false;
+    for (int f : {2, 3, 5})
+        while (v % f == 0) v /= f;
+    return v == 1;
+}
+}  // namespace
+
+int check_extents(const int nx[3]) {
+    if (!pow2(nx[2])) {
+        set_error("n3 = %d: the contiguous extent must be a power of two in [8, 1024]", nx[2]);
+        return CLAIRE_EINVAL;
+    }
+    for (int a = 0; a < 2; ++a)
+        if (!smooth_even(nx[a])) {
+            set_error("n%d = %d: must be an even product of 2, 3 and 5 in [8, 1024]", a + 1,
+                      nx[a]);
+            return CLAIRE_EINVAL;
+        }
+    return 0;
+}
+
 Geo make_geo(const int nx[3]) {
     Geo g;
     g.n1 = nx[0];
@@ -48,6 +74,7 @@ Geo make_geo(const int nx[3]) {
     g.nh = g.n3 / 2 + 1;
     g.n = (long long)g.n1 * g.n2 * g.n3;
     g.nspec = (long long)g.n1 * g.n2 * g.nh;
+    g.pow2 = (1 << g.l1) == g.n1 && (1 << g.l2) == g.n2 && (1 << g.l3) == g.n3;
     return g;
 }
 
@@ -126,15 +153,9 @@ void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
 
-bool pow2(int v) { return v >= 8 && v <= 1024 && (v & (v - 1)) == 0; }
-
 int check_args(const int nx[3], int nt, double alpha, int reg_order) {
     if (!nx) { set_error("nx is NULL"); return CLAIRE_EINVAL; }
-    for (int a = 0; a < 3; ++a)
-        if (!pow2(nx[a])) {
-            set_error("n%d = %d: each extent must be a power of two in [8, 1024]", a + 1, nx[a]);
-            return CLAIRE_EINVAL;
-        }
+    CL_TRY(check_extents(nx));
     if (nt < 1 || nt > 64) { set_error("nt = %d out of range [1, 64]", nt); return CLAIRE_EINVAL; }
     if (!(alpha > 0.0) || !std::isfinite(alpha)) { set_error("alpha must be positive"); return CLAIRE_EINVAL; }
     if (reg_order != 1 && reg_order != 2) { set_error("reg_order must be 1 or 2"); return CLAIRE_EINVAL; }

@@ -24,6 +24,7 @@ struct Lat {
 __device__ __forceinline__ float ld(const float* p, unsigned i) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (i << 2));
 }
+__device__ __forceinline__ float ldf(const float* p, unsigned i) { return ld(p, i); }
 
 // FD8 sums along the three axes at voxel idx of field u (not yet scaled by
 // 1 / (840 h)).
@@ -87,6 +88,54 @@ __global__ __launch_bounds__(kThreads) void k_fd8_div(const float* __restrict__ 
     out[i] = c1 * d1 + c2 * d2 + c3 * d3;
 }
 
+// General extents (n1, n2 not powers of two): neighbours along x1 and x2
+// by a modulo wrap, x3 (a power of two) by a mask.
+struct LatG {
+    int n1, n2, m3, l3;
+};
+
+__device__ __forceinline__ int wrapn(int x, int n) {
+    const int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+template <bool DIV>
+__global__ __launch_bounds__(kThreads) void k_fd8_gen(const float* __restrict__ u,
+                                                      float* __restrict__ out, LatG L,
+                                                      long long n, float c1, float c2,
+                                                      float c3) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const unsigned idx = (unsigned)i;
+    const int i3 = idx & L.m3;
+    const unsigned r = idx >> L.l3;
+    const int i2 = (int)(r % (unsigned)L.n2);
+    const int i1 = (int)(r / (unsigned)L.n2);
+    const float* u1 = u;
+    const float* u2 = DIV ? u + n : u;
+    const float* u3 = DIV ? u + 2 * n : u;
+    auto a1 = [&](int s) {
+        return ldf(u1, (unsigned)(((wrapn(i1 + s, L.n1) * L.n2 + i2) << L.l3) + i3));
+    };
+    auto a2 = [&](int s) {
+        return ldf(u2, (unsigned)(((i1 * L.n2 + wrapn(i2 + s, L.n2)) << L.l3) + i3));
+    };
+    auto a3 = [&](int s) { return ldf(u3, (idx & ~(unsigned)L.m3) | ((i3 + s) & L.m3)); };
+    const float d1 = 672.f * (a1(1) - a1(-1)) - 168.f * (a1(2) - a1(-2)) +
+                     32.f * (a1(3) - a1(-3)) - 3.f * (a1(4) - a1(-4));
+    const float d2 = 672.f * (a2(1) - a2(-1)) - 168.f * (a2(2) - a2(-2)) +
+                     32.f * (a2(3) - a2(-3)) - 3.f * (a2(4) - a2(-4));
+    const float d3 = 672.f * (a3(1) - a3(-1)) - 168.f * (a3(2) - a3(-2)) +
+                     32.f * (a3(3) - a3(-3)) - 3.f * (a3(4) - a3(-4));
+    if (DIV) {
+        out[i] = c1 * d1 + c2 * d2 + c3 * d3;
+    } else {
+        out[i] = c1 * d1;
+        out[n + i] = c2 * d2;
+        out[2 * n + i] = c3 * d3;
+    }
+}
+
 Lat make_lat(const Geo& g) {
     Lat L;
     L.m1 = g.n1 - 1;
@@ -103,6 +152,13 @@ float inv840h(int n) { return (float)((double)n / (2.0 * M_PI * 840.0)); }
 
 int launch_fd8_grad(const Geo& g, const float* u, float* out, hipStream_t s) {
     const unsigned nb = (unsigned)((g.n + kThreads - 1) / kThreads);
+    if (!g.pow2) {
+        hipLaunchKernelGGL(k_fd8_gen<false>, dim3(nb), dim3(kThreads), 0, s, u, out,
+                           LatG{g.n1, g.n2, g.n3 - 1, g.l3}, g.n, inv840h(g.n1), inv840h(g.n2),
+                           inv840h(g.n3));
+        CL_LAUNCH_CHECK();
+        return 0;
+    }
     hipLaunchKernelGGL(k_fd8_grad, dim3(nb), dim3(kThreads), 0, s, u, out, make_lat(g), g.n,
                        inv840h(g.n1), inv840h(g.n2), inv840h(g.n3));
     CL_LAUNCH_CHECK();
@@ -111,6 +167,13 @@ int launch_fd8_grad(const Geo& g, const float* u, float* out, hipStream_t s) {
 
 int launch_fd8_div(const Geo& g, const float* v, float* out, hipStream_t s) {
     const unsigned nb = (unsigned)((g.n + kThreads - 1) / kThreads);
+    if (!g.pow2) {
+        hipLaunchKernelGGL(k_fd8_gen<true>, dim3(nb), dim3(kThreads), 0, s, v, out,
+                           LatG{g.n1, g.n2, g.n3 - 1, g.l3}, g.n, inv840h(g.n1), inv840h(g.n2),
+                           inv840h(g.n3));
+        CL_LAUNCH_CHECK();
+        return 0;
+    }
     hipLaunchKernelGGL(k_fd8_div, dim3(nb), dim3(kThreads), 0, s, v, out, make_lat(g), g.n,
                        inv840h(g.n1), inv840h(g.n2), inv840h(g.n3));
     CL_LAUNCH_CHECK();

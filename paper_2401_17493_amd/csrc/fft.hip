@@ -20,6 +20,11 @@
 // each stage goes through registers so a single LDS buffer suffices.
 // Twiddles come from tables built on the host in double precision.
 //
+// General extents (n1, n2 even products of 2, 3 and 5; n3 a power of two):
+// the x3 passes are the same; the x2 and x1 column transforms are
+// mixed-radix Stockham stages (radix 4, 2, 3, 5) between two LDS buffers, and
+// the multiplier is a separate pointwise pass over the full spectrum.
+//
 // Precision. The multiplier alpha |k|^{2p} of L amplifies the forward
 // transform's round-off at high wavenumbers by up to (k_max/k_data)^{2p}; in
 // float32 that reaches 1e-4..1e-2 of the result for smooth fields. The
@@ -543,6 +548,200 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     }
 }
 
+// ------------------------------------------------------- general extents
+// Radices of a mixed-radix transform in stage order.
+struct RadixPlan {
+    int N;
+    int ns;
+    int R[16];
+};
+
+// Radix-R DFT y_m = sum_r x_r exp(DIR 2 pi i r m / R) of registers x, R in
+// {2, 3, 4, 5}.
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void small_dft(const C* x, C* y) {
+    using T = typename RealOf<C>::T;
+    if constexpr (R == 2) {
+        y[0] = cadd(x[0], x[1]);
+        y[1] = csub(x[0], x[1]);
+    } else if constexpr (R == 4) {
+        const C b0 = cadd(x[0], x[2]), b1 = csub(x[0], x[2]);
+        const C b2 = cadd(x[1], x[3]);
+        C b3 = csub(x[1], x[3]);
+        b3 = (DIR < 0) ? cx<C>(b3.y, -b3.x) : cx<C>(-b3.y, b3.x);
+        y[0] = cadd(b0, b2);
+        y[1] = cadd(b1, b3);
+        y[2] = csub(b0, b2);
+        y[3] = csub(b1, b3);
+    } else {
+        // cos/sin of 2 pi q / R for q < R
+        T cs[R], sn[R];
+        if constexpr (R == 3) {
+            cs[0] = T(1); sn[0] = T(0);
+            cs[1] = T(-0.5); sn[1] = T(0.86602540378443864676);
+            cs[2] = T(-0.5); sn[2] = T(-0.86602540378443864676);
+        } else {
+            cs[0] = T(1); sn[0] = T(0);
+            cs[1] = T(0.30901699437494742410); sn[1] = T(0.95105651629515357212);
+            cs[2] = T(-0.80901699437494742410); sn[2] = T(0.58778525229247312917);
+            cs[3] = T(-0.80901699437494742410); sn[3] = T(-0.58778525229247312917);
+            cs[4] = T(0.30901699437494742410); sn[4] = T(-0.95105651629515357212);
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            C acc = x[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int q = (r * m) % R;
+                const C w = cx<C>(cs[q], DIR < 0 ? -sn[q] : sn[q]);
+                acc = cadd(acc, cmul(x[r], w));
+            }
+            y[m] = acc;
+        }
+    }
+}
+
+// One Stockham stage on CW columns: butterfly j (of N/R per column) reads
+// src[j + r N/R], twiddles by exp(DIR 2 pi i r k / (Ns R)), k = j mod Ns, and
+// writes dst[(j - k) R + k + m Ns]. Element e of row q is at q CW + column.
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void stage_gen(const C* src, C* dst, int N, int CW, int Ns,
+                                          const C* tw, int tid) {
+    const int M = N / R;
+    const int tstep = N / (Ns * R);
+    for (int t = tid; t < M * CW; t += kThreads) {
+        const int j = t / CW, col = t - j * CW;
+        const int k = j % Ns;
+        C x[R], y[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            C v = src[(j + r * M) * CW + col];
+            if (r > 0) {
+                C w = tw[r * k * tstep];
+                if (DIR > 0) w.y = -w.y;
+                v = cmul(v, w);
+            }
+            x[r] = v;
+        }
+        small_dft<R, DIR>(x, y);
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int m = 0; m < R; ++m) dst[(o + m * Ns) * CW + col] = y[m];
+    }
+}
+
+// Column transforms of length N = plan.N along an axis with element stride
+// `stride`; tiles of CW consecutive half-complex x3 bins, one tile row per
+// blockIdx.y (ystride apart), component blockIdx.z.
+template <int DIR, typename C>
+__global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int CW,
+                                                       long long stride, long long ystride,
+                                                       int nh, long long nspec,
+                                                       const C* __restrict__ tw,
+                                                       RadixPlan plan) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = plan.N;
+    C* tw_s = reinterpret_cast<C*>(smem_raw);
+    C* A = tw_s + N;
+    C* B = A + N * CW;
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * CW;
+    const int cw = min(CW, nh - c0);
+    C* base = data + blockIdx.z * nspec + blockIdx.y * ystride + c0;
+    for (int q = tid; q < N; q += kThreads) tw_s[q] = tw[q];
+    for (int e = tid; e < N * CW; e += kThreads) {
+        const int r = e / CW, c = e - r * CW;
+        A[e] = (c < cw) ? base[r * stride + c] : cx<C>(0, 0);
+    }
+    __syncthreads();
+    C* src = A;
+    C* dst = B;
+    int Ns = 1;
+    for (int st = 0; st < plan.ns; ++st) {
+        const int R = plan.R[st];
+        if (R == 4) stage_gen<4, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else if (R == 2) stage_gen<2, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else if (R == 3) stage_gen<3, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else stage_gen<5, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        __syncthreads();
+        C* t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+    for (int e = tid; e < N * CW; e += kThreads) {
+        const int r = e / CW, c = e - r * CW;
+        if (c < cw) base[r * stride + c] = src[e];
+    }
+}
+
+// Pointwise multiplier of every spectral operator on a full spectrum (general
+// grids): GRAD 1 -> 3, DIV 3 -> 1, REG (from the double spectrum), REG_INV,
+// REG_ISQRT, and the coupled near-incompressible modes; in place on S.
+enum GenMult { GM_GRAD, GM_DIV, GM_REG, GM_REG_INV, GM_REG_ISQRT, GM_NI_PROJECT, GM_NI_PENALTY };
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_mult_gen(float2* __restrict__ S,
+                                                       const double2* __restrict__ S64,
+                                                       int n1, int n2, int n3, int nh,
+                                                       long long nspec, double alpha, int p,
+                                                       double beta, double norm) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= nspec) return;
+    const int i3 = (int)(idx % nh);
+    const long long r = idx / nh;
+    const int i2 = (int)(r % n2);
+    const int i1 = (int)(r / n2);
+    const int k1 = signed_k(i1, n1), k2 = signed_k(i2, n2), k3 = i3;
+    const float kd[3] = {deriv_k(i1, n1), deriv_k(i2, n2), deriv_k(i3, n3)};
+    const float nf = (float)norm;
+    if (MODE == GM_GRAD) {
+        const float2 a = S[idx];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[c * nspec + idx] = cscale(times_i(a), kd[c] * nf);
+    } else if (MODE == GM_DIV) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc = cadd(acc, cscale(times_i(S[c * nspec + idx]), kd[c] * nf));
+        S[idx] = acc;
+    } else if (MODE == GM_REG) {
+        const double f = norm * alpha * reg_symbol(p, k1, k2, k3);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 a = S64[c * nspec + idx];
+            S[c * nspec + idx] = make_float2((float)(a.x * f), (float)(a.y * f));
+        }
+    } else if (MODE == GM_REG_INV || MODE == GM_REG_ISQRT) {
+        const double sym = alpha * reg_symbol(p, k1, k2, k3);
+        const float f = (float)(sym == 0.0 ? norm
+                                           : (MODE == GM_REG_INV ? norm / sym : norm / sqrt(sym)));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[c * nspec + idx] = cscale(S[c * nspec + idx], f);
+    } else {
+        const double kk = (double)k1 * k1 + (double)k2 * k2 + (double)k3 * k3;
+        float2 t[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = S[c * nspec + idx];
+        const float2 q = make_float2(kd[0] * t[0].x + kd[1] * t[1].x + kd[2] * t[2].x,
+                                     kd[0] * t[0].y + kd[1] * t[1].y + kd[2] * t[2].y);
+        float s1, s2 = 0.f;
+        if (MODE == GM_NI_PROJECT) {
+            s1 = nf;
+            if (kk > 0.0) {
+                const double ba = beta * (1.0 / kk + 1.0);
+                s2 = (float)(-norm * (ba / (alpha + ba)) / kk);
+            }
+        } else {
+            s1 = 0.f;
+            if (kk > 0.0) s2 = (float)(norm * beta * (1.0 / kk + 1.0));
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            S[c * nspec + idx] = make_float2(s1 * t[c].x + s2 * kd[c] * q.x,
+                                             s1 * t[c].y + s2 * kd[c] * q.y);
+    }
+}
+
 // ------------------------------------------------------------- host side
 // Kernels whose dynamic LDS exceeds the 64 KiB default opt in to the larger
 // gfx950 allocation (160 KiB per CU).
@@ -691,6 +890,81 @@ int fused_x1(const Geo& g, const SpectralWork& w, const float2* in, float2* out,
     return 0;
 }
 
+RadixPlan make_plan(int N) {
+    RadixPlan p;
+    p.N = N;
+    p.ns = 0;
+    int m = N;
+    while (m % 4 == 0) { p.R[p.ns++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.R[p.ns++] = 2; m /= 2; }
+    while (m % 3 == 0) { p.R[p.ns++] = 3; m /= 3; }
+    while (m % 5 == 0) { p.R[p.ns++] = 5; m /= 5; }
+    return p;   // m == 1 for extents accepted by make_geo's caller
+}
+
+// General-grid column transform along x2 (axis 2) or x1 (axis 1)
+template <int DIR, typename C>
+int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_t s) {
+    const int N = axis == 1 ? g.n1 : g.n2;
+    // two tiles and the twiddle table within 64 KiB of LDS
+    int CW = (int)((65536 / sizeof(C) - N) / (2 * N));
+    if (CW > 16) CW = 16;
+    if (CW > g.nh) CW = g.nh;
+    if (CW < 1) {
+        set_error("column length %d exceeds the general-grid FFT tile", N);
+        return CLAIRE_EINVAL;
+    }
+    const size_t sh = sizeof(C) * ((size_t)N + 2 * (size_t)N * CW);
+    const long long stride = axis == 1 ? (long long)g.n2 * g.nh : g.nh;
+    const long long ystride = axis == 1 ? g.nh : (long long)g.n2 * g.nh;
+    dim3 grid((g.nh + CW - 1) / CW, axis == 1 ? g.n2 : g.n1, ncomp);
+    hipLaunchKernelGGL((k_cols_gen<DIR, C>), grid, dim3(kThreads), sh, s, spec, CW, stride,
+                       ystride, g.nh, g.nspec, tw, make_plan(N));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+template <int MODE>
+int mult_gen(const Geo& g, SpectralWork& w, double alpha, int p, double beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_mult_gen<MODE>, dim3((unsigned)((g.nspec + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, w.spec, w.spec64, g.n1, g.n2, g.n3, g.nh, g.nspec,
+                       alpha, p, beta, 1.0 / ((double)g.n1 * g.n2 * g.n3));
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+// Spectral operator on a general grid: x3 R2C, x2 and x1 forward columns,
+// pointwise multiplier, x1 and x2 inverse columns, x3 C2R (with the addend
+// or the fused dot product).
+int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float* out,
+                 double alpha, int p, double beta, hipStream_t s, const float* add,
+                 const float* dot_with, Reducer* red, int slot) {
+    const int nin = mode == GM_GRAD ? 1 : 3;
+    const int nout = mode == GM_DIV ? 1 : 3;
+    float2* S = w.spec;
+    if (mode == GM_REG) {
+        CL_TRY(fwd_x3(g, w.tw64, w.tw_n, in, w.spec64, 3, s));
+        CL_TRY(cols_gen<-1>(g, 2, w.tw2_64, w.spec64, 3, s));
+        CL_TRY(cols_gen<-1>(g, 1, w.tw1_64, w.spec64, 3, s));
+    } else {
+        CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, nin, s));
+        CL_TRY(cols_gen<-1>(g, 2, w.tw2, S, nin, s));
+        CL_TRY(cols_gen<-1>(g, 1, w.tw1, S, nin, s));
+    }
+    switch (mode) {
+    case GM_GRAD: CL_TRY(mult_gen<GM_GRAD>(g, w, alpha, p, beta, s)); break;
+    case GM_DIV: CL_TRY(mult_gen<GM_DIV>(g, w, alpha, p, beta, s)); break;
+    case GM_REG: CL_TRY(mult_gen<GM_REG>(g, w, alpha, p, beta, s)); break;
+    case GM_REG_INV: CL_TRY(mult_gen<GM_REG_INV>(g, w, alpha, p, beta, s)); break;
+    case GM_REG_ISQRT: CL_TRY(mult_gen<GM_REG_ISQRT>(g, w, alpha, p, beta, s)); break;
+    case GM_NI_PROJECT: CL_TRY(mult_gen<GM_NI_PROJECT>(g, w, alpha, p, beta, s)); break;
+    default: CL_TRY(mult_gen<GM_NI_PENALTY>(g, w, alpha, p, beta, s)); break;
+    }
+    CL_TRY(cols_gen<+1>(g, 1, w.tw1, S, nout, s));
+    CL_TRY(cols_gen<+1>(g, 2, w.tw2, S, nout, s));
+    return inv_x3(g, w, S, out, add, nout, s, dot_with, red, slot);
+}
+
 template <int CM>
 int coupled_x1(const Geo& g, const SpectralWork& w, float2* spec, Mult m, double beta,
                hipStream_t s) {
@@ -811,6 +1085,22 @@ __global__ __launch_bounds__(kThreads) void k_spec_combine(float2* __restrict__ 
 
 }  // namespace
 
+// exp(-2 pi i q / N), q < N, in float and double
+int make_table(int N, float2** tf, double2** td) {
+    std::vector<float2> h(N);
+    std::vector<double2> hd(N);
+    for (int q = 0; q < N; ++q) {
+        const double a = -2.0 * M_PI * (double)q / (double)N;
+        hd[q] = make_double2(std::cos(a), std::sin(a));
+        h[q] = make_float2((float)hd[q].x, (float)hd[q].y);
+    }
+    CL_HIP(hipMalloc(tf, sizeof(float2) * N));
+    CL_HIP(hipMemcpy(*tf, h.data(), sizeof(float2) * N, hipMemcpyHostToDevice));
+    CL_HIP(hipMalloc(td, sizeof(double2) * N));
+    CL_HIP(hipMemcpy(*td, hd.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
+    return 0;
+}
+
 int spectral_init(SpectralWork& w, const Geo& g) {
     int T = g.n1;
     if (g.n2 > T) T = g.n2;
@@ -818,6 +1108,13 @@ int spectral_init(SpectralWork& w, const Geo& g) {
     if (T > kMaxTw) {
         set_error("grid extent %d exceeds the FFT limit %d", T, kMaxTw);
         return CLAIRE_EINVAL;
+    }
+    if (!g.pow2) {
+        // x3 passes index a power-of-two table by shifts; x1 and x2 columns
+        // use tables of their own lengths
+        T = g.n3;
+        CL_TRY(make_table(g.n1, &w.tw1, &w.tw1_64));
+        CL_TRY(make_table(g.n2, &w.tw2, &w.tw2_64));
     }
     w.tw_n = T;
     std::vector<float2> h(T);
@@ -839,6 +1136,10 @@ int spectral_init(SpectralWork& w, const Geo& g) {
 void spectral_free(SpectralWork& w) {
     if (w.tw) (void)hipFree(w.tw);
     if (w.tw64) (void)hipFree(w.tw64);
+    if (w.tw1) (void)hipFree(w.tw1);
+    if (w.tw1_64) (void)hipFree(w.tw1_64);
+    if (w.tw2) (void)hipFree(w.tw2);
+    if (w.tw2_64) (void)hipFree(w.tw2_64);
     if (w.spec) (void)hipFree(w.spec);
     if (w.spec64) (void)hipFree(w.spec64);
     w = SpectralWork();
@@ -850,6 +1151,14 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
     if (dot_with && (mode != SPEC_REG_INV || !red || add)) {
         set_error("fused dot product only with SPEC_REG_INV, a reducer and no addend");
         return CLAIRE_EINVAL;
+    }
+    if (!g.pow2) {
+        static const int gm[] = {GM_GRAD, GM_DIV, GM_REG, GM_REG_INV, GM_REG_ISQRT};
+        if ((int)mode < 0 || (int)mode > 4) {
+            set_error("unknown spectral mode %d", (int)mode);
+            return CLAIRE_EINVAL;
+        }
+        return spectral_gen(g, w, gm[mode], in, out, alpha, p, 0.0, s, add, dot_with, red, slot);
     }
     Mult m;
     m.n1 = g.n1;
@@ -914,6 +1223,9 @@ int spectral_ni(const Geo& g, SpectralWork& w, NiMode mode, const float* in, flo
         set_error("the near-incompressible operators need beta > 0");
         return CLAIRE_EINVAL;
     }
+    if (!g.pow2)
+        return spectral_gen(g, w, mode == NI_PROJECT ? GM_NI_PROJECT : GM_NI_PENALTY, in, out,
+                            alpha, 1, beta, s, add, dot_with, red, slot);
     Mult m;
     m.n1 = g.n1;
     m.n2 = g.n2;
@@ -933,14 +1245,23 @@ int spectral_ni(const Geo& g, SpectralWork& w, NiMode mode, const float* in, flo
 int spectral_forward(const Geo& g, const SpectralWork& w, const float* in, float2* spec,
                      int ncomp, hipStream_t s) {
     CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, spec, ncomp, s));
+    if (!g.pow2) {
+        CL_TRY(cols_gen<-1>(g, 2, w.tw2, spec, ncomp, s));
+        return cols_gen<-1>(g, 1, w.tw1, spec, ncomp, s);
+    }
     CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, spec, ncomp, s));
     return cols_x1<-1>(g, w.tw, w.tw_n, spec, ncomp, s);
 }
 
 int spectral_inverse(const Geo& g, const SpectralWork& w, float2* spec, float* out, int ncomp,
                      hipStream_t s) {
-    CL_TRY(cols_x1<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
-    CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
+    if (!g.pow2) {
+        CL_TRY(cols_gen<+1>(g, 1, w.tw1, spec, ncomp, s));
+        CL_TRY(cols_gen<+1>(g, 2, w.tw2, spec, ncomp, s));
+    } else {
+        CL_TRY(cols_x1<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
+        CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, spec, ncomp, s));
+    }
     return inv_x3(g, w, spec, out, nullptr, ncomp, s);
 }
 

@@ -11,16 +11,23 @@
 
 namespace claire {
 
-// Grid geometry: power-of-two extents, masks and shifts for periodic wrap.
+// Grid geometry. n3 (the contiguous axis) is a power of two; n1 and n2 are
+// even products of 2, 3 and 5. When all three are powers of two (pow2) the
+// tuned kernels run, with masks and shifts for the periodic wrap; otherwise
+// the general-extent kernels (modulo wrap, mixed-radix column FFTs).
 struct Geo {
     int n1, n2, n3;     // extents
-    int l1, l2, l3;     // log2 of the extents
+    int l1, l2, l3;     // log2 of the extents (l1, l2 only meaningful when pow2)
     int nh;             // n3/2 + 1: length of a half-complex x3 row
     long long n;        // voxels
     long long nspec;    // half-complex spectrum length n1*n2*nh
+    bool pow2;          // every extent a power of two
 };
 
 Geo make_geo(const int nx[3]);
+// CLAIRE_OK if nx is a supported grid (n3 a power of two, n1 and n2 even
+// products of 2, 3 and 5, all in [8, 1024]); else CLAIRE_EINVAL with a message
+int check_extents(const int nx[3]);
 
 struct Reducer;
 
@@ -51,7 +58,12 @@ struct SpectralWork {
     double2* spec64 = nullptr;  // [3][nspec]
     float2* tw = nullptr;       // [tw_n]
     double2* tw64 = nullptr;    // [tw_n]
-    int tw_n = 0;
+    int tw_n = 0;               // max extent (power-of-two grids), n3 otherwise
+    // general grids: exp(-2 pi i q / n_a), q < n_a, for the x1 and x2 columns
+    float2* tw1 = nullptr;
+    double2* tw1_64 = nullptr;
+    float2* tw2 = nullptr;
+    double2* tw2_64 = nullptr;
 };
 
 int spectral_init(SpectralWork& w, const Geo& g);

@@ -82,8 +82,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_step(float* __restrict__ x, flo
 int twolevel_init(TwoLevel& T, const Geo& gf) {
     if (T.ready) return 0;
     const int nc[3] = {gf.n1 / 2, gf.n2 / 2, gf.n3 / 2};
-    if (nc[0] < 8 || nc[1] < 8 || nc[2] < 8) {
-        set_error("the two-level preconditioner needs every extent >= 16");
+    if (check_extents(nc) != 0) {
+        set_error("the two-level preconditioner's coarse grid %dx%dx%d (half the extents) is "
+                  "not a supported grid: every extent >= 16 and n1/2, n2/2 even needed",
+                  nc[0], nc[1], nc[2]);
         return CLAIRE_EINVAL;
     }
     T.gc = make_geo(nc);

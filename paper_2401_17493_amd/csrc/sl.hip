@@ -5,8 +5,9 @@
 // so a query is (integer grid index) + (float displacement): the stencil
 // origin floor(d) is exact and a zero displacement returns grid values
 // bit-for-bit. One thread per output voxel, x3 fastest across the wavefront;
-// the 4x4x4 stencil is read with wrapped indices (extents are powers of two,
-// so the wrap is a mask).
+// the 4x4x4 stencil is read with wrapped indices: a mask when the extents are
+// powers of two (the LDS-staged kernels), a modulo along x1 and x2 on grids
+// with other extents (direct gathers, below).
 
 #include "internal.h"
 
@@ -581,9 +582,117 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
     }
 }
 
+// ------------------------------------------------------------------------
+// General extents: n1, n2 any even products of 2, 3, 5 (n3 a power of two).
+// Every gather reads its 4x4x4 stencil directly from global memory with a
+// modulo wrap along x1 and x2; the epilogues are those of the LDS kernels.
+struct GG {
+    int n1, n2, m3, l3;
+};
+
+GG make_gg(const Geo& g) { return GG{g.n1, g.n2, g.n3 - 1, g.l3}; }
+
+__device__ __forceinline__ int wrapn(int x, int n) {
+    const int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ void coords_gen(const GG& g, unsigned idx, int& i1, int& i2,
+                                           int& i3) {
+    i3 = (int)(idx & (unsigned)g.m3);
+    const unsigned r = idx >> g.l3;
+    i2 = (int)(r % (unsigned)g.n2);
+    i1 = (int)(r / (unsigned)g.n2);
+}
+
+__device__ __forceinline__ void make_stencil_gen(const GG& g, int i1, int i2, int i3, float d1,
+                                                 float d2, float d3, Stencil& st) {
+    const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
+    const int b1 = i1 + (int)f1 - 1, b2 = i2 + (int)f2 - 1, b3 = i3 + (int)f3 - 1;
+    cubic_basis(d1 - f1, st.w1);
+    cubic_basis(d2 - f2, st.w2);
+    cubic_basis(d3 - f3, st.w3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        st.o1[q] = (wrapn(b1 + q, g.n1) * g.n2) << g.l3;
+        st.o2[q] = wrapn(b2 + q, g.n2) << g.l3;
+        st.o3[q] = (b3 + q) & g.m3;
+    }
+}
+
+template <class Epi>
+__global__ __launch_bounds__(kThreads) void k_gather_gen(const float* __restrict__ src,
+                                                         const float* __restrict__ d, Epi epi,
+                                                         GG g, long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    const unsigned i = (unsigned)idx;
+    const auto pre = epi.load(i);
+    int i1, i2, i3;
+    coords_gen(g, i, i1, i2, i3);
+    Stencil st;
+    make_stencil_gen(g, i1, i2, i3, ldi(d, i), ldi(d + n, i), ldi(d + 2 * n, i), st);
+    float u;
+    gather<1>(src, n, st, &u);
+    epi.store(i, u, pre);
+}
+
+template <int NF>
+__global__ __launch_bounds__(kThreads) void k_interp_gen(const float* __restrict__ f,
+                                                         const float* __restrict__ d,
+                                                         float* __restrict__ out, GG g,
+                                                         long long n) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    int i1, i2, i3;
+    coords_gen(g, (unsigned)idx, i1, i2, i3);
+    Stencil st;
+    make_stencil_gen(g, i1, i2, i3, d[idx], d[n + idx], d[2 * n + idx], st);
+    float r[NF];
+    gather<NF>(f, n, st, r);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k * n + idx] = r[k];
+}
+
+// RK2 backtrace for +v and -v with direct gathers (same steps as
+// k_backtrace_lds): y~ = x + s c v(x), y = x + s (c/2)(v(x) + v(y~)), s = -1
+// for y+ and +1 for y-.
+__global__ __launch_bounds__(kThreads) void k_backtrace_gen(const float* __restrict__ v,
+                                                            float* __restrict__ dp,
+                                                            float* __restrict__ dm, GG g,
+                                                            long long n, float c1, float c2,
+                                                            float c3) {
+    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= n) return;
+    const float c[3] = {c1, c2, c3};
+    int i1, i2, i3;
+    coords_gen(g, (unsigned)idx, i1, i2, i3);
+    const float vx[3] = {v[idx], v[n + idx], v[2 * n + idx]};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const float sg = dir == 0 ? -1.f : 1.f;
+        Stencil st;
+        make_stencil_gen(g, i1, i2, i3, sg * c[0] * vx[0], sg * c[1] * vx[1], sg * c[2] * vx[2],
+                         st);
+        float u[3];
+        gather<3>(v, n, st, u);
+        float* out = dir == 0 ? dp : dm;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a * n + idx] = sg * 0.5f * c[a] * (vx[a] + u[a]);
+    }
+}
+
+unsigned blocks_for(long long n);
+
 template <class Epi>
 int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
                       const Epi& epi, hipStream_t s) {
+    if (!g.pow2) {
+        hipLaunchKernelGGL((k_gather_gen<Epi>), dim3(blocks_for(g.n)), dim3(kThreads), 0, s, src,
+                           disp, epi, make_gg(g), g.n);
+        CL_LAUNCH_CHECK();
+        return 0;
+    }
     const Brick br = make_brick(g);
     hipLaunchKernelGGL((k_gather_lds<Epi>), dim3(br.nbricks), dim3(kThreads), 0, s, src, disp,
                        table, epi, make_g3(g), br, g.n);
@@ -802,6 +911,12 @@ int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus, 
     const float c1 = (float)(ht * g.n1 / (2.0 * M_PI));
     const float c2 = (float)(ht * g.n2 / (2.0 * M_PI));
     const float c3 = (float)(ht * g.n3 / (2.0 * M_PI));
+    if (!g.pow2) {
+        hipLaunchKernelGGL(k_backtrace_gen, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, v, dplus,
+                           dminus, make_gg(g), g.n, c1, c2, c3);
+        CL_LAUNCH_CHECK();
+        return 0;
+    }
     const Brick br = make_brick(g);
     hipLaunchKernelGGL(k_backtrace_lds, dim3(br.nbricks), dim3(kThreads), 0, s, v, dplus, dminus,
                        make_g3(g), br, g.n, c1, c2, c3);
@@ -813,12 +928,20 @@ int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, f
                   hipStream_t s, const int* boxes) {
     if (nfield == 1) return launch_gather_lds(g, f, disp, boxes, EpiStore{out}, s);
     const G3 g3 = make_g3(g);
+    const GG gg = make_gg(g);
     int k = 0;
     while (k < nfield) {
         const int chunk = (nfield - k >= 3) ? 3 : (nfield - k);
         const float* fk = f + (long long)k * g.n;
         float* ok = out + (long long)k * g.n;
-        if (chunk == 3)
+        if (!g.pow2) {
+            if (chunk == 3)
+                hipLaunchKernelGGL(k_interp_gen<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+            else if (chunk == 2)
+                hipLaunchKernelGGL(k_interp_gen<2>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+            else
+                hipLaunchKernelGGL(k_interp_gen<1>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+        } else if (chunk == 3)
             hipLaunchKernelGGL(k_interp<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
         else if (chunk == 2)
             hipLaunchKernelGGL(k_interp<2>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
@@ -878,7 +1001,7 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
     return 0;
 }
 
-int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
+int brick_table_ints(const Geo& g) { return g.pow2 ? 6 * make_brick(g).nbricks : 6; }
 
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
@@ -918,6 +1041,7 @@ int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int n
 }
 
 int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s) {
+    if (!g.pow2) return 0;   // the direct gathers of general grids use no box table
     const Brick br = make_brick(g);
     hipLaunchKernelGGL(k_brick_boxes, dim3(br.nbricks), dim3(kThreads), 0, s, disp, table,
                        make_g3(g), br, g.n);

@@ -43,6 +43,11 @@ WORKLOADS = {
         n=(512, 512, 512), nt=8, reg_order=1, alphas=(1e-3,), phantom="ellipsoids",
         kmax=16, vmax=1.0, noise=0.01, seed=1005, gtol=5e-2,
     ),
+    # the grid of the paper's NIREP brain images (256 x 300 x 256), same phantom recipe
+    "ellipsoids_nirep": dict(
+        n=(256, 300, 256), nt=4, reg_order=1, alphas=(1e-3,), phantom="ellipsoids",
+        kmax=8, vmax=1.0, noise=0.01, seed=1006, gtol=5e-2,
+    ),
 }
 
 

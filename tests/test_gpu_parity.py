@@ -224,7 +224,7 @@ def test_detdefgrad(C):
 
 def test_errors_are_reported(C):
     with pytest.raises(C.ClaireError) as e:
-        C.Context((12, 16, 16), 4, 1.0, 1)
+        C.Context((14, 16, 16), 4, 1.0, 1)   # 14 = 2 * 7
     assert e.value.code == -1
     with pytest.raises(C.ClaireError):
         C.Context((16, 16, 16), 0, 1.0, 1)
