@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["mixed", "fp32", "both"])
     ap.add_argument("--precond", default="reg", choices=["reg", "twolevel"],
                     help="PCG preconditioner: (alpha L)^-1 or the two-level zero-velocity scheme")
+    ap.add_argument("--beta", type=float, default=0.0,
+                    help="> 0: near-incompressible model with this divergence-penalty weight")
     ap.add_argument("--warmstart", default=WEIGHTS,
                     help="trained warm-start weights (.npz) or 'none'")
     ap.add_argument("--kernels-only", action="store_true",
@@ -157,12 +159,15 @@ def main():
     alpha = w["alphas"][-1]
     levels = list(w["alphas"]) if len(w["alphas"]) > 1 else None
     opts = dict(gtol=w.get("gtol", 5e-2), compute_det=1,
-                precond={"reg": C.PRECOND_REG, "twolevel": C.PRECOND_TWOLEVEL}[args.precond])
+                precond={"reg": C.PRECOND_REG, "twolevel": C.PRECOND_TWOLEVEL}[args.precond],
+                beta=args.beta)
     if levels:
         opts["alpha_levels"] = levels
 
     ctx = C.Context(n, nt, alpha, w["reg_order"])
     ctx.set_images(m0, m1)
+    if args.beta > 0:
+        ctx.set_beta(args.beta)   # the matvec timing uses the same model as the solve
     kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
            "assemble": C.KERNEL_ASSEMBLE, "copy": C.KERNEL_COPY}[args.roofline_kernel]
     if args.kernels_only:
@@ -175,7 +180,9 @@ def main():
         return
     precisions = {"mixed": [1], "fp32": [0], "both": [1, 0]}[args.precision]
     net = None
-    if args.warmstart != "none" and os.path.exists(args.warmstart) and 1 in precisions:
+    # the warm-start network takes power-of-two grids only
+    pow2 = all(k & (k - 1) == 0 for k in n)
+    if args.warmstart != "none" and os.path.exists(args.warmstart) and 1 in precisions and pow2:
         from paper_2401_17493_amd.warmstart import Net
         net = Net.load(args.warmstart)
     # (label, precision, warm start)
@@ -266,7 +273,9 @@ def main():
         "data": "synthetic (seeded nested-ellipsoid phantom, band-limited v*)",
         "config": {"workload": args.workload, "grid": list(n), "nt": nt,
                    "alpha": alpha if not levels else levels,
-                   "regularization": "H%d seminorm" % w["reg_order"],
+                   "regularization": "H%d seminorm" % w["reg_order"] + (
+                       "" if args.beta <= 0 else
+                       ", near-incompressible (divergence penalty beta = %g)" % args.beta),
                    "gtol": opts["gtol"],
                    "preconditioner": "(alpha L)^-1" if args.precond == "reg" else
                    "two-level zero-velocity H0 (coarse grid n/2, inner CG to 0.1 eta)",
