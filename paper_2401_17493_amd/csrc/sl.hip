@@ -19,9 +19,10 @@ namespace {
 constexpr int kThreads = 256;
 
 struct G3 {
-    int m1, m2, m3;     // extent - 1 (masks)
+    int m1, m2, m3;     // extent - 1 (masks; m3 only on general grids)
     int l2, l3;         // shifts
     int s1;             // l2 + l3
+    int n1, n2;         // extents (general grids: modulo wrap along x1, x2)
 };
 
 G3 make_g3(const Geo& g) {
@@ -32,7 +33,14 @@ G3 make_g3(const Geo& g) {
     r.l2 = g.l2;
     r.l3 = g.l3;
     r.s1 = g.l2 + g.l3;
+    r.n1 = g.n1;
+    r.n2 = g.n2;
     return r;
+}
+
+__device__ __forceinline__ int wrapn(int x, int n) {
+    const int r = x % n;
+    return r < 0 ? r + n : r;
 }
 
 // Cubic Lagrange basis through nodes -1, 0, 1, 2 at fractional offset t.
@@ -52,6 +60,7 @@ struct Stencil {
     float w1[4], w2[4], w3[4];
 };
 
+template <bool GEN = false>
 __device__ __forceinline__ void make_stencil(const G3& g, int i1, int i2, int i3, float d1,
                                              float d2, float d3, Stencil& st) {
     const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
@@ -61,8 +70,13 @@ __device__ __forceinline__ void make_stencil(const G3& g, int i1, int i2, int i3
     cubic_basis(d3 - f3, st.w3);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        st.o1[q] = ((b1 + q) & g.m1) << g.s1;
-        st.o2[q] = ((b2 + q) & g.m2) << g.l3;
+        if constexpr (GEN) {
+            st.o1[q] = (wrapn(b1 + q, g.n1) * g.n2) << g.l3;
+            st.o2[q] = wrapn(b2 + q, g.n2) << g.l3;
+        } else {
+            st.o1[q] = ((b1 + q) & g.m1) << g.s1;
+            st.o2[q] = ((b2 + q) & g.m2) << g.l3;
+        }
         st.o3[q] = (b3 + q) & g.m3;
     }
 }
@@ -157,17 +171,32 @@ struct Brick {
     int lb1, lb2, lb3;     // log2 of the brick extents
     int lnb2, lnb3;        // log2 of the bricks per axis along x2, x3
     int nbricks;
+    int nb2, nb3;          // bricks along x2, x3 (general grids: the last ones ragged)
 };
 
 // brick 2^(1 + log2 kVox) x 8 x 16 (4 x 8 x 16 for kVox = 2), clipped to the grid
 Brick make_brick(const Geo& g) {
     Brick b;
+    if (!g.pow2) {
+        // general grids (n1, n2 >= 8): full 2^(1+log2 kVox) x 8 x 16 bricks,
+        // ragged along x1 and x2 at the high end
+        b.lb1 = 1 + kLogVox;
+        b.lb2 = 3;
+        b.lb3 = g.l3 < 4 ? g.l3 : 4;
+        b.nb2 = (g.n2 + 7) >> 3;
+        b.nb3 = g.n3 >> b.lb3;
+        b.lnb2 = b.lnb3 = 0;
+        b.nbricks = ((g.n1 + (1 << b.lb1) - 1) >> b.lb1) * b.nb2 * b.nb3;
+        return b;
+    }
     b.lb1 = g.l1 < 1 + kLogVox ? g.l1 : 1 + kLogVox;
     b.lb2 = g.l2 < 3 ? g.l2 : 3;
     b.lb3 = g.l3 < 4 ? g.l3 : 4;
     b.lnb2 = g.l2 - b.lb2;
     b.lnb3 = g.l3 - b.lb3;
     b.nbricks = 1 << (g.l1 - b.lb1 + b.lnb2 + b.lnb3);
+    b.nb2 = 1 << b.lnb2;
+    b.nb3 = 1 << b.lnb3;
     return b;
 }
 
@@ -244,13 +273,22 @@ struct BrickPos {
     int id;            // brick index (x3 fastest), independent of the launch order
 };
 
+template <bool GEN>
 __device__ __forceinline__ BrickPos brick_pos(const Brick& br) {
     int bid = blockIdx.x;
     if ((br.nbricks & 7) == 0) bid = (bid & 7) * (br.nbricks >> 3) + (bid >> 3);
     BrickPos p;
-    p.o3 = (bid & ((1 << br.lnb3) - 1)) << br.lb3;
-    p.o2 = ((bid >> br.lnb3) & ((1 << br.lnb2) - 1)) << br.lb2;
-    p.o1 = (bid >> (br.lnb3 + br.lnb2)) << br.lb1;
+    if constexpr (GEN) {
+        const int r = bid / br.nb3;
+        p.o3 = (bid - r * br.nb3) << br.lb3;
+        const int r2 = r / br.nb2;
+        p.o2 = (r - r2 * br.nb2) << br.lb2;
+        p.o1 = r2 << br.lb1;
+    } else {
+        p.o3 = (bid & ((1 << br.lnb3) - 1)) << br.lb3;
+        p.o2 = ((bid >> br.lnb3) & ((1 << br.lnb2) - 1)) << br.lb2;
+        p.o1 = (bid >> (br.lnb3 + br.lnb2)) << br.lb1;
+    }
     p.bvol = 1 << (br.lb1 + br.lb2 + br.lb3);
     p.id = bid;
     return p;
@@ -259,6 +297,7 @@ __device__ __forceinline__ BrickPos brick_pos(const Brick& br) {
 // k-th voxel of this thread: grid coordinates and linear index (false if
 // none). Order within the brick: x3 fastest, then x1, then x2, so the 64 lanes
 // of a wave cover 16 x3 voxels in each of 4 x1 planes of one x2 row.
+template <bool GEN>
 __device__ __forceinline__ bool brick_voxel(const G3& g, const Brick& br, const BrickPos& p,
                                             int k, int& i1, int& i2, int& i3, unsigned& idx) {
     const int v = threadIdx.x + k * kThreads;
@@ -266,7 +305,12 @@ __device__ __forceinline__ bool brick_voxel(const G3& g, const Brick& br, const 
     i3 = p.o3 + (v & ((1 << br.lb3) - 1));
     i1 = p.o1 + ((v >> br.lb3) & ((1 << br.lb1) - 1));
     i2 = p.o2 + (v >> (br.lb3 + br.lb1));
-    idx = ((unsigned)i1 << g.s1) | ((unsigned)i2 << g.l3) | (unsigned)i3;
+    if constexpr (GEN) {
+        if (i1 >= g.n1 || i2 >= g.n2) return false;   // ragged brick
+        idx = ((unsigned)(i1 * g.n2 + i2) << g.l3) | (unsigned)i3;
+    } else {
+        idx = ((unsigned)i1 << g.s1) | ((unsigned)i2 << g.l3) | (unsigned)i3;
+    }
     return true;
 }
 
@@ -339,6 +383,7 @@ __device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
 // ng): one division per segment. Batches of independent 16-byte loads, then
 // the 16-byte LDS stores.
 constexpr int kSegBatch = 4;
+template <bool GEN>
 __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ src, const G3& g,
                                           const Box& b) {
     const int nrows = b.e1 * b.e2;
@@ -357,8 +402,13 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
             if (row < nrows) {
                 int a2;
                 const int a1 = quot(row, b.e2, inv_e2, a2);
-                const unsigned off = ((unsigned)((b.lo1 + a1) & g.m1) << g.s1) |
-                                     ((unsigned)((b.lo2 + a2) & g.m2) << g.l3) | col;
+                unsigned off;
+                if constexpr (GEN)
+                    off = ((unsigned)(wrapn(b.lo1 + a1, g.n1) * g.n2 + wrapn(b.lo2 + a2, g.n2))
+                           << g.l3) | col;
+                else
+                    off = ((unsigned)((b.lo1 + a1) & g.m1) << g.s1) |
+                          ((unsigned)((b.lo2 + a2) & g.m2) << g.l3) | col;
                 tmp[u] = ldi4(src, off);
             }
         }
@@ -405,12 +455,12 @@ __device__ __forceinline__ float interp_box(const float* box, const Box& b, cons
 }
 
 // Tricubic value by direct global gathers (bricks whose box does not fit).
-template <typename T>
+template <bool GEN, typename T>
 __device__ __forceinline__ float interp_global(const T* __restrict__ src, const G3& g,
                                                long long n, int i1, int i2, int i3,
                                                const float d[3]) {
     Stencil st;
-    make_stencil(g, i1, i2, i3, d[0], d[1], d[2], st);
+    make_stencil<GEN>(g, i1, i2, i3, d[0], d[1], d[2], st);
     float u;
     gather<1, T>(src, n, st, &u);
     return u;
@@ -418,18 +468,19 @@ __device__ __forceinline__ float interp_global(const T* __restrict__ src, const 
 
 // Per-brick stencil bounding boxes of a departure field: 6 ints per brick
 // (lo1, lo2, lo3, e1, e2, e3), indexed by BrickPos::id.
+template <bool GEN>
 __global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restrict__ d,
                                                           int* __restrict__ table, G3 g,
                                                           Brick br, long long n) {
     __shared__ int red[kThreads / 64][6];
-    const BrickPos bp = brick_pos(br);
+    const BrickPos bp = brick_pos<GEN>(br);
     int mn1 = 1 << 30, mn2 = 1 << 30, mn3 = 1 << 30;
     int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
         int i1, i2, i3;
         unsigned idx;
-        if (brick_voxel(g, br, bp, k, i1, i2, i3, idx)) {
+        if (brick_voxel<GEN>(g, br, bp, k, i1, i2, i3, idx)) {
             const int q1 = i1 + (int)floorf(ldi(d, idx)) - 1;
             const int q2 = i2 + (int)floorf(ldi(d + n, idx)) - 1;
             const int q3 = i3 + (int)floorf(ldi(d + 2 * n, idx)) - 1;
@@ -448,13 +499,13 @@ __global__ __launch_bounds__(kThreads) void k_brick_boxes(const float* __restric
 
 // Single-field gather u = src(x + d(x)) with epilogue; `table` holds the
 // per-brick boxes of d (NULL: reduce them here).
-template <class Epi>
+template <class Epi, bool GEN>
 __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
     const float* __restrict__ src, const float* __restrict__ d, const int* __restrict__ table,
     Epi epi, G3 g, Brick br, long long n) {
     __shared__ __align__(16) float box[kBoxCap];
     __shared__ int red[kThreads / 64][6];
-    const BrickPos bp = brick_pos(br);
+    const BrickPos bp = brick_pos<GEN>(br);
     float dd[kVox][3];
     int q[kVox][3];
     int ii[kVox][3];
@@ -465,7 +516,7 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
     int mx1 = -(1 << 30), mx2 = -(1 << 30), mx3 = -(1 << 30);
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
-        on[k] = brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
+        on[k] = brick_voxel<GEN>(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
         if (on[k]) {
             dd[k][0] = ldi(d, gi[k]);
             dd[k][1] = ldi(d + n, gi[k]);
@@ -479,7 +530,7 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
         b.lo1 = t[0]; b.lo2 = t[1]; b.lo3 = t[2];
         b.e1 = t[3]; b.e2 = t[4]; b.e3 = t[5];
         box_layout(b);
-        if (b.vol <= kBoxCap) stage_box(box, src, g, b);
+        if (b.vol <= kBoxCap) stage_box<GEN>(box, src, g, b);
     }
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
@@ -492,7 +543,7 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
     }
     if (!table) {
         b = reduce_box(mn1, mn2, mn3, mx1, mx2, mx3, red);
-        if (b.vol <= kBoxCap) stage_box(box, src, g, b);
+        if (b.vol <= kBoxCap) stage_box<GEN>(box, src, g, b);
     }
     if (b.vol <= kBoxCap) {
         __syncthreads();
@@ -503,7 +554,8 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
 #pragma unroll
         for (int k = 0; k < kVox; ++k)
             if (on[k])
-                epi.store(gi[k], interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]),
+                epi.store(gi[k],
+                          interp_global<GEN>(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]),
                           pre[k]);
     }
 }
@@ -512,12 +564,13 @@ __global__ __launch_bounds__(kThreads, kGatherWaves) void k_gather_lds(
 //   y~ = x - s h_t v(x),  y = x - s (h_t/2) (v(x) + v(y~)),  s = +1, -1.
 // c_a = h_t / h_a converts velocity to voxels per step. For each direction
 // the three components of v are staged through the brick's box in turn.
+template <bool GEN>
 __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
     const float* __restrict__ v, float* __restrict__ dp, float* __restrict__ dm, G3 g, Brick br,
     long long n, float c1, float c2, float c3) {
     __shared__ __align__(16) float box[kBoxCapBT];
     __shared__ int red[kThreads / 64][6];
-    const BrickPos bp = brick_pos(br);
+    const BrickPos bp = brick_pos<GEN>(br);
     const float c[3] = {c1, c2, c3};
     float vx[kVox][3];
     int ii[kVox][3];
@@ -525,7 +578,7 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
     bool on[kVox];
 #pragma unroll
     for (int k = 0; k < kVox; ++k) {
-        on[k] = brick_voxel(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
+        on[k] = brick_voxel<GEN>(g, br, bp, k, ii[k][0], ii[k][1], ii[k][2], gi[k]);
         if (on[k]) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) vx[k][a] = ldi(v + a * n, gi[k]);
@@ -559,7 +612,7 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
             const float* src = v + f * n;
             if (fits) {
                 if (f > 0) __syncthreads();   // previous component's reads are done
-                stage_box(box, src, g, b);
+                stage_box<GEN>(box, src, g, b);
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < kVox; ++k)
@@ -568,7 +621,8 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
 #pragma unroll
                 for (int k = 0; k < kVox; ++k)
                     if (on[k])
-                        u[k][f] = interp_global(src, g, n, ii[k][0], ii[k][1], ii[k][2], dd[k]);
+                        u[k][f] = interp_global<GEN>(src, g, n, ii[k][0], ii[k][1], ii[k][2],
+                                                     dd[k]);
             }
         }
         float* out = dir == 0 ? dp : dm;
@@ -584,20 +638,10 @@ __global__ __launch_bounds__(kThreads, kBacktraceWaves) void k_backtrace_lds(
 
 // ------------------------------------------------------------------------
 // General extents: n1, n2 any even products of 2, 3, 5 (n3 a power of two).
-// Every gather reads its 4x4x4 stencil directly from global memory with a
-// modulo wrap along x1 and x2; the epilogues are those of the LDS kernels.
-struct GG {
-    int n1, n2, m3, l3;
-};
-
-GG make_gg(const Geo& g) { return GG{g.n1, g.n2, g.n3 - 1, g.l3}; }
-
-__device__ __forceinline__ int wrapn(int x, int n) {
-    const int r = x % n;
-    return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ void coords_gen(const GG& g, unsigned idx, int& i1, int& i2,
+// The single-field gathers and the backtrace are the LDS-staged kernels
+// instantiated for ragged bricks and a modulo wrap (GEN); multi-field
+// interpolation reads its stencil directly from global memory.
+__device__ __forceinline__ void coords_gen(const G3& g, unsigned idx, int& i1, int& i2,
                                            int& i3) {
     i3 = (int)(idx & (unsigned)g.m3);
     const unsigned r = idx >> g.l3;
@@ -605,81 +649,21 @@ __device__ __forceinline__ void coords_gen(const GG& g, unsigned idx, int& i1, i
     i1 = (int)(r / (unsigned)g.n2);
 }
 
-__device__ __forceinline__ void make_stencil_gen(const GG& g, int i1, int i2, int i3, float d1,
-                                                 float d2, float d3, Stencil& st) {
-    const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
-    const int b1 = i1 + (int)f1 - 1, b2 = i2 + (int)f2 - 1, b3 = i3 + (int)f3 - 1;
-    cubic_basis(d1 - f1, st.w1);
-    cubic_basis(d2 - f2, st.w2);
-    cubic_basis(d3 - f3, st.w3);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        st.o1[q] = (wrapn(b1 + q, g.n1) * g.n2) << g.l3;
-        st.o2[q] = wrapn(b2 + q, g.n2) << g.l3;
-        st.o3[q] = (b3 + q) & g.m3;
-    }
-}
-
-template <class Epi>
-__global__ __launch_bounds__(kThreads) void k_gather_gen(const float* __restrict__ src,
-                                                         const float* __restrict__ d, Epi epi,
-                                                         GG g, long long n) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    const unsigned i = (unsigned)idx;
-    const auto pre = epi.load(i);
-    int i1, i2, i3;
-    coords_gen(g, i, i1, i2, i3);
-    Stencil st;
-    make_stencil_gen(g, i1, i2, i3, ldi(d, i), ldi(d + n, i), ldi(d + 2 * n, i), st);
-    float u;
-    gather<1>(src, n, st, &u);
-    epi.store(i, u, pre);
-}
-
 template <int NF>
 __global__ __launch_bounds__(kThreads) void k_interp_gen(const float* __restrict__ f,
                                                          const float* __restrict__ d,
-                                                         float* __restrict__ out, GG g,
+                                                         float* __restrict__ out, G3 g,
                                                          long long n) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= n) return;
     int i1, i2, i3;
     coords_gen(g, (unsigned)idx, i1, i2, i3);
     Stencil st;
-    make_stencil_gen(g, i1, i2, i3, d[idx], d[n + idx], d[2 * n + idx], st);
+    make_stencil<true>(g, i1, i2, i3, d[idx], d[n + idx], d[2 * n + idx], st);
     float r[NF];
     gather<NF>(f, n, st, r);
 #pragma unroll
     for (int k = 0; k < NF; ++k) out[k * n + idx] = r[k];
-}
-
-// RK2 backtrace for +v and -v with direct gathers (same steps as
-// k_backtrace_lds): y~ = x + s c v(x), y = x + s (c/2)(v(x) + v(y~)), s = -1
-// for y+ and +1 for y-.
-__global__ __launch_bounds__(kThreads) void k_backtrace_gen(const float* __restrict__ v,
-                                                            float* __restrict__ dp,
-                                                            float* __restrict__ dm, GG g,
-                                                            long long n, float c1, float c2,
-                                                            float c3) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    const float c[3] = {c1, c2, c3};
-    int i1, i2, i3;
-    coords_gen(g, (unsigned)idx, i1, i2, i3);
-    const float vx[3] = {v[idx], v[n + idx], v[2 * n + idx]};
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-        const float sg = dir == 0 ? -1.f : 1.f;
-        Stencil st;
-        make_stencil_gen(g, i1, i2, i3, sg * c[0] * vx[0], sg * c[1] * vx[1], sg * c[2] * vx[2],
-                         st);
-        float u[3];
-        gather<3>(v, n, st, u);
-        float* out = dir == 0 ? dp : dm;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) out[a * n + idx] = sg * 0.5f * c[a] * (vx[a] + u[a]);
-    }
 }
 
 unsigned blocks_for(long long n);
@@ -687,15 +671,13 @@ unsigned blocks_for(long long n);
 template <class Epi>
 int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
                       const Epi& epi, hipStream_t s) {
-    if (!g.pow2) {
-        hipLaunchKernelGGL((k_gather_gen<Epi>), dim3(blocks_for(g.n)), dim3(kThreads), 0, s, src,
-                           disp, epi, make_gg(g), g.n);
-        CL_LAUNCH_CHECK();
-        return 0;
-    }
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL((k_gather_lds<Epi>), dim3(br.nbricks), dim3(kThreads), 0, s, src, disp,
-                       table, epi, make_g3(g), br, g.n);
+    if (!g.pow2)
+        hipLaunchKernelGGL((k_gather_lds<Epi, true>), dim3(br.nbricks), dim3(kThreads), 0, s, src,
+                           disp, table, epi, make_g3(g), br, g.n);
+    else
+        hipLaunchKernelGGL((k_gather_lds<Epi, false>), dim3(br.nbricks), dim3(kThreads), 0, s,
+                           src, disp, table, epi, make_g3(g), br, g.n);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -911,15 +893,13 @@ int launch_backtrace(const Geo& g, const float* v, float* dplus, float* dminus, 
     const float c1 = (float)(ht * g.n1 / (2.0 * M_PI));
     const float c2 = (float)(ht * g.n2 / (2.0 * M_PI));
     const float c3 = (float)(ht * g.n3 / (2.0 * M_PI));
-    if (!g.pow2) {
-        hipLaunchKernelGGL(k_backtrace_gen, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, v, dplus,
-                           dminus, make_gg(g), g.n, c1, c2, c3);
-        CL_LAUNCH_CHECK();
-        return 0;
-    }
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL(k_backtrace_lds, dim3(br.nbricks), dim3(kThreads), 0, s, v, dplus, dminus,
-                       make_g3(g), br, g.n, c1, c2, c3);
+    if (!g.pow2)
+        hipLaunchKernelGGL(k_backtrace_lds<true>, dim3(br.nbricks), dim3(kThreads), 0, s, v,
+                           dplus, dminus, make_g3(g), br, g.n, c1, c2, c3);
+    else
+        hipLaunchKernelGGL(k_backtrace_lds<false>, dim3(br.nbricks), dim3(kThreads), 0, s, v,
+                           dplus, dminus, make_g3(g), br, g.n, c1, c2, c3);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -928,7 +908,6 @@ int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, f
                   hipStream_t s, const int* boxes) {
     if (nfield == 1) return launch_gather_lds(g, f, disp, boxes, EpiStore{out}, s);
     const G3 g3 = make_g3(g);
-    const GG gg = make_gg(g);
     int k = 0;
     while (k < nfield) {
         const int chunk = (nfield - k >= 3) ? 3 : (nfield - k);
@@ -936,11 +915,11 @@ int launch_interp(const Geo& g, const float* f, int nfield, const float* disp, f
         float* ok = out + (long long)k * g.n;
         if (!g.pow2) {
             if (chunk == 3)
-                hipLaunchKernelGGL(k_interp_gen<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+                hipLaunchKernelGGL(k_interp_gen<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
             else if (chunk == 2)
-                hipLaunchKernelGGL(k_interp_gen<2>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+                hipLaunchKernelGGL(k_interp_gen<2>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
             else
-                hipLaunchKernelGGL(k_interp_gen<1>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, gg, g.n);
+                hipLaunchKernelGGL(k_interp_gen<1>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
         } else if (chunk == 3)
             hipLaunchKernelGGL(k_interp<3>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, fk, disp, ok, g3, g.n);
         else if (chunk == 2)
@@ -1001,7 +980,7 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
     return 0;
 }
 
-int brick_table_ints(const Geo& g) { return g.pow2 ? 6 * make_brick(g).nbricks : 6; }
+int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
 
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
@@ -1041,10 +1020,13 @@ int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int n
 }
 
 int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s) {
-    if (!g.pow2) return 0;   // the direct gathers of general grids use no box table
     const Brick br = make_brick(g);
-    hipLaunchKernelGGL(k_brick_boxes, dim3(br.nbricks), dim3(kThreads), 0, s, disp, table,
-                       make_g3(g), br, g.n);
+    if (!g.pow2)
+        hipLaunchKernelGGL(k_brick_boxes<true>, dim3(br.nbricks), dim3(kThreads), 0, s, disp,
+                           table, make_g3(g), br, g.n);
+    else
+        hipLaunchKernelGGL(k_brick_boxes<false>, dim3(br.nbricks), dim3(kThreads), 0, s, disp,
+                           table, make_g3(g), br, g.n);
     CL_LAUNCH_CHECK();
     return 0;
 }
