@@ -130,3 +130,24 @@ def test_full_solve_ni(C, alpha, beta):
     assert st["gn_iters"] == s_ref.gn_iters and st["matvecs"] == s_ref.matvecs
     assert rel_err(vh, v_ref) < 1e-4
     assert abs(st["J"] - s_ref.J) <= 1e-4 * s_ref.J
+
+
+def test_setup_and_matvec_ni_fd8(C):
+    """FD8 first derivatives for the transport and adjoint equations with the
+    near-incompressible model (whose own operators stay spectral)."""
+    nt, alpha, beta = 4, 1e-2, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    v = f32(0.5 * vstar)
+    vt = f32(bandlimited_velocity(grid.n, 78, 4, 0.5))
+    st = O.setup_velocity(grid, m0, m1, v, alpha, nt, 1, deriv="fd8", beta=beta)
+    ref = O.hessian_matvec(st, vt)
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_beta(beta)
+        ctx.set_derivative(C.DERIV_FD8)
+        ctx.set_velocity(dev(v))
+        g, J = ctx.gradient()
+        errs = dict(g=rel_err(host(g), st.g), J=abs(J - st.J) / st.J,
+                    Hv=rel_err(host(ctx.hessian_matvec(dev(vt))), ref))
+    print("NI + FD8 setup:", {k: "%.2e" % e for k, e in errs.items()})
+    assert max(errs.values()) <= TOL
