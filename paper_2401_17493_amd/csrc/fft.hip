@@ -630,15 +630,43 @@ __device__ __forceinline__ void stage_gen(const C* src, C* dst, int N, int CW, i
     }
 }
 
+// Multiplier applied inside an x1 column pass (general grids): 0 none,
+// 1 (alpha |k|^{2p})^{-1}, 2 (alpha |k|^{2p})^{-1/2}, both 1 at k = 0, times norm.
+struct ColMult {
+    int n2;            // x2 extent (blockIdx.y is the x2 index)
+    double alpha, norm;
+    int p;
+};
+
+template <int DIR, typename C, int MULT>
+__device__ __forceinline__ void stages_gen(C*& src, C*& dst, int N, int CW, const C* tw_s,
+                                           const RadixPlan& plan, int tid) {
+    int Ns = 1;
+    for (int st = 0; st < plan.ns; ++st) {
+        const int R = plan.R[st];
+        if (R == 4) stage_gen<4, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else if (R == 2) stage_gen<2, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else if (R == 3) stage_gen<3, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        else stage_gen<5, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+        __syncthreads();
+        C* t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+}
+
 // Column transforms of length N = plan.N along an axis with element stride
 // `stride`; tiles of CW consecutive half-complex x3 bins, one tile row per
-// blockIdx.y (ystride apart), component blockIdx.z.
-template <int DIR, typename C>
+// blockIdx.y (ystride apart), component blockIdx.z. With MULT (x1 axis,
+// float only) the tile is transformed forward, multiplied and transformed
+// back in LDS.
+template <int DIR, typename C, int MULT>
 __global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int CW,
                                                        long long stride, long long ystride,
                                                        int nh, long long nspec,
                                                        const C* __restrict__ tw,
-                                                       RadixPlan plan) {
+                                                       RadixPlan plan, ColMult cm) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int N = plan.N;
     C* tw_s = reinterpret_cast<C*>(smem_raw);
@@ -656,18 +684,21 @@ __global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int
     __syncthreads();
     C* src = A;
     C* dst = B;
-    int Ns = 1;
-    for (int st = 0; st < plan.ns; ++st) {
-        const int R = plan.R[st];
-        if (R == 4) stage_gen<4, DIR>(src, dst, N, CW, Ns, tw_s, tid);
-        else if (R == 2) stage_gen<2, DIR>(src, dst, N, CW, Ns, tw_s, tid);
-        else if (R == 3) stage_gen<3, DIR>(src, dst, N, CW, Ns, tw_s, tid);
-        else stage_gen<5, DIR>(src, dst, N, CW, Ns, tw_s, tid);
+    if constexpr (MULT == 0) {
+        stages_gen<DIR, C, 0>(src, dst, N, CW, tw_s, plan, tid);
+    } else {
+        stages_gen<-1, C, 0>(src, dst, N, CW, tw_s, plan, tid);
+        const int k2 = signed_k(blockIdx.y, cm.n2);
+        for (int e = tid; e < N * CW; e += kThreads) {
+            const int r = e / CW, c = e - r * CW;
+            const double sym = cm.alpha * reg_symbol(cm.p, signed_k(r, N), k2, c0 + c);
+            const float f = (float)(sym == 0.0 ? cm.norm
+                                               : (MULT == 1 ? cm.norm / sym
+                                                            : cm.norm / sqrt(sym)));
+            src[e] = cscale(src[e], f);
+        }
         __syncthreads();
-        C* t = src;
-        src = dst;
-        dst = t;
-        Ns *= R;
+        stages_gen<+1, C, 0>(src, dst, N, CW, tw_s, plan, tid);
     }
     for (int e = tid; e < N * CW; e += kThreads) {
         const int r = e / CW, c = e - r * CW;
@@ -675,9 +706,10 @@ __global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int
     }
 }
 
-// Pointwise multiplier of every spectral operator on a full spectrum (general
-// grids): GRAD 1 -> 3, DIV 3 -> 1, REG (from the double spectrum), REG_INV,
-// REG_ISQRT, and the coupled near-incompressible modes; in place on S.
+// Pointwise multiplier on a full spectrum (general grids): GRAD 1 -> 3,
+// DIV 3 -> 1, REG (from the double spectrum) and the coupled
+// near-incompressible modes; in place on S. (alpha L)^{-1} and its square
+// root are fused into the x1 column pass instead.
 enum GenMult { GM_GRAD, GM_DIV, GM_REG, GM_REG_INV, GM_REG_ISQRT, GM_NI_PROJECT, GM_NI_PENALTY };
 
 template <int MODE>
@@ -711,12 +743,6 @@ __global__ __launch_bounds__(kThreads) void k_mult_gen(float2* __restrict__ S,
             const double2 a = S64[c * nspec + idx];
             S[c * nspec + idx] = make_float2((float)(a.x * f), (float)(a.y * f));
         }
-    } else if (MODE == GM_REG_INV || MODE == GM_REG_ISQRT) {
-        const double sym = alpha * reg_symbol(p, k1, k2, k3);
-        const float f = (float)(sym == 0.0 ? norm
-                                           : (MODE == GM_REG_INV ? norm / sym : norm / sqrt(sym)));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) S[c * nspec + idx] = cscale(S[c * nspec + idx], f);
     } else {
         const double kk = (double)k1 * k1 + (double)k2 * k2 + (double)k3 * k3;
         float2 t[3];
@@ -902,9 +928,11 @@ RadixPlan make_plan(int N) {
     return p;   // m == 1 for extents accepted by make_geo's caller
 }
 
-// General-grid column transform along x2 (axis 2) or x1 (axis 1)
-template <int DIR, typename C>
-int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_t s) {
+// General-grid column transform along x2 (axis 2) or x1 (axis 1); MULT > 0
+// (x1 only): forward, multiplier, inverse in one pass
+template <int DIR, typename C, int MULT = 0>
+int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_t s,
+             double alpha = 0.0, int p = 1) {
     const int N = axis == 1 ? g.n1 : g.n2;
     // two tiles and the twiddle table within 64 KiB of LDS
     int CW = (int)((65536 / sizeof(C) - N) / (2 * N));
@@ -918,8 +946,13 @@ int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_
     const long long stride = axis == 1 ? (long long)g.n2 * g.nh : g.nh;
     const long long ystride = axis == 1 ? g.nh : (long long)g.n2 * g.nh;
     dim3 grid((g.nh + CW - 1) / CW, axis == 1 ? g.n2 : g.n1, ncomp);
-    hipLaunchKernelGGL((k_cols_gen<DIR, C>), grid, dim3(kThreads), sh, s, spec, CW, stride,
-                       ystride, g.nh, g.nspec, tw, make_plan(N));
+    ColMult cm;
+    cm.n2 = g.n2;
+    cm.alpha = alpha;
+    cm.norm = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+    cm.p = p;
+    hipLaunchKernelGGL((k_cols_gen<DIR, C, MULT>), grid, dim3(kThreads), sh, s, spec, CW, stride,
+                       ystride, g.nh, g.nspec, tw, make_plan(N), cm);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -935,13 +968,23 @@ int mult_gen(const Geo& g, SpectralWork& w, double alpha, int p, double beta, hi
 
 // Spectral operator on a general grid: x3 R2C, x2 and x1 forward columns,
 // pointwise multiplier, x1 and x2 inverse columns, x3 C2R (with the addend
-// or the fused dot product).
+// or the fused dot product); for (alpha L)^{-1} and (alpha L)^{-1/2} the x1
+// forward, multiplier and x1 inverse are one pass.
 int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float* out,
                  double alpha, int p, double beta, hipStream_t s, const float* add,
                  const float* dot_with, Reducer* red, int slot) {
     const int nin = mode == GM_GRAD ? 1 : 3;
     const int nout = mode == GM_DIV ? 1 : 3;
     float2* S = w.spec;
+    if (mode == GM_REG_INV || mode == GM_REG_ISQRT) {
+        // the multiplier is fused into the x1 pass
+        CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
+        CL_TRY(cols_gen<-1>(g, 2, w.tw2, S, 3, s));
+        if (mode == GM_REG_INV) CL_TRY((cols_gen<-1, float2, 1>(g, 1, w.tw1, S, 3, s, alpha, p)));
+        else CL_TRY((cols_gen<-1, float2, 2>(g, 1, w.tw1, S, 3, s, alpha, p)));
+        CL_TRY(cols_gen<+1>(g, 2, w.tw2, S, 3, s));
+        return inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot);
+    }
     if (mode == GM_REG) {
         CL_TRY(fwd_x3(g, w.tw64, w.tw_n, in, w.spec64, 3, s));
         CL_TRY(cols_gen<-1>(g, 2, w.tw2_64, w.spec64, 3, s));
@@ -955,8 +998,6 @@ int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float
     case GM_GRAD: CL_TRY(mult_gen<GM_GRAD>(g, w, alpha, p, beta, s)); break;
     case GM_DIV: CL_TRY(mult_gen<GM_DIV>(g, w, alpha, p, beta, s)); break;
     case GM_REG: CL_TRY(mult_gen<GM_REG>(g, w, alpha, p, beta, s)); break;
-    case GM_REG_INV: CL_TRY(mult_gen<GM_REG_INV>(g, w, alpha, p, beta, s)); break;
-    case GM_REG_ISQRT: CL_TRY(mult_gen<GM_REG_ISQRT>(g, w, alpha, p, beta, s)); break;
     case GM_NI_PROJECT: CL_TRY(mult_gen<GM_NI_PROJECT>(g, w, alpha, p, beta, s)); break;
     default: CL_TRY(mult_gen<GM_NI_PENALTY>(g, w, alpha, p, beta, s)); break;
     }
