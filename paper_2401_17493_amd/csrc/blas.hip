@@ -157,6 +157,38 @@ __global__ __launch_bounds__(kThreads) void k_xpby(const float* __restrict__ x,
     if (i < n) y[i] = fmaf(b, y[i], x[i]);
 }
 
+// y = x + b y with the block's max |y| -> partial[block] (n4 float4 groups,
+// then the tail of n - 4 n4 floats)
+__global__ __launch_bounds__(kThreads) void k_xpby_absmax(const float4* __restrict__ x,
+                                                          float4* __restrict__ y, float b,
+                                                          long long n4, long long n,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[kThreads / kWave];
+    double mx = identity<OP_MAX>();
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride) {
+        const float4 a = x[i];
+        float4 v = y[i];
+        v.x = fmaf(b, v.x, a.x);
+        v.y = fmaf(b, v.y, a.y);
+        v.z = fmaf(b, v.z, a.z);
+        v.w = fmaf(b, v.w, a.w);
+        y[i] = v;
+        mx = fmax(mx, fmax(fmax(fabs((double)v.x), fabs((double)v.y)),
+                           fmax(fabs((double)v.z), fabs((double)v.w))));
+    }
+    const float* xs = reinterpret_cast<const float*>(x);
+    float* ys = reinterpret_cast<float*>(y);
+    for (long long i = 4 * n4 + (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += stride) {
+        const float v = fmaf(b, ys[i], xs[i]);
+        ys[i] = v;
+        mx = fmax(mx, fabs((double)v));
+    }
+    mx = block_reduce<OP_MAX>(mx, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = mx;
+}
+
 __global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ x,
                                                       const float* __restrict__ z,
                                                       float* __restrict__ y, float b,
@@ -301,6 +333,23 @@ int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s) {
 
 int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, b, n);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_xpby_absmax(Reducer& r, const float* x, float* y, float b, long long n, int slot,
+                       hipStream_t s) {
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) {
+        set_error("xpby_absmax needs 16-byte aligned vectors");
+        return CLAIRE_EINVAL;
+    }
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_xpby_absmax, dim3(nb), dim3(kThreads), 0, s,
+                       reinterpret_cast<const float4*>(x), reinterpret_cast<float4*>(y), b, n / 4,
+                       n, r.partial);
+    CL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 1, 0,
+                       r.result, slot);
     CL_LAUNCH_CHECK();
     return 0;
 }

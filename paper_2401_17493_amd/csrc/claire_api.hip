@@ -316,8 +316,12 @@ int run_setup(claire_ctx* c) {
 // reg_part: alpha L vt when the caller already has it (PCG), else NULL and
 // it is computed here by FFT. dot_slot >= 0: also <vt, out> into that
 // reduction slot.
+// Reducer slot of the mixed matvec's scale max|v~| (used by its kernels on
+// the device)
+constexpr int kScaleSlot = 7;
+
 int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
-                     int dot_slot);
+                     int dot_slot, bool scale_ready);
 
 // out = reg_part + K ni_tmp (near-incompressible projection of the data term
 // in ni_tmp), and <vt, out> -> dot_slot when >= 0
@@ -329,9 +333,10 @@ int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* re
     return 0;
 }
 
+// scale_ready (mixed path): max|vt| is already in the reducer's kScaleSlot
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
-               int dot_slot = -1) {
-    if (c->precision == 1) return run_matvec_mixed(c, vt, out, reg_part, dot_slot);
+               int dot_slot = -1, bool scale_ready = false) {
+    if (c->precision == 1) return run_matvec_mixed(c, vt, out, reg_part, dot_slot, scale_ready);
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -381,14 +386,13 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
 // normalised by max|v~| (a device scalar, no host round trip) so no stored
 // value can overflow, and the assembly multiplies the scale back in.
 int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
-                     int dot_slot) {
+                     int dot_slot, bool scale_ready) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
     const double ht = 1.0 / nt;
-    const int kScaleSlot = 7;
     const double* scale = c->red.result + kScaleSlot;
-    CL_TRY(red_absmax(c->red, vt, 3 * n, kScaleSlot, c->s));
+    if (!scale_ready) CL_TRY(red_absmax(c->red, vt, 3 * n, kScaleSlot, c->s));
     CL_TRY(launch_mixed_sources(g, c->gm16, vt, scale, c->f16, c->w0, nt, c->s));
     float* src = c->w0;
     float* nxt = c->w1;
@@ -504,8 +508,10 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
     }
     bool converged = false;
+    bool scale_ready = false;   // max|s| already reduced by the direction update
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
+        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0,   // <s, Hs> -> slot 0
+                          scale_ready));
         ++res.its;
         CL_TRY(red_fetch(c->red, s));
         const double shs = c->red.host[0];
@@ -533,7 +539,14 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         const double rz_new = c->red.host[2];
         const double mu = rz_new / rz;
         for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
-        CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
+        if (c->precision == 1) {
+            // the mixed matvec scales its float16 sources by max|s|: reduce
+            // it in the same pass
+            CL_TRY(launch_xpby_absmax(c->red, c->z, c->sd, (float)mu, n3, kScaleSlot, s));
+            scale_ready = true;
+        } else {
+            CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
+        }
         if (!two) CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }

@@ -245,6 +245,9 @@ int twolevel_apply(TwoLevel& T, const Geo& gf, SpectralWork& swf, const float* r
 int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s);
 // y = x + b*y
 int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s);
+// y = x + b*y and max |y| -> r.result[slot] (x, y 16-byte aligned)
+int launch_xpby_absmax(Reducer& r, const float* x, float* y, float b, long long n, int slot,
+                       hipStream_t s);
 // y = x + b*z
 int launch_lincomb(const float* x, const float* z, float* y, float b, long long n,
                    hipStream_t s);
