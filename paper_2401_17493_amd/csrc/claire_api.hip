@@ -72,8 +72,9 @@ Geo make_geo(const int nx[3]) {
     g.l2 = lg(g.n2);
     g.l3 = lg(g.n3);
     g.nh = g.n3 / 2 + 1;
+    g.hp = spec_pitch(g.nh);
     g.n = (long long)g.n1 * g.n2 * g.n3;
-    g.nspec = (long long)g.n1 * g.n2 * g.nh;
+    g.nspec = (long long)g.n1 * g.n2 * g.hp;
     g.pow2 = (1 << g.l1) == g.n1 && (1 << g.l2) == g.n2 && (1 << g.l3) == g.n3;
     return g;
 }

@@ -3,7 +3,9 @@
 // Sections 2.5.5-2.5.6: (alpha L)^{-1}).
 //
 // Layout: real fields [n1][n2][n3] (x3 contiguous); spectra are half-complex
-// [n1][n2][nh], nh = n3/2 + 1.
+// [n1][n2][hp], nh = n3/2 + 1 bins per row padded to a pitch hp of whole
+// 128-byte lines (16 complex), so that the column passes' row segments are
+// line-aligned.
 //
 // A spectral operator is five passes over HBM:
 //   1. x3 R2C: rows of n3 reals read as n3/2 complex (even + i odd), an
@@ -182,10 +184,10 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
     C* buf = tw_s + (1 << logT);
     using R = typename RealOf<C>::T;
     const int tid = threadIdx.x;
-    const int n3 = 1 << l3, M = n3 >> 1, nh = M + 1;
+    const int n3 = 1 << l3, M = n3 >> 1, nh = M + 1, hp = spec_pitch(nh);
     const long long row0 = (long long)blockIdx.x * RB;
     const float2* src = reinterpret_cast<const float2*>(in + blockIdx.y * n) + row0 * M;
-    C* dst = out + blockIdx.y * nspec + row0 * nh;
+    C* dst = out + blockIdx.y * nspec + row0 * hp;
     load_twiddles(tw_s, tw, 1 << logT, tid);
     stage<E>(buf, RB * M, tid, [&](int e) {
         const float2 x = src[e];
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
         const C ev = cscale(cadd(zk, zc), (R)0.5);
         const C od = cscale(csub(zk, zc), (R)0.5);
         const C wo = cmul(tw_s[k << tsh], od);
-        dst[e] = cx<C>(ev.x + wo.y, ev.y - wo.x);   // ev - i * wo
+        dst[r * hp + k] = cx<C>(ev.x + wo.y, ev.y - wo.x);   // ev - i * wo
     }
 }
 
@@ -223,9 +225,9 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     float2* tw_s = reinterpret_cast<float2*>(smem_raw);
     float2* buf = tw_s + (1 << logT);
     const int tid = threadIdx.x;
-    const int n3 = 1 << l3, M = n3 >> 1, nh = M + 1;
+    const int n3 = 1 << l3, M = n3 >> 1, hp = spec_pitch(M + 1);
     const long long row0 = (long long)blockIdx.x * RB;
-    const float2* src = in + blockIdx.y * nspec + row0 * nh;
+    const float2* src = in + blockIdx.y * nspec + row0 * hp;
     load_twiddles(tw_s, tw, 1 << logT, tid);
     __syncthreads();
     // Z[k] = (X[k] + conj X[M-k]) + i conj(w^k) (X[k] - conj X[M-k]); the
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     const int tsh = logT - l3;
     stage<E>(buf, RB * M, tid, [&](int e) {
         const int r = e >> (l3 - 1), k = e & (M - 1);
-        const float2* x = src + (long long)r * nh;
+        const float2* x = src + (long long)r * hp;
         float2 xk = x[k];
         float2 xm = x[M - k];
         if (k == 0) { xk.y = 0.f; xm.y = 0.f; }
@@ -311,6 +313,7 @@ struct Mult {
     double alpha;   // regularisation weight
     int p;          // power of |k|^2
     double norm;    // 1 / (n1 n2 n3)
+    int hp;         // row pitch of the spectrum
 };
 
 __device__ __forceinline__ int signed_k(int i, int n) { return i < (n >> 1) ? i : i - n; }
@@ -343,8 +346,8 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     const int N = 1 << l1;
     const int c0 = blockIdx.x * CW;
     const int cw = min(CW, nh - c0);
-    const long long stride = (long long)m.n2 * nh;
-    const long long off = blockIdx.z * nspec + (long long)blockIdx.y * nh + c0;
+    const long long stride = (long long)m.n2 * m.hp;
+    const long long off = blockIdx.z * nspec + (long long)blockIdx.y * m.hp + c0;
     const int k2 = signed_k(blockIdx.y, m.n2);
     load_twiddles(tw_d, tw64, 1 << logT, tid);
     load_twiddles(tw_f, tw32, 1 << logT, tid);
@@ -397,8 +400,8 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     const int k2i = blockIdx.y;
     const int c0 = blockIdx.x * CW;
     const int cw = min(CW, nh - c0);
-    const long long stride = (long long)m.n2 * nh;
-    const long long off = (long long)k2i * nh + c0;
+    const long long stride = (long long)m.n2 * m.hp;
+    const long long off = (long long)k2i * m.hp + c0;
     const int k2 = signed_k(k2i, m.n2);
     const float norm = (float)m.norm;
     load_twiddles(tw_s, tw, 1 << logT, tid);
@@ -497,8 +500,8 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     const int k2i = blockIdx.y;
     const int c0 = blockIdx.x * CW;
     const int cw = min(CW, nh - c0);
-    const long long stride = (long long)m.n2 * nh;
-    const long long off = (long long)k2i * nh + c0;
+    const long long stride = (long long)m.n2 * m.hp;
+    const long long off = (long long)k2i * m.hp + c0;
     const float norm = (float)m.norm;
     const float alpha = (float)m.alpha;
     load_twiddles(tw_s, tw, 1 << logT, tid);
@@ -720,8 +723,10 @@ __global__ __launch_bounds__(kThreads) void k_mult_gen(float2* __restrict__ S,
                                                        double beta, double norm) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= nspec) return;
-    const int i3 = (int)(idx % nh);
-    const long long r = idx / nh;
+    const int hp = spec_pitch(nh);
+    const int i3 = (int)(idx % hp);
+    if (i3 >= nh) return;   // row padding
+    const long long r = idx / hp;
     const int i2 = (int)(r % n2);
     const int i1 = (int)(r / n2);
     const int k1 = signed_k(i1, n1), k2 = signed_k(i2, n2), k3 = i3;
@@ -862,7 +867,7 @@ int cols_launch(const Geo& g, const C* tw, int logT, C* spec, int CW, size_t sh,
                 hipStream_t s) {
     CL_TRY(allow_lds(k_c2c_cols<DIR, E, C>, sh));
     hipLaunchKernelGGL((k_c2c_cols<DIR, E, C>), grid, dim3(kThreads), sh, s, spec, g.l2, CW,
-                       (long long)g.nh, (long long)g.n2 * g.nh, g.nh, g.nspec, tw, logT);
+                       (long long)g.hp, (long long)g.n2 * g.hp, g.nh, g.nspec, tw, logT);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -943,8 +948,8 @@ int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_
         return CLAIRE_EINVAL;
     }
     const size_t sh = sizeof(C) * ((size_t)N + 2 * (size_t)N * CW);
-    const long long stride = axis == 1 ? (long long)g.n2 * g.nh : g.nh;
-    const long long ystride = axis == 1 ? g.nh : (long long)g.n2 * g.nh;
+    const long long stride = axis == 1 ? (long long)g.n2 * g.hp : g.hp;
+    const long long ystride = axis == 1 ? g.hp : (long long)g.n2 * g.hp;
     dim3 grid((g.nh + CW - 1) / CW, axis == 1 ? g.n2 : g.n1, ncomp);
     ColMult cm;
     cm.n2 = g.n2;
@@ -1047,7 +1052,7 @@ int cols_x1(const Geo& g, const float2* tw, int T, float2* spec, int ncomp, hipS
     const size_t sh = sizeof(float2) * ((1 << logT) + (size_t)g.n1 * CW);
     dim3 grid((g.nh + CW - 1) / CW, g.n2, ncomp);
     const int per = (g.n1 * CW + kThreads - 1) / kThreads;
-    const long long stride = (long long)g.n2 * g.nh, ystride = g.nh;
+    const long long stride = (long long)g.n2 * g.hp, ystride = g.hp;
     auto go = [&](auto kern) -> int {
         CL_TRY(allow_lds(kern, sh));
         hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, s, spec, g.l1, CW, stride, ystride,
@@ -1081,14 +1086,15 @@ __global__ __launch_bounds__(kThreads) void k_spec_restrict(const float2* __rest
     if (idx >= cspec * ncomp) return;
     const int comp = (int)(idx / cspec);
     const long long e = idx - comp * cspec;
-    const int i3 = (int)(e % ch);
-    const int i2 = (int)((e / ch) % c2);
-    const int i1 = (int)(e / ((long long)ch * c2));
+    const int chp = spec_pitch(ch), fhp = spec_pitch(fh);
+    const int i3 = (int)(e % chp);
+    const int i2 = (int)((e / chp) % c2);
+    const int i1 = (int)(e / ((long long)chp * c2));
     const int k1 = signed_k(i1, c1), k2 = signed_k(i2, c2), k3 = i3;
     float2 out = make_float2(0.f, 0.f);
-    if (kept(k1, k2, k3, c1, c2, c3)) {
+    if (i3 < ch && kept(k1, k2, k3, c1, c2, c3)) {
         const int j1 = (k1 + f1) % f1, j2 = (k2 + f2) % f2;
-        const float2 v = F[comp * fspec + ((long long)j1 * f2 + j2) * fh + k3];
+        const float2 v = F[comp * fspec + ((long long)j1 * f2 + j2) * fhp + k3];
         const float sg = (isqrt ? isqrt_symbol(alpha, p, k1, k2, k3) : 1.f) * inv_nf;
         out = make_float2(v.x * sg, v.y * sg);
     }
@@ -1106,15 +1112,17 @@ __global__ __launch_bounds__(kThreads) void k_spec_combine(float2* __restrict__ 
     if (idx >= fspec * ncomp) return;
     const int comp = (int)(idx / fspec);
     const long long e = idx - comp * fspec;
-    const int i3 = (int)(e % fh);
-    const int i2 = (int)((e / fh) % f2);
-    const int i1 = (int)(e / ((long long)fh * f2));
+    const int chp = spec_pitch(ch), fhp = spec_pitch(fh);
+    const int i3 = (int)(e % fhp);
+    if (i3 >= fh) return;   // row padding
+    const int i2 = (int)((e / fhp) % f2);
+    const int i1 = (int)(e / ((long long)fhp * f2));
     const int k1 = signed_k(i1, f1), k2 = signed_k(i2, f2), k3 = i3;
     const float sg = isqrt_symbol(alpha, p, k1, k2, k3);
     float2 out;
     if (kept(k1, k2, k3, c1, c2, c3)) {
         const int j1 = (k1 + c1) % c1, j2 = (k2 + c2) % c2;
-        const float2 v = S[comp * cspec + ((long long)j1 * c2 + j2) * ch + k3];
+        const float2 v = S[comp * cspec + ((long long)j1 * c2 + j2) * chp + k3];
         out = make_float2(v.x * sg * inv_nc, v.y * sg * inv_nc);
     } else {
         const float2 v = F[idx];
@@ -1208,6 +1216,7 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
     m.alpha = alpha;
     m.p = p;
     m.norm = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+    m.hp = g.hp;
     float2* S = w.spec;
     switch (mode) {
     case SPEC_GRAD:
@@ -1274,6 +1283,7 @@ int spectral_ni(const Geo& g, SpectralWork& w, NiMode mode, const float* in, flo
     m.alpha = alpha;
     m.p = 1;
     m.norm = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+    m.hp = g.hp;
     float2* S = w.spec;
     CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
     CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));

@@ -18,13 +18,17 @@ namespace claire {
 struct Geo {
     int n1, n2, n3;     // extents
     int l1, l2, l3;     // log2 of the extents (l1, l2 only meaningful when pow2)
-    int nh;             // n3/2 + 1: length of a half-complex x3 row
+    int nh;             // n3/2 + 1: bins of a half-complex x3 row
+    int hp;             // row pitch of the spectra: nh rounded up to 16 complex (128 B)
     long long n;        // voxels
-    long long nspec;    // half-complex spectrum length n1*n2*nh
+    long long nspec;    // half-complex spectrum length n1*n2*hp
     bool pow2;          // every extent a power of two
 };
 
 Geo make_geo(const int nx[3]);
+// Row pitch of a half-complex spectrum with nh bins: a multiple of 16 complex
+// values, so that column tiles read whole 128-byte lines.
+__host__ __device__ __forceinline__ int spec_pitch(int nh) { return (nh + 15) & ~15; }
 // CLAIRE_OK if nx is a supported grid (n3 a power of two, n1 and n2 even
 // products of 2, 3 and 5, all in [8, 1024]); else CLAIRE_EINVAL with a message
 int check_extents(const int nx[3]);
