@@ -232,42 +232,82 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(const float2* __restrict__ 
     __syncthreads();
     // Z[k] = (X[k] + conj X[M-k]) + i conj(w^k) (X[k] - conj X[M-k]); the
     // imaginary parts of the DC and Nyquist bins are ignored (real signal).
+    // A thread takes the pair (k, M-k), 0 < k < M/2, from one load of each
+    // bin; k = 0 also takes Z[0] (from X[0], X[M]) and Z[M/2]. All of a
+    // thread's loads are issued before its first LDS store.
     const int tsh = logT - l3;
-    stage<E>(buf, RB * M, tid, [&](int e) {
-        const int r = e >> (l3 - 1), k = e & (M - 1);
-        const float2* x = src + (long long)r * hp;
-        float2 xk = x[k];
-        float2 xm = x[M - k];
-        if (k == 0) { xk.y = 0.f; xm.y = 0.f; }
+    const int half = M >> 1, lh = l3 - 2;
+    auto zval = [&](float2 xk, float2 xm, int k) {
         const float2 xc = cconj(xm);
         const float2 sm = cadd(xk, xc);
         const float2 df = csub(xk, xc);
         const float2 w = cconj(tw_s[k << tsh]);
         return cadd(sm, times_i(cmul(w, df)));
-    });
-    __syncthreads();
-    lds_fft<+1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
-    float2* dst = reinterpret_cast<float2*>(out + blockIdx.y * n) + row0 * M;
-    double dot = 0.0;
-    if (AUX == 0) {
-        for (int e = tid; e < RB * M; e += kThreads) dst[e] = buf[e];
-    } else {
-        // all of this thread's aux loads in flight at once
-        const float2* ax = reinterpret_cast<const float2*>(aux + blockIdx.y * n) + row0 * M;
-        float2 pre[E];
+    };
+    {
+        constexpr int EH = E / 2;
+        const int npair = RB * half;
+        float2 xa[EH], xb[EH], xh[EH];
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
+        for (int i = 0; i < EH; ++i) {
             const int e = tid + i * kThreads;
-            if (e < RB * M) pre[i] = ax[e];
+            if (e < npair) {
+                const int r = e >> lh, k = e & (half - 1);
+                const float2* x = src + (long long)r * hp;
+                xa[i] = x[k];
+                xb[i] = x[M - k];
+                if (k == 0) xh[i] = x[half];
+            }
         }
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
+        for (int i = 0; i < EH; ++i) {
             const int e = tid + i * kThreads;
-            if (e < RB * M) {
-                float2 val = buf[e];
-                if (AUX == 1) { val.x += pre[i].x; val.y += pre[i].y; }
+            if (e < npair) {
+                const int r = e >> lh, k = e & (half - 1);
+                float2* z = buf + r * M;
+                if (k == 0) {
+                    float2 x0 = xa[i], xn = xb[i];
+                    x0.y = 0.f; xn.y = 0.f;
+                    z[0] = zval(x0, xn, 0);
+                    z[half] = zval(xh[i], xh[i], half);
+                } else {
+                    z[k] = zval(xa[i], xb[i], k);
+                    z[M - k] = zval(xb[i], xa[i], M - k);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<+1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
+    // output rows as 16-byte stores (two complex values of buf each)
+    float4* dst = reinterpret_cast<float4*>(out + blockIdx.y * n) + row0 * (M >> 1);
+    const float4* b4 = reinterpret_cast<const float4*>(buf);
+    const int nq = (RB * M) >> 1;
+    double dot = 0.0;
+    if (AUX == 0) {
+        for (int e = tid; e < nq; e += kThreads) dst[e] = b4[e];
+    } else {
+        // all of this thread's aux loads in flight at once
+        constexpr int EQ = E / 2;
+        const float4* ax = reinterpret_cast<const float4*>(aux + blockIdx.y * n) + row0 * (M >> 1);
+        float4 pre[EQ];
+#pragma unroll
+        for (int i = 0; i < EQ; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < nq) pre[i] = ax[e];
+        }
+#pragma unroll
+        for (int i = 0; i < EQ; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < nq) {
+                float4 val = b4[e];
+                if (AUX == 1) {
+                    val.x += pre[i].x; val.y += pre[i].y; val.z += pre[i].z; val.w += pre[i].w;
+                }
                 dst[e] = val;
-                if (AUX == 2) dot += (double)val.x * pre[i].x + (double)val.y * pre[i].y;
+                if (AUX == 2)
+                    dot += ((double)val.x * pre[i].x + (double)val.y * pre[i].y) +
+                           ((double)val.z * pre[i].z + (double)val.w * pre[i].w);
             }
         }
     }
@@ -318,6 +358,27 @@ struct Mult {
 
 __device__ __forceinline__ int signed_k(int i, int n) { return i < (n >> 1) ? i : i - n; }
 
+// Block coordinates of an x1 column-tile launch, grid (column blocks, n2,
+// components), reordered so that each of the 8 XCDs (which receive workgroups
+// round-robin in dispatch order) sweeps one contiguous range of (column block,
+// row, component): the two 8-column tiles that share each 128-byte line of a
+// spectrum row then run on the same XCD, close in time, and the line is
+// fetched from HBM once instead of once per L2. Grids whose size is not a
+// multiple of 8 keep the plain order.
+struct TileXYZ { int x, y, z; };
+__device__ __forceinline__ TileXYZ xcd_tile() {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned total = gx * gy * gridDim.z;
+    unsigned w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    if ((total & 7u) == 0) w = (w & 7u) * (total >> 3) + (w >> 3);
+    TileXYZ t;
+    const unsigned q = w / gx;
+    t.x = (int)(w - q * gx);
+    t.z = (int)(q / gy);
+    t.y = (int)(q - (unsigned)t.z * gy);
+    return t;
+}
+
 // wavenumber of an odd derivative: the Nyquist index of the axis maps to 0
 __device__ __forceinline__ float deriv_k(int i, int n) {
     return (i == (n >> 1)) ? 0.f : (float)signed_k(i, n);
@@ -344,11 +405,12 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     float2* Af = reinterpret_cast<float2*>(A);   // same storage, narrowed in place
     const int tid = threadIdx.x;
     const int N = 1 << l1;
-    const int c0 = blockIdx.x * CW;
+    const TileXYZ bt = xcd_tile();
+    const int c0 = bt.x * CW;
     const int cw = min(CW, nh - c0);
     const long long stride = (long long)m.n2 * m.hp;
-    const long long off = blockIdx.z * nspec + (long long)blockIdx.y * m.hp + c0;
-    const int k2 = signed_k(blockIdx.y, m.n2);
+    const long long off = bt.z * nspec + (long long)bt.y * m.hp + c0;
+    const int k2 = signed_k(bt.y, m.n2);
     load_twiddles(tw_d, tw64, 1 << logT, tid);
     load_twiddles(tw_f, tw32, 1 << logT, tid);
     stage<E>(A, N * CW, tid, [&](int e) {
@@ -397,8 +459,9 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     float2* B = A + ((MODE == SPEC_GRAD || MODE == SPEC_DIV) ? (1 << l1) * CW : 0);
     const int tid = threadIdx.x;
     const int N = 1 << l1;
-    const int k2i = blockIdx.y;
-    const int c0 = blockIdx.x * CW;
+    const TileXYZ bt = xcd_tile();
+    const int k2i = bt.y;
+    const int c0 = bt.x * CW;
     const int cw = min(CW, nh - c0);
     const long long stride = (long long)m.n2 * m.hp;
     const long long off = (long long)k2i * m.hp + c0;
@@ -420,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     };
 
     if (MODE == SPEC_REG_INV || MODE == SPEC_REG_ISQRT) {
-        const int comp = blockIdx.z;
+        const int comp = bt.z;
         load_tile(A, in + comp * nspec);
         __syncthreads();
         lds_fft<-1, E, true>(A, l1, CW, 1, CW, tw_s, logT, tid);
@@ -497,8 +560,9 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     const int tid = threadIdx.x;
     const int N = 1 << l1;
     const int tile = N * CW;
-    const int k2i = blockIdx.y;
-    const int c0 = blockIdx.x * CW;
+    const TileXYZ bt = xcd_tile();
+    const int k2i = bt.y;
+    const int c0 = bt.x * CW;
     const int cw = min(CW, nh - c0);
     const long long stride = (long long)m.n2 * m.hp;
     const long long off = (long long)k2i * m.hp + c0;
