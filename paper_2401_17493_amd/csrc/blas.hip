@@ -208,6 +208,47 @@ __global__ __launch_bounds__(kThreads) void k_als_update(const float* __restrict
     als[i] = fmaf(mu, als[i], r[i] - mean);
 }
 
+// 16-byte variants of xpby, the als update and fill for aligned vectors
+// whose length is a multiple of 4 (every field here: n3 >= 8); grid-stride.
+__global__ __launch_bounds__(kThreads) void k_xpby4(const float4* __restrict__ x,
+                                                    float4* __restrict__ y, float b,
+                                                    long long n4) {
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride) {
+        const float4 a = x[i];
+        float4 v = y[i];
+        v.x = fmaf(b, v.x, a.x);
+        v.y = fmaf(b, v.y, a.y);
+        v.z = fmaf(b, v.z, a.z);
+        v.w = fmaf(b, v.w, a.w);
+        y[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_als_update4(const float4* __restrict__ r,
+                                                          float4* __restrict__ als, float m0,
+                                                          float m1, float m2, float mu,
+                                                          long long n4) {
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
+        const float mean = (i < n4) ? m0 : (i < 2 * n4 ? m1 : m2);
+        const float4 a = r[i];
+        float4 v = als[i];
+        v.x = fmaf(mu, v.x, a.x - mean);
+        v.y = fmaf(mu, v.y, a.y - mean);
+        v.z = fmaf(mu, v.z, a.z - mean);
+        v.w = fmaf(mu, v.w, a.w - mean);
+        als[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill4(float4* __restrict__ y, float v,
+                                                    long long n4) {
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride)
+        y[i] = make_float4(v, v, v, v);
+}
+
 __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ y, float v, long long n) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i < n) y[i] = v;
@@ -341,8 +382,19 @@ int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s) {
     return 0;
 }
 
+// true when both pointers are 16-byte aligned and n is a multiple of 4
+static bool vec4(const void* a, const void* b, long long n) {
+    return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15u) == 0 &&
+           (n & 3) == 0;
+}
+
 int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, b, n);
+    if (vec4(x, y, n))
+        hipLaunchKernelGGL(k_xpby4, dim3(red_blocks(n)), dim3(kThreads), 0, s,
+                           reinterpret_cast<const float4*>(x), reinterpret_cast<float4*>(y), b,
+                           n / 4);
+    else
+        hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, b, n);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -372,14 +424,23 @@ int launch_lincomb(const float* x, const float* z, float* y, float b, long long 
 
 int launch_als_update(const float* r, float* als, const double mean[3], float mu, long long n,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_als_update, dim3(blocks_for(3 * n)), dim3(kThreads), 0, s, r, als,
-                       (float)mean[0], (float)mean[1], (float)mean[2], mu, n);
+    if (vec4(r, als, n))
+        hipLaunchKernelGGL(k_als_update4, dim3(red_blocks(3 * n)), dim3(kThreads), 0, s,
+                           reinterpret_cast<const float4*>(r), reinterpret_cast<float4*>(als),
+                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n / 4);
+    else
+        hipLaunchKernelGGL(k_als_update, dim3(blocks_for(3 * n)), dim3(kThreads), 0, s, r, als,
+                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n);
     CL_LAUNCH_CHECK();
     return 0;
 }
 
 int launch_fill(float* y, float value, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, y, value, n);
+    if (vec4(y, y, n))
+        hipLaunchKernelGGL(k_fill4, dim3(red_blocks(n)), dim3(kThreads), 0, s,
+                           reinterpret_cast<float4*>(y), value, n / 4);
+    else
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, y, value, n);
     CL_LAUNCH_CHECK();
     return 0;
 }
