@@ -100,7 +100,8 @@ __device__ __forceinline__ void stockham_stage(C* buf, int logN, int nb, int bs,
         const int t = tid + i * kThreads;
         if (t < total) {
             int b, j;
-            if (BMAJOR) { b = t % nb; j = t / nb; }
+            // B-major batches (column tiles) come in powers of two
+            if (BMAJOR) { b = t & (nb - 1); j = t >> (31 - __clz(nb)); }
             else        { j = t & (nbf - 1); b = t >> (logN - logR); }
             const int k = j & (Ns - 1);
             const C* src = buf + b * bs;
@@ -330,19 +331,20 @@ __global__ __launch_bounds__(kThreads) void k_c2c_cols(C* __restrict__ data, int
     C* tw_s = reinterpret_cast<C*>(smem_raw);
     C* buf = tw_s + (1 << logT);
     const int tid = threadIdx.x;
+    const int lcw = 31 - __clz(CW);   // CW is a power of two
     const int N = 1 << logN;
     const int c0 = blockIdx.x * CW;
     const int cw = min(CW, nh - c0);
     C* base = data + blockIdx.z * nspec + blockIdx.y * ystride + c0;
     load_twiddles(tw_s, tw, 1 << logT, tid);
     stage<E>(buf, N * CW, tid, [&](int e) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         return (c < cw) ? base[r * stride + c] : cx<C>(0, 0);
     });
     __syncthreads();
     lds_fft<DIR, E, true>(buf, logN, CW, 1, CW, tw_s, logT, tid);
     for (int e = tid; e < N * CW; e += kThreads) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         if (c < cw) base[r * stride + c] = buf[e];
     }
 }
@@ -404,6 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     double2* A = reinterpret_cast<double2*>(tw_f + (1 << logT));
     float2* Af = reinterpret_cast<float2*>(A);   // same storage, narrowed in place
     const int tid = threadIdx.x;
+    const int lcw = 31 - __clz(CW);   // CW is a power of two
     const int N = 1 << l1;
     const TileXYZ bt = xcd_tile();
     const int c0 = bt.x * CW;
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     load_twiddles(tw_d, tw64, 1 << logT, tid);
     load_twiddles(tw_f, tw32, 1 << logT, tid);
     stage<E>(A, N * CW, tid, [&](int e) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         return (c < cw) ? in[off + r * stride + c] : make_double2(0.0, 0.0);
     });
     __syncthreads();
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     for (int i = 0; i < PER; ++i) {
         const int e = tid + i * kThreads;
         if (e < N * CW) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             const double f = m.norm * m.alpha * reg_symbol(m.p, signed_k(r, m.n1), k2, c0 + c);
             const double2 a = A[e];
             keep[i] = make_float2((float)(a.x * f), (float)(a.y * f));
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     __syncthreads();
     lds_fft<+1, E, true>(Af, l1, CW, 1, CW, tw_f, logT, tid);
     for (int e = tid; e < N * CW; e += kThreads) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         if (c < cw) out[off + r * stride + c] = Af[e];
     }
 }
@@ -458,6 +461,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
     float2* A = tw_s + (1 << logT);
     float2* B = A + ((MODE == SPEC_GRAD || MODE == SPEC_DIV) ? (1 << l1) * CW : 0);
     const int tid = threadIdx.x;
+    const int lcw = 31 - __clz(CW);   // CW is a power of two
     const int N = 1 << l1;
     const TileXYZ bt = xcd_tile();
     const int k2i = bt.y;
@@ -471,13 +475,13 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
 
     auto load_tile = [&](float2* dstb, const float2* src) {
         stage<E>(dstb, N * CW, tid, [&](int e) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             return (c < cw) ? src[off + r * stride + c] : make_float2(0.f, 0.f);
         });
     };
     auto store_tile = [&](const float2* srcb, float2* dstp) {
         for (int e = tid; e < N * CW; e += kThreads) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             if (c < cw) dstp[off + r * stride + c] = srcb[e];
         }
     };
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         lds_fft<-1, E, true>(A, l1, CW, 1, CW, tw_s, logT, tid);
         const float alpha = (float)m.alpha;
         for (int e = tid; e < N * CW; e += kThreads) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             const float sym = (float)reg_symbol(m.p, signed_k(r, m.n1), k2, c0 + c);
             const float f = (sym == 0.f) ? norm
                             : (MODE == SPEC_REG_INV ? norm / (alpha * sym)
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         const float kd2 = deriv_k(k2i, m.n2);
         for (int a = 0; a < 3; ++a) {
             for (int e = tid; e < N * CW; e += kThreads) {
-                const int r = e / CW, c = e - r * CW;
+                const int r = e >> lcw, c = e & (CW - 1);
                 float ka;
                 if (a == 0) ka = deriv_k(r, m.n1);
                 else if (a == 1) ka = kd2;
@@ -525,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
             __syncthreads();
             lds_fft<-1, E, true>(B, l1, CW, 1, CW, tw_s, logT, tid);
             for (int e = tid; e < N * CW; e += kThreads) {
-                const int r = e / CW, c = e - r * CW;
+                const int r = e >> lcw, c = e & (CW - 1);
                 float ka;
                 if (a == 0) ka = deriv_k(r, m.n1);
                 else if (a == 1) ka = kd2;
@@ -558,6 +562,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     float2* tw_s = reinterpret_cast<float2*>(smem_raw);
     float2* T = tw_s + (1 << logT);
     const int tid = threadIdx.x;
+    const int lcw = 31 - __clz(CW);   // CW is a power of two
     const int N = 1 << l1;
     const int tile = N * CW;
     const TileXYZ bt = xcd_tile();
@@ -572,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     for (int a = 0; a < 3; ++a) {
         const float2* src = data + a * nspec;
         stage<E>(T + a * tile, tile, tid, [&](int e) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             return (c < cw) ? src[off + r * stride + c] : make_float2(0.f, 0.f);
         });
     }
@@ -581,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
     const int k2 = signed_k(k2i, m.n2);
     const float kd2 = deriv_k(k2i, m.n2);
     for (int e = tid; e < tile; e += kThreads) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         const int k1 = signed_k(r, m.n1), k3 = c0 + c;
         const float kd1 = deriv_k(r, m.n1), kd3 = deriv_k(k3, m.n3);
         const float kk = (float)(k1 * k1 + k2 * k2 + k3 * k3);
@@ -609,7 +614,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_coupled(float2* __restrict__ da
         lds_fft<+1, E, true>(buf, l1, CW, 1, CW, tw_s, logT, tid);
         float2* dst = data + a * nspec;
         for (int e = tid; e < tile; e += kThreads) {
-            const int r = e / CW, c = e - r * CW;
+            const int r = e >> lcw, c = e & (CW - 1);
             if (c < cw) dst[off + r * stride + c] = buf[e];
         }
     }
@@ -856,11 +861,14 @@ int ilog2(int v) {
 
 // Column tile width for a transform of length N with `elems` complex values
 // per tile (E = elems / kThreads per thread).
+// The width is a power of two: the column-tile kernels index their tiles
+// with shifts and masks.
 int tile_cols(int N, int nh, int elems) {
     int C = elems / N;
     if (C > 16) C = 16;
     if (C > nh) C = nh;
     if (C < 1) C = 1;
+    while (C & (C - 1)) C &= C - 1;   // round down to a power of two
     return C;
 }
 
