@@ -198,8 +198,10 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(const float* __restrict__ i
     lds_fft<-1, E, false>(buf, l3 - 1, RB, M, 1, tw_s, logT, tid);
     // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) w^k (Z[k] - conj Z[M-k]), w = exp(-2 pi i / n3)
     const int tsh = logT - l3;
+    const float inv_nh = quot_inv(nh);   // RB nh < 2^14 and nh <= 513
     for (int e = tid; e < RB * nh; e += kThreads) {
-        const int r = e / nh, k = e - r * nh;
+        int k;
+        const int r = quot(e, nh, inv_nh, k);
         const C* z = buf + r * M;
         const C zk = z[k & (M - 1)];
         const C zc = cconj(z[(M - k) & (M - 1)]);

@@ -29,6 +29,18 @@ Geo make_geo(const int nx[3]);
 // Row pitch of a half-complex spectrum with nh bins: a multiple of 16 complex
 // values, so that column tiles read whole 128-byte lines.
 __host__ __device__ __forceinline__ int spec_pitch(int nh) { return (nh + 15) & ~15; }
+
+// Exact a / b for 0 <= a < 2^14 and 1 <= b <= 4096 from one float product:
+// with inv_b = (1 + 2^-16) / b rounded to float, trunc(a * inv_b) = floor(a/b)
+// (the bias lifts exact multiples above the rounding error and stays below
+// 1/b for a < 2^14; verified exhaustively in IEEE single precision over that
+// range). 24-bit integer products keep the remainder full-rate.
+__device__ __forceinline__ float quot_inv(int b) { return (1.0f + 0x1p-16f) / (float)b; }
+__device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
+    const int q = (int)((float)a * inv_b);
+    r = a - (int)__umul24((unsigned)q, (unsigned)b);
+    return q;
+}
 // CLAIRE_OK if nx is a supported grid (n3 a power of two, n1 and n2 even
 // products of 2, 3 and 5, all in [8, 1024]); else CLAIRE_EINVAL with a message
 int check_extents(const int nx[3]);

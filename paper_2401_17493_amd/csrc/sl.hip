@@ -364,18 +364,6 @@ __device__ __forceinline__ Box reduce_box(int mn1, int mn2, int mn3, int mx1, in
     return b;
 }
 
-// Exact a / b for 0 <= a < 2^14 and 1 <= b <= 4096 from one float product:
-// with inv_b = (1 + 2^-16) / b rounded to float, trunc(a * inv_b) = floor(a/b)
-// (the bias lifts exact multiples above the rounding error and stays below
-// 1/b for a < 2^14; verified exhaustively in IEEE single precision over that
-// range). 24-bit integer products keep the remainder full-rate.
-__device__ __forceinline__ float quot_inv(int b) { return (1.0f + 0x1p-16f) / (float)b; }
-__device__ __forceinline__ int quot(int a, int b, float inv_b, int& r) {
-    const int q = (int)((float)a * inv_b);
-    r = a - (int)__umul24((unsigned)q, (unsigned)b);
-    return q;
-}
-
 // Copy the box of field `src` into LDS (requires b.vol within the LDS
 // budget; rows e1 e2 < 2^14). Row `row` = a1 e2 + a2 starts at LDS float
 // a1 pp + a2 p3 and holds columns cb .. cb + p3 - 1 as ng float4 segments. A
