@@ -683,9 +683,12 @@ __device__ __forceinline__ void stage_gen(const C* src, C* dst, int N, int CW, i
                                           const C* tw, int tid) {
     const int M = N / R;
     const int tstep = N / (Ns * R);
+    const int lcw = 31 - __clz(CW);        // CW is a power of two
+    const float inv_ns = quot_inv(Ns);     // j < N <= 1024, Ns <= 1024
     for (int t = tid; t < M * CW; t += kThreads) {
-        const int j = t / CW, col = t - j * CW;
-        const int k = j % Ns;
+        const int j = t >> lcw, col = t & (CW - 1);
+        int k;
+        (void)quot(j, Ns, inv_ns, k);      // k = j mod Ns
         C x[R], y[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -747,12 +750,14 @@ __global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int
     C* A = tw_s + N;
     C* B = A + N * CW;
     const int tid = threadIdx.x;
-    const int c0 = blockIdx.x * CW;
+    const int lcw = 31 - __clz(CW);   // CW is a power of two
+    const TileXYZ bt = xcd_tile();
+    const int c0 = bt.x * CW;
     const int cw = min(CW, nh - c0);
-    C* base = data + blockIdx.z * nspec + blockIdx.y * ystride + c0;
+    C* base = data + bt.z * nspec + bt.y * ystride + c0;
     for (int q = tid; q < N; q += kThreads) tw_s[q] = tw[q];
     for (int e = tid; e < N * CW; e += kThreads) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         A[e] = (c < cw) ? base[r * stride + c] : cx<C>(0, 0);
     }
     __syncthreads();
@@ -762,20 +767,21 @@ __global__ __launch_bounds__(kThreads) void k_cols_gen(C* __restrict__ data, int
         stages_gen<DIR, C, 0>(src, dst, N, CW, tw_s, plan, tid);
     } else {
         stages_gen<-1, C, 0>(src, dst, N, CW, tw_s, plan, tid);
-        const int k2 = signed_k(blockIdx.y, cm.n2);
+        const int k2 = signed_k(bt.y, cm.n2);
+        const float alpha = (float)cm.alpha, norm = (float)cm.norm;
         for (int e = tid; e < N * CW; e += kThreads) {
-            const int r = e / CW, c = e - r * CW;
-            const double sym = cm.alpha * reg_symbol(cm.p, signed_k(r, N), k2, c0 + c);
-            const float f = (float)(sym == 0.0 ? cm.norm
-                                               : (MULT == 1 ? cm.norm / sym
-                                                            : cm.norm / sqrt(sym)));
+            const int r = e >> lcw, c = e & (CW - 1);
+            // in float, as in the power-of-two x1 pass
+            const float sym = alpha * (float)reg_symbol(cm.p, signed_k(r, N), k2, c0 + c);
+            const float f = (sym == 0.f) ? norm
+                            : (MULT == 1 ? norm / sym : norm / sqrtf(sym));
             src[e] = cscale(src[e], f);
         }
         __syncthreads();
         stages_gen<+1, C, 0>(src, dst, N, CW, tw_s, plan, tid);
     }
     for (int e = tid; e < N * CW; e += kThreads) {
-        const int r = e / CW, c = e - r * CW;
+        const int r = e >> lcw, c = e & (CW - 1);
         if (c < cw) base[r * stride + c] = src[e];
     }
 }
@@ -794,12 +800,15 @@ __global__ __launch_bounds__(kThreads) void k_mult_gen(float2* __restrict__ S,
                                                        double beta, double norm) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= nspec) return;
-    const int hp = spec_pitch(nh);
-    const int i3 = (int)(idx % hp);
+    const unsigned hp = (unsigned)spec_pitch(nh);
+    // nspec < 2^32 (extents <= 1024): 32-bit index arithmetic
+    const unsigned u = (unsigned)idx;
+    const unsigned r = u / hp;
+    const int i3 = (int)(u - r * hp);
     if (i3 >= nh) return;   // row padding
-    const long long r = idx / hp;
-    const int i2 = (int)(r % n2);
-    const int i1 = (int)(r / n2);
+    const unsigned r1 = r / (unsigned)n2;
+    const int i2 = (int)(r - r1 * (unsigned)n2);
+    const int i1 = (int)r1;
     const int k1 = signed_k(i1, n1), k2 = signed_k(i2, n2), k3 = i3;
     const float kd[3] = {deriv_k(i1, n1), deriv_k(i2, n2), deriv_k(i3, n3)};
     const float nf = (float)norm;
@@ -971,25 +980,25 @@ int cols_x2(const Geo& g, const C* tw, int T, C* spec, int ncomp, hipStream_t s)
 }
 
 template <int MODE>
-int fused_x1(const Geo& g, const SpectralWork& w, const float2* in, float2* out, Mult m,
+int fused_x1(const Geo& g, const float2* tw, int T, const float2* in, float2* out, Mult m,
              int ncomp, hipStream_t s) {
     const int CW = tile_cols(g.n1, g.nh, CLAIRE_FFT_X1_ELEMS);
-    const int logT = ilog2(w.tw_n);
+    const int logT = ilog2(T);
     const int tiles = (MODE == SPEC_GRAD || MODE == SPEC_DIV) ? 2 : 1;
     const size_t sh = sizeof(float2) * ((1 << logT) + (size_t)tiles * g.n1 * CW);
     dim3 grid((g.nh + CW - 1) / CW, g.n2, ncomp);
     if (g.n1 * CW <= 8 * kThreads) {
         CL_TRY(allow_lds(k_x1_fused<MODE, 8>, sh));
         hipLaunchKernelGGL((k_x1_fused<MODE, 8>), grid, dim3(kThreads), sh, s, in, out, g.l1, CW,
-                           g.nh, g.nspec, m, w.tw, logT);
+                           g.nh, g.nspec, m, tw, logT);
     } else if (g.n1 * CW <= 16 * kThreads) {
         CL_TRY(allow_lds(k_x1_fused<MODE, 16>, sh));
         hipLaunchKernelGGL((k_x1_fused<MODE, 16>), grid, dim3(kThreads), sh, s, in, out, g.l1, CW,
-                           g.nh, g.nspec, m, w.tw, logT);
+                           g.nh, g.nspec, m, tw, logT);
     } else {
         CL_TRY(allow_lds(k_x1_fused<MODE, 32>, sh));
         hipLaunchKernelGGL((k_x1_fused<MODE, 32>), grid, dim3(kThreads), sh, s, in, out, g.l1, CW,
-                           g.nh, g.nspec, m, w.tw, logT);
+                           g.nh, g.nspec, m, tw, logT);
     }
     CL_LAUNCH_CHECK();
     return 0;
@@ -1021,6 +1030,7 @@ int cols_gen(const Geo& g, int axis, const C* tw, C* spec, int ncomp, hipStream_
         set_error("column length %d exceeds the general-grid FFT tile", N);
         return CLAIRE_EINVAL;
     }
+    while (CW & (CW - 1)) CW &= CW - 1;   // a power of two: shift indexing
     const size_t sh = sizeof(C) * ((size_t)N + 2 * (size_t)N * CW);
     const long long stride = axis == 1 ? (long long)g.n2 * g.hp : g.hp;
     const long long ystride = axis == 1 ? g.hp : (long long)g.n2 * g.hp;
@@ -1049,6 +1059,23 @@ int mult_gen(const Geo& g, SpectralWork& w, double alpha, int p, double beta, hi
 // pointwise multiplier, x1 and x2 inverse columns, x3 C2R (with the addend
 // or the fused dot product); for (alpha L)^{-1} and (alpha L)^{-1/2} the x1
 // forward, multiplier and x1 inverse are one pass.
+template <int DIR>
+int cols_x1(const Geo& g, const float2* tw, int T, float2* spec, int ncomp, hipStream_t s);
+
+// Column passes of a general grid: an axis whose extent is a power of two
+// takes the power-of-two column kernels (with that axis's own twiddle table),
+// the others the mixed-radix ones.
+template <int DIR>
+int gen_x1(const Geo& g, const SpectralWork& w, float2* S, int ncomp, hipStream_t s) {
+    if ((1 << g.l1) == g.n1) return cols_x1<DIR>(g, w.tw1, g.n1, S, ncomp, s);
+    return cols_gen<DIR>(g, 1, w.tw1, S, ncomp, s);
+}
+template <int DIR, typename C>
+int gen_x2(const Geo& g, const C* tw2, C* S, int ncomp, hipStream_t s) {
+    if ((1 << g.l2) == g.n2) return cols_x2<DIR>(g, tw2, g.n2, S, ncomp, s);
+    return cols_gen<DIR>(g, 2, tw2, S, ncomp, s);
+}
+
 int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float* out,
                  double alpha, int p, double beta, hipStream_t s, const float* add,
                  const float* dot_with, Reducer* red, int slot) {
@@ -1058,20 +1085,36 @@ int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float
     if (mode == GM_REG_INV || mode == GM_REG_ISQRT) {
         // the multiplier is fused into the x1 pass
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
-        CL_TRY(cols_gen<-1>(g, 2, w.tw2, S, 3, s));
-        if (mode == GM_REG_INV) CL_TRY((cols_gen<-1, float2, 1>(g, 1, w.tw1, S, 3, s, alpha, p)));
-        else CL_TRY((cols_gen<-1, float2, 2>(g, 1, w.tw1, S, 3, s, alpha, p)));
-        CL_TRY(cols_gen<+1>(g, 2, w.tw2, S, 3, s));
+        CL_TRY(gen_x2<-1>(g, w.tw2, S, 3, s));
+        if ((1 << g.l1) == g.n1) {
+            Mult m;
+            m.n1 = g.n1;
+            m.n2 = g.n2;
+            m.n3 = g.n3;
+            m.alpha = alpha;
+            m.p = p;
+            m.norm = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+            m.hp = g.hp;
+            if (mode == GM_REG_INV)
+                CL_TRY(fused_x1<SPEC_REG_INV>(g, w.tw1, g.n1, S, S, m, 3, s));
+            else
+                CL_TRY(fused_x1<SPEC_REG_ISQRT>(g, w.tw1, g.n1, S, S, m, 3, s));
+        } else if (mode == GM_REG_INV) {
+            CL_TRY((cols_gen<-1, float2, 1>(g, 1, w.tw1, S, 3, s, alpha, p)));
+        } else {
+            CL_TRY((cols_gen<-1, float2, 2>(g, 1, w.tw1, S, 3, s, alpha, p)));
+        }
+        CL_TRY(gen_x2<+1>(g, w.tw2, S, 3, s));
         return inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot);
     }
     if (mode == GM_REG) {
         CL_TRY(fwd_x3(g, w.tw64, w.tw_n, in, w.spec64, 3, s));
-        CL_TRY(cols_gen<-1>(g, 2, w.tw2_64, w.spec64, 3, s));
+        CL_TRY(gen_x2<-1>(g, w.tw2_64, w.spec64, 3, s));
         CL_TRY(cols_gen<-1>(g, 1, w.tw1_64, w.spec64, 3, s));
     } else {
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, nin, s));
-        CL_TRY(cols_gen<-1>(g, 2, w.tw2, S, nin, s));
-        CL_TRY(cols_gen<-1>(g, 1, w.tw1, S, nin, s));
+        CL_TRY(gen_x2<-1>(g, w.tw2, S, nin, s));
+        CL_TRY(gen_x1<-1>(g, w, S, nin, s));
     }
     switch (mode) {
     case GM_GRAD: CL_TRY(mult_gen<GM_GRAD>(g, w, alpha, p, beta, s)); break;
@@ -1080,8 +1123,8 @@ int spectral_gen(const Geo& g, SpectralWork& w, int mode, const float* in, float
     case GM_NI_PROJECT: CL_TRY(mult_gen<GM_NI_PROJECT>(g, w, alpha, p, beta, s)); break;
     default: CL_TRY(mult_gen<GM_NI_PENALTY>(g, w, alpha, p, beta, s)); break;
     }
-    CL_TRY(cols_gen<+1>(g, 1, w.tw1, S, nout, s));
-    CL_TRY(cols_gen<+1>(g, 2, w.tw2, S, nout, s));
+    CL_TRY(gen_x1<+1>(g, w, S, nout, s));
+    CL_TRY(gen_x2<+1>(g, w.tw2, S, nout, s));
     return inv_x3(g, w, S, out, add, nout, s, dot_with, red, slot);
 }
 
@@ -1297,14 +1340,14 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 1, s));
         CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 1, s));
         // output a = 0 overwrites the input tile only after it was loaded
-        CL_TRY(fused_x1<SPEC_GRAD>(g, w, S, S, m, 1, s));
+        CL_TRY(fused_x1<SPEC_GRAD>(g, w.tw, w.tw_n, S, S, m, 1, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(inv_x3(g, w, S, out, add, 3, s));
         break;
     case SPEC_DIV:
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
         CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
-        CL_TRY(fused_x1<SPEC_DIV>(g, w, S, S, m, 1, s));
+        CL_TRY(fused_x1<SPEC_DIV>(g, w.tw, w.tw_n, S, S, m, 1, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 1, s));
         CL_TRY(inv_x3(g, w, S, out, add, 1, s));
         break;
@@ -1318,14 +1361,14 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
     case SPEC_REG_INV:
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
         CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
-        CL_TRY(fused_x1<SPEC_REG_INV>(g, w, S, S, m, 3, s));
+        CL_TRY(fused_x1<SPEC_REG_INV>(g, w.tw, w.tw_n, S, S, m, 3, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(inv_x3(g, w, S, out, add, 3, s, dot_with, red, slot));
         break;
     case SPEC_REG_ISQRT:
         CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
         CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
-        CL_TRY(fused_x1<SPEC_REG_ISQRT>(g, w, S, S, m, 3, s));
+        CL_TRY(fused_x1<SPEC_REG_ISQRT>(g, w.tw, w.tw_n, S, S, m, 3, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(inv_x3(g, w, S, out, add, 3, s));
         break;

@@ -19,8 +19,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-# radices: 24 = 4.2.3, 20 = 4.5, 30 = 2.3.5, 12 = 4.3, 18 = 2.3.3, 50 = 2.5.5
-SHAPES = [(24, 20, 16), (30, 12, 32), (18, 50, 8)]
+# radices: 24 = 4.2.3, 20 = 4.5, 30 = 2.3.5, 12 = 4.3, 18 = 2.3.3, 50 = 2.5.5;
+# the last two shapes have one power-of-two column axis (16), which takes the
+# power-of-two column kernels (as x1 = 256 of the NIREP grid does)
+SHAPES = [(24, 20, 16), (30, 12, 32), (18, 50, 8), (16, 30, 16), (20, 16, 32)]
 
 
 @pytest.fixture(scope="module")
@@ -128,9 +130,10 @@ def test_detdefgrad_general(C):
     assert s["nonpositive"] == int((ref <= 0).sum())
 
 
-def test_full_solve_general(C):
+@pytest.mark.parametrize("n", [(24, 20, 32), (32, 20, 32)])
+def test_full_solve_general(C, n):
     nt, alpha = 4, 1e-2
-    grid, m0, m1, vstar = blob_problem(n=(24, 20, 32), kmax=4)
+    grid, m0, m1, vstar = blob_problem(n=n, kmax=4)
     v_ref, _, s_ref = O.gn_solve(grid, m0, m1, nt, 1, [alpha])
     with C.Context(grid.n, nt, alpha, 1) as ctx:
         ctx.set_images(dev(m0), dev(m1))
