@@ -384,6 +384,7 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
     float4* box4 = reinterpret_cast<float4*>(box);
     for (int r = r0; r < nrows; r += rpp * kSegBatch) {
         float4 tmp[kSegBatch];
+        unsigned at[kSegBatch];   // LDS float4 index of each segment
 #pragma unroll
         for (int u = 0; u < kSegBatch; ++u) {
             const int row = r + u * rpp;
@@ -398,18 +399,13 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
                     off = ((unsigned)((b.lo1 + a1) & g.m1) << g.s1) |
                           ((unsigned)((b.lo2 + a2) & g.m2) << g.l3) | col;
                 tmp[u] = ldi4(src, off);
+                at[u] = __umul24((unsigned)a1, (unsigned)(b.pp >> 2)) +
+                        __umul24((unsigned)a2, (unsigned)b.ng) + j;
             }
         }
 #pragma unroll
-        for (int u = 0; u < kSegBatch; ++u) {
-            const int row = r + u * rpp;
-            if (row < nrows) {
-                int a2;
-                const int a1 = quot(row, b.e2, inv_e2, a2);
-                box4[__umul24((unsigned)a1, (unsigned)(b.pp >> 2)) +
-                     __umul24((unsigned)a2, (unsigned)b.ng) + j] = tmp[u];
-            }
-        }
+        for (int u = 0; u < kSegBatch; ++u)
+            if (r + u * rpp < nrows) box4[at[u]] = tmp[u];
     }
 }
 
