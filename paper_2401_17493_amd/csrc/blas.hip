@@ -126,23 +126,36 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restric
     }
 }
 
-// fold nb partials (with element stride `stride`, offset `off`) into result[slot]
+// fold nb partials (with element stride `stride`, offset `off`) into
+// result[slot] on the device and, when given, into the mapped host mirror
+// (the host reads it after a stream synchronisation, with no copy). One
+// 1024-thread block: few dependent load rounds even for thousands of partials.
+constexpr int kFoldThreads = 1024;
 template <int OP>
-__global__ __launch_bounds__(kThreads) void k_fold(const double* __restrict__ partial, int nb,
-                                                   int stride, int off,
-                                                   double* __restrict__ result, int slot) {
-    __shared__ double sh[kThreads / kWave];
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const double* __restrict__ partial,
+                                                       int nb, int stride, int off,
+                                                       double* __restrict__ result, int slot,
+                                                       double* __restrict__ mirror) {
+    __shared__ double sh[kFoldThreads / kWave];
     // four independent accumulators keep several loads in flight
     double acc[4] = {identity<OP>(), identity<OP>(), identity<OP>(), identity<OP>()};
     int i = threadIdx.x;
-    for (; i + 3 * kThreads < nb; i += 4 * kThreads) {
+    for (; i + 3 * kFoldThreads < nb; i += 4 * kFoldThreads) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = combine<OP>(acc[u], partial[(i + u * kThreads) * stride + off]);
+        for (int u = 0; u < 4; ++u)
+            acc[u] = combine<OP>(acc[u], partial[(i + u * kFoldThreads) * stride + off]);
     }
-    for (; i < nb; i += kThreads) acc[0] = combine<OP>(acc[0], partial[i * stride + off]);
+    for (; i < nb; i += kFoldThreads) acc[0] = combine<OP>(acc[0], partial[i * stride + off]);
     double a = combine<OP>(combine<OP>(acc[0], acc[1]), combine<OP>(acc[2], acc[3]));
-    a = block_reduce<OP>(a, sh);
-    if (threadIdx.x == 0) result[slot] = a;
+    for (int o = kWave / 2; o > 0; o >>= 1) a = combine<OP>(a, __shfl_down(a, o, kWave));
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int w = 1; w < kFoldThreads / kWave; ++w) r = combine<OP>(r, sh[w]);
+        result[slot] = r;
+        if (mirror) mirror[slot] = r;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_axpy(const float* __restrict__ x,
@@ -292,8 +305,8 @@ int red_generic(Reducer& r, const float* a, const float* b, long long n, int slo
     hipLaunchKernelGGL(k_partial<KIND>, dim3(nb), dim3(kThreads), 0, s, a, b, n, r.partial);
     CL_LAUNCH_CHECK();
     constexpr int OP = (KIND == 2) ? OP_MAX : OP_SUM;
-    hipLaunchKernelGGL(k_fold<OP>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 1, 0,
-                       r.result, slot);
+    hipLaunchKernelGGL(k_fold<OP>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 1, 0,
+                       r.result, slot, r.mirror);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -305,7 +318,10 @@ int reducer_init(Reducer& r, long long n) {
     if ((n + kThreads - 1) / kThreads > np) np = (n + kThreads - 1) / kThreads;
     CL_HIP(hipMalloc(&r.partial, sizeof(double) * np));
     CL_HIP(hipMalloc(&r.result, sizeof(double) * 8));
-    CL_HIP(hipHostMalloc(&r.host, sizeof(double) * 8, hipHostMallocDefault));
+    // pinned, mapped, coherent: the folds store their results here as well
+    CL_HIP(hipHostMalloc(&r.host, sizeof(double) * 8,
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    CL_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&r.mirror), r.host, 0));
     return 0;
 }
 
@@ -337,17 +353,17 @@ int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s) {
     const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_partial_stats, dim3(nb), dim3(kThreads), 0, s, a, n, r.partial);
     CL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fold<OP_MIN>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 0, r.result, 0);
-    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 1, r.result, 1);
-    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 2, r.result, 2);
-    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 4, 3, r.result, 3);
+    hipLaunchKernelGGL(k_fold<OP_MIN>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 4, 0, r.result, 0, r.mirror);
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 4, 1, r.result, 1, r.mirror);
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 4, 2, r.result, 2, r.mirror);
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 4, 3, r.result, 3, r.mirror);
     CL_LAUNCH_CHECK();
     return 0;
 }
 
 int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, s, r.partial, nb, stride, off,
-                       r.result, slot);
+    hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, nb, stride, off,
+                       r.result, slot, r.mirror);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -361,17 +377,18 @@ int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, flo
                        reinterpret_cast<float4*>(vt), reinterpret_cast<float4*>(r), kappa, n4,
                        red.partial);
     CL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, st, red.partial, (int)nb, 4, 0,
-                       red.result, smax);
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, st, red.partial, (int)nb, 4, 0,
+                       red.result, smax, red.mirror);
     for (int a = 0; a < 3; ++a)
-        hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kThreads), 0, st, red.partial, (int)nb, 4,
-                           1 + a, red.result, ssum + a);
+        hipLaunchKernelGGL(k_fold<OP_SUM>, dim3(1), dim3(kFoldThreads), 0, st, red.partial, (int)nb, 4,
+                           1 + a, red.result, ssum + a, red.mirror);
     CL_LAUNCH_CHECK();
     return 0;
 }
 
+// every fold also wrote its slot to the mapped host mirror r.host: waiting
+// for the stream is enough
 int red_fetch(Reducer& r, hipStream_t s) {
-    CL_HIP(hipMemcpyAsync(r.host, r.result, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
     CL_HIP(hipStreamSynchronize(s));
     return 0;
 }
@@ -410,8 +427,8 @@ int launch_xpby_absmax(Reducer& r, const float* x, float* y, float b, long long 
                        reinterpret_cast<const float4*>(x), reinterpret_cast<float4*>(y), b, n / 4,
                        n, r.partial);
     CL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kThreads), 0, s, r.partial, (int)nb, 1, 0,
-                       r.result, slot);
+    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 1, 0,
+                       r.result, slot, r.mirror);
     CL_LAUNCH_CHECK();
     return 0;
 }

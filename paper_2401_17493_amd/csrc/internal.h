@@ -189,7 +189,8 @@ int launch_det(const Geo& g, const float* F, double* det, hipStream_t s);
 struct Reducer {
     double* partial = nullptr;   // [max(4 kRedBlocks, one per 256 voxels)]
     double* result = nullptr;    // [8] device
-    double* host = nullptr;      // [8] pinned host
+    double* host = nullptr;      // [8] pinned, mapped host memory: the last fold of each slot
+    double* mirror = nullptr;    // device address of `host`
 };
 constexpr int kRedBlocks = 1024;
 
