@@ -817,6 +817,25 @@ __global__ __launch_bounds__(kThreads) void k_mixed_sources(const __half* __rest
     }
 }
 
+// 8-byte stores of four halves (round to nearest, as __float2half)
+__device__ __forceinline__ uint2 pack_h4(const float o[4]) {
+    const __half2 lo = __floats2half2_rn(o[0], o[1]);
+    const __half2 hi = __floats2half2_rn(o[2], o[3]);
+    uint2 u;
+    u.x = *reinterpret_cast<const unsigned*>(&lo);
+    u.y = *reinterpret_cast<const unsigned*>(&hi);
+    return u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_to_half4(const float4* __restrict__ x,
+                                                       uint2* __restrict__ y, long long n4) {
+    const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n4) return;
+    const float4 v = x[q];
+    const float o[4] = {v.x, v.y, v.z, v.w};
+    y[q] = pack_h4(o);
+}
+
 // out = add + sc h_t sum_j c_j lam^j grad m^j with grad m^j in half; optional
 // <dv, out> per block.
 template <bool DOT>
@@ -967,7 +986,11 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
 int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
 
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
+    if ((n & 3) == 0 && ((reinterpret_cast<uintptr_t>(x) & 15) | (reinterpret_cast<uintptr_t>(y) & 7)) == 0)
+        hipLaunchKernelGGL(k_to_half4, dim3(blocks_for(n / 4)), dim3(kThreads), 0, s,
+                           reinterpret_cast<const float4*>(x), reinterpret_cast<uint2*>(y), n / 4);
+    else
+        hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
     CL_LAUNCH_CHECK();
     return 0;
 }
