@@ -382,6 +382,20 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
     const unsigned col = (unsigned)((b.cb + 4 * j) & g.m3);
     const float inv_e2 = quot_inv(b.e2);
     float4* box4 = reinterpret_cast<float4*>(box);
+    // general grids: the box origin wrapped once; a row index then wraps with
+    // one subtraction (a second only for boxes wider than the grid)
+    int lo1w = 0, lo2w = 0;
+    if constexpr (GEN) {
+        lo1w = wrapn(b.lo1, g.n1);
+        lo2w = wrapn(b.lo2, g.n2);
+    }
+    auto wrap_up = [](int i, int n) {
+        if (i >= n) {
+            i -= n;
+            if (i >= n) i %= n;
+        }
+        return i;
+    };
     for (int r = r0; r < nrows; r += rpp * kSegBatch) {
         float4 tmp[kSegBatch];
         unsigned at[kSegBatch];   // LDS float4 index of each segment
@@ -393,7 +407,7 @@ __device__ __forceinline__ void stage_box(float* box, const float* __restrict__ 
                 const int a1 = quot(row, b.e2, inv_e2, a2);
                 unsigned off;
                 if constexpr (GEN)
-                    off = ((unsigned)(wrapn(b.lo1 + a1, g.n1) * g.n2 + wrapn(b.lo2 + a2, g.n2))
+                    off = ((unsigned)(wrap_up(lo1w + a1, g.n1) * g.n2 + wrap_up(lo2w + a2, g.n2))
                            << g.l3) | col;
                 else
                     off = ((unsigned)((b.lo1 + a1) & g.m1) << g.s1) |
