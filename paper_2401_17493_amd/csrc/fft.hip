@@ -926,11 +926,16 @@ int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, 
     const size_t sh = sizeof(float2) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
     if (dot_with) {
-        CL_TRY(allow_lds(k_c2r_x3<16, 2>, sh));
-        hipLaunchKernelGGL((k_c2r_x3<16, 2>), grid, dim3(kThreads), sh, s, spec, out, dot_with,
-                           g.l3, RB, g.n, g.nspec, w.tw, logT, red->partial);
+        // half-size row blocks: twice the workgroups to cover the extra
+        // operand's loads
+        const int RB2 = row_block(g.n3, rows, 2048);
+        const size_t sh2 = sizeof(float2) * ((1 << logT) + RB2 * (g.n3 / 2));
+        dim3 grid2((unsigned)(rows / RB2), ncomp);
+        CL_TRY(allow_lds(k_c2r_x3<8, 2>, sh2));
+        hipLaunchKernelGGL((k_c2r_x3<8, 2>), grid2, dim3(kThreads), sh2, s, spec, out, dot_with,
+                           g.l3, RB2, g.n, g.nspec, w.tw, logT, red->partial);
         CL_LAUNCH_CHECK();
-        return red_fold_sum(*red, (int)(grid.x * grid.y), 1, 0, slot, s);
+        return red_fold_sum(*red, (int)(grid2.x * grid2.y), 1, 0, slot, s);
     }
     if (add) {
         CL_TRY(allow_lds(k_c2r_x3<16, 1>, sh));
