@@ -900,13 +900,13 @@ constexpr int tile_elems() { return sizeof(C) == 8 ? 4096 : 2048; }
 template <typename C>
 int fwd_x3(const Geo& g, const C* tw, int T, const float* in, C* spec, int ncomp, hipStream_t s) {
     const long long rows = (long long)g.n1 * g.n2;
-    const int RB = row_block(g.n3, rows, tile_elems<C>());
+    const int RB = row_block(g.n3, rows, 2048);
     const int logT = ilog2(T);
     const size_t sh = sizeof(C) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
     if (sizeof(C) == 8) {
-        CL_TRY(allow_lds(k_r2c_x3<16, C>, sh));
-        hipLaunchKernelGGL((k_r2c_x3<16, C>), grid, dim3(kThreads), sh, s, in, spec, g.l3, RB,
+        CL_TRY(allow_lds(k_r2c_x3<8, C>, sh));
+        hipLaunchKernelGGL((k_r2c_x3<8, C>), grid, dim3(kThreads), sh, s, in, spec, g.l3, RB,
                            g.n, g.nspec, tw, logT);
     } else {
         CL_TRY(allow_lds(k_r2c_x3<8, C>, sh));
@@ -937,14 +937,17 @@ int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, 
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)(grid2.x * grid2.y), 1, 0, slot, s);
     }
+    const int RB8 = row_block(g.n3, rows, 2048);
+    const size_t sh8 = sizeof(float2) * ((1 << logT) + RB8 * (g.n3 / 2));
+    dim3 grid8((unsigned)(rows / RB8), ncomp);
     if (add) {
-        CL_TRY(allow_lds(k_c2r_x3<16, 1>, sh));
-        hipLaunchKernelGGL((k_c2r_x3<16, 1>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
-                           RB, g.n, g.nspec, w.tw, logT, nullptr);
+        CL_TRY(allow_lds(k_c2r_x3<8, 1>, sh8));
+        hipLaunchKernelGGL((k_c2r_x3<8, 1>), grid8, dim3(kThreads), sh8, s, spec, out, add, g.l3,
+                           RB8, g.n, g.nspec, w.tw, logT, nullptr);
     } else {
-        CL_TRY(allow_lds(k_c2r_x3<16, 0>, sh));
-        hipLaunchKernelGGL((k_c2r_x3<16, 0>), grid, dim3(kThreads), sh, s, spec, out, nullptr,
-                           g.l3, RB, g.n, g.nspec, w.tw, logT, nullptr);
+        CL_TRY(allow_lds(k_c2r_x3<8, 0>, sh8));
+        hipLaunchKernelGGL((k_c2r_x3<8, 0>), grid8, dim3(kThreads), sh8, s, spec, out, nullptr,
+                           g.l3, RB8, g.n, g.nspec, w.tw, logT, nullptr);
     }
     CL_LAUNCH_CHECK();
     return 0;
