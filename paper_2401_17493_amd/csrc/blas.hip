@@ -91,8 +91,9 @@ __global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __rest
     }
 }
 
-// v~ += kappa s; r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0), with
-// per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
+// (VT: v~ += kappa s;) r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0),
+// with per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
+template <bool VT>
 __global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restrict__ sd,
                                                          const float4* __restrict__ hs,
                                                          float4* __restrict__ vt,
@@ -102,13 +103,17 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restric
     double mx = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
-        const float4 a = sd[i], h = hs[i];
-        float4 v = vt[i], q = r[i];
-        v.x = fmaf(kappa, a.x, v.x); v.y = fmaf(kappa, a.y, v.y);
-        v.z = fmaf(kappa, a.z, v.z); v.w = fmaf(kappa, a.w, v.w);
+        const float4 h = hs[i];
+        float4 q = r[i];
+        if (VT) {
+            const float4 a = sd[i];
+            float4 v = vt[i];
+            v.x = fmaf(kappa, a.x, v.x); v.y = fmaf(kappa, a.y, v.y);
+            v.z = fmaf(kappa, a.z, v.z); v.w = fmaf(kappa, a.w, v.w);
+            vt[i] = v;
+        }
         q.x = fmaf(-kappa, h.x, q.x); q.y = fmaf(-kappa, h.y, q.y);
         q.z = fmaf(-kappa, h.z, q.z); q.w = fmaf(-kappa, h.w, q.w);
-        vt[i] = v;
         r[i] = q;
         mx = fmax(mx, (double)fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
         const double sum = (double)q.x + (double)q.y + (double)q.z + (double)q.w;
@@ -170,36 +175,48 @@ __global__ __launch_bounds__(kThreads) void k_xpby(const float* __restrict__ x,
     if (i < n) y[i] = fmaf(b, y[i], x[i]);
 }
 
-// y = x + b y with the block's max |y| -> partial[block] (n4 float4 groups,
-// then the tail of n - 4 n4 floats)
-__global__ __launch_bounds__(kThreads) void k_xpby_absmax(const float4* __restrict__ x,
-                                                          float4* __restrict__ y, float b,
-                                                          long long n4, long long n,
-                                                          double* __restrict__ partial) {
+// PCG direction update with the previous direction s: v~ += kappa s, then
+// s = z + mu s (n4 float4 groups, then the tail of n - 4 n4 floats); MAX: the
+// block's max |s| -> partial[block] (the scale of the mixed matvec's float16
+// sources).
+template <bool MAX>
+__global__ __launch_bounds__(kThreads) void k_pcg_direction(const float4* __restrict__ z,
+                                                            float4* __restrict__ sd, float mu,
+                                                            float4* __restrict__ vt, float kappa,
+                                                            long long n4, long long n,
+                                                            double* __restrict__ partial) {
     __shared__ double sh[kThreads / kWave];
     double mx = identity<OP_MAX>();
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride) {
-        const float4 a = x[i];
-        float4 v = y[i];
-        v.x = fmaf(b, v.x, a.x);
-        v.y = fmaf(b, v.y, a.y);
-        v.z = fmaf(b, v.z, a.z);
-        v.w = fmaf(b, v.w, a.w);
-        y[i] = v;
-        mx = fmax(mx, fmax(fmax(fabs((double)v.x), fabs((double)v.y)),
-                           fmax(fabs((double)v.z), fabs((double)v.w))));
+        const float4 a = z[i];
+        float4 v = sd[i], t = vt[i];
+        t.x = fmaf(kappa, v.x, t.x); t.y = fmaf(kappa, v.y, t.y);
+        t.z = fmaf(kappa, v.z, t.z); t.w = fmaf(kappa, v.w, t.w);
+        v.x = fmaf(mu, v.x, a.x);
+        v.y = fmaf(mu, v.y, a.y);
+        v.z = fmaf(mu, v.z, a.z);
+        v.w = fmaf(mu, v.w, a.w);
+        vt[i] = t;
+        sd[i] = v;
+        if (MAX)
+            mx = fmax(mx, fmax(fmax(fabs((double)v.x), fabs((double)v.y)),
+                               fmax(fabs((double)v.z), fabs((double)v.w))));
     }
-    const float* xs = reinterpret_cast<const float*>(x);
-    float* ys = reinterpret_cast<float*>(y);
+    const float* zs = reinterpret_cast<const float*>(z);
+    float* ss = reinterpret_cast<float*>(sd);
+    float* ts = reinterpret_cast<float*>(vt);
     for (long long i = 4 * n4 + (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += stride) {
-        const float v = fmaf(b, ys[i], xs[i]);
-        ys[i] = v;
-        mx = fmax(mx, fabs((double)v));
+        ts[i] = fmaf(kappa, ss[i], ts[i]);
+        const float v = fmaf(mu, ss[i], zs[i]);
+        ss[i] = v;
+        if (MAX) mx = fmax(mx, fabs((double)v));
     }
-    mx = block_reduce<OP_MAX>(mx, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = mx;
+    if (MAX) {
+        mx = block_reduce<OP_MAX>(mx, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = mx;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ x,
@@ -372,10 +389,16 @@ int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, flo
                float kappa, long long n, int smax, int ssum, hipStream_t st) {
     const long long n4 = n / 4;
     unsigned nb = red_blocks(3 * n4);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kThreads), 0, st,
-                       reinterpret_cast<const float4*>(s_dir), reinterpret_cast<const float4*>(hs),
-                       reinterpret_cast<float4*>(vt), reinterpret_cast<float4*>(r), kappa, n4,
-                       red.partial);
+    if (vt)
+        hipLaunchKernelGGL(k_pcg_update<true>, dim3(nb), dim3(kThreads), 0, st,
+                           reinterpret_cast<const float4*>(s_dir),
+                           reinterpret_cast<const float4*>(hs), reinterpret_cast<float4*>(vt),
+                           reinterpret_cast<float4*>(r), kappa, n4, red.partial);
+    else
+        hipLaunchKernelGGL(k_pcg_update<false>, dim3(nb), dim3(kThreads), 0, st,
+                           reinterpret_cast<const float4*>(s_dir),
+                           reinterpret_cast<const float4*>(hs), nullptr,
+                           reinterpret_cast<float4*>(r), kappa, n4, red.partial);
     CL_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, st, red.partial, (int)nb, 4, 0,
                        red.result, smax, red.mirror);
@@ -416,19 +439,26 @@ int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
     return 0;
 }
 
-int launch_xpby_absmax(Reducer& r, const float* x, float* y, float b, long long n, int slot,
-                       hipStream_t s) {
-    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) {
-        set_error("xpby_absmax needs 16-byte aligned vectors");
+int launch_pcg_direction(Reducer* r, const float* z, float* sd, float mu, float* vt,
+                         float kappa, long long n, int slot, hipStream_t s) {
+    if ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(sd) |
+         reinterpret_cast<uintptr_t>(vt)) & 15u) {
+        set_error("pcg direction update needs 16-byte aligned vectors");
         return CLAIRE_EINVAL;
     }
     const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_xpby_absmax, dim3(nb), dim3(kThreads), 0, s,
-                       reinterpret_cast<const float4*>(x), reinterpret_cast<float4*>(y), b, n / 4,
-                       n, r.partial);
-    CL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r.partial, (int)nb, 1, 0,
-                       r.result, slot, r.mirror);
+    if (r) {
+        hipLaunchKernelGGL(k_pcg_direction<true>, dim3(nb), dim3(kThreads), 0, s,
+                           reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
+                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, r->partial);
+        CL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r->partial, (int)nb,
+                           1, 0, r->result, slot, r->mirror);
+    } else {
+        hipLaunchKernelGGL(k_pcg_direction<false>, dim3(nb), dim3(kThreads), 0, s,
+                           reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
+                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, nullptr);
+    }
     CL_LAUNCH_CHECK();
     return 0;
 }

@@ -529,25 +529,30 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
             break;
         }
         const double kappa = rz / shs;
-        // v~ += kappa s, r -= kappa Hs, with max|r| -> slot 1 and the residual's
-        // component sums -> slots 3..5
-        CL_TRY(pcg_update(c->red, c->sd, c->hs, c->vt, c->r, (float)kappa, n, 1, 3, s));
-        if (res.its == limit) break;
+        // r -= kappa Hs, with max|r| -> slot 1 and the residual's component
+        // sums -> slots 3..5; v~ += kappa s follows in the direction update,
+        // which reads s anyway (or directly, when the iteration ends here)
+        CL_TRY(pcg_update(c->red, c->sd, c->hs, nullptr, c->r, (float)kappa, n, 1, 3, s));
+        if (res.its == limit) {
+            CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
+            break;
+        }
         // preconditioned residual and <z, r>: one host round trip with the above
         CL_TRY(precond(2));   // z and <z, r> -> slot 2
         CL_TRY(red_fetch(c->red, s));
-        if (!fixed && c->red.host[1] <= tol) { converged = true; break; }
+        if (!fixed && c->red.host[1] <= tol) {
+            converged = true;
+            CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
+            break;
+        }
         const double rz_new = c->red.host[2];
         const double mu = rz_new / rz;
         for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
-        if (c->precision == 1) {
-            // the mixed matvec scales its float16 sources by max|s|: reduce
-            // it in the same pass
-            CL_TRY(launch_xpby_absmax(c->red, c->z, c->sd, (float)mu, n3, kScaleSlot, s));
-            scale_ready = true;
-        } else {
-            CL_TRY(launch_xpby(c->z, c->sd, (float)mu, n3, s));
-        }
+        // v~ += kappa s, s = z + mu s; the mixed matvec scales its float16
+        // sources by max|s|, reduced in the same pass
+        CL_TRY(launch_pcg_direction(c->precision == 1 ? &c->red : nullptr, c->z, c->sd,
+                                    (float)mu, c->vt, (float)kappa, n3, kScaleSlot, s));
+        scale_ready = c->precision == 1;
         if (!two) CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }

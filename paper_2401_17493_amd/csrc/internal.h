@@ -220,9 +220,9 @@ int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
 int red_fetch(Reducer& r, hipStream_t s);
 // fold nb partial sums (r.partial[i*stride + off]) into r.result[slot]
 int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s);
-// PCG update v~ += kappa s, r -= kappa Hs on [3][n] vectors, fused with the
-// reductions of the new residual: max |r| -> slot smax, sum of each component
-// of r -> slots ssum..ssum+2
+// PCG update (v~ += kappa s when vt is given,) r -= kappa Hs on [3][n]
+// vectors, fused with the reductions of the new residual: max |r| -> slot
+// smax, sum of each component of r -> slots ssum..ssum+2
 int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
                float kappa, long long n, int smax, int ssum, hipStream_t st);
 
@@ -262,9 +262,10 @@ int twolevel_apply(TwoLevel& T, const Geo& gf, SpectralWork& swf, const float* r
 int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s);
 // y = x + b*y
 int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s);
-// y = x + b*y and max |y| -> r.result[slot] (x, y 16-byte aligned)
-int launch_xpby_absmax(Reducer& r, const float* x, float* y, float b, long long n, int slot,
-                       hipStream_t s);
+// PCG direction update with the previous direction: vt += kappa sd, then
+// sd = z + mu sd; with r, max |sd| -> r->result[slot] (16-byte aligned vectors)
+int launch_pcg_direction(Reducer* r, const float* z, float* sd, float mu, float* vt,
+                         float kappa, long long n, int slot, hipStream_t s);
 // y = x + b*z
 int launch_lincomb(const float* x, const float* z, float* y, float b, long long n,
                    hipStream_t s);
