@@ -920,34 +920,28 @@ int fwd_x3(const Geo& g, const C* tw, int T, const float* in, C* spec, int ncomp
 int inv_x3(const Geo& g, const SpectralWork& w, const float2* spec, float* out, const float* add,
            int ncomp, hipStream_t s, const float* dot_with = nullptr, Reducer* red = nullptr,
            int slot = 0) {
+    // half-size row blocks (2048 complex values): twice the workgroups in
+    // flight, which covers the loads of the addend or dot operand
     const long long rows = (long long)g.n1 * g.n2;
-    const int RB = row_block(g.n3, rows, 4096);
+    const int RB = row_block(g.n3, rows, 2048);
     const int logT = ilog2(w.tw_n);
     const size_t sh = sizeof(float2) * ((1 << logT) + RB * (g.n3 / 2));
     dim3 grid((unsigned)(rows / RB), ncomp);
     if (dot_with) {
-        // half-size row blocks: twice the workgroups to cover the extra
-        // operand's loads
-        const int RB2 = row_block(g.n3, rows, 2048);
-        const size_t sh2 = sizeof(float2) * ((1 << logT) + RB2 * (g.n3 / 2));
-        dim3 grid2((unsigned)(rows / RB2), ncomp);
-        CL_TRY(allow_lds(k_c2r_x3<8, 2>, sh2));
-        hipLaunchKernelGGL((k_c2r_x3<8, 2>), grid2, dim3(kThreads), sh2, s, spec, out, dot_with,
-                           g.l3, RB2, g.n, g.nspec, w.tw, logT, red->partial);
+        CL_TRY(allow_lds(k_c2r_x3<8, 2>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<8, 2>), grid, dim3(kThreads), sh, s, spec, out, dot_with,
+                           g.l3, RB, g.n, g.nspec, w.tw, logT, red->partial);
         CL_LAUNCH_CHECK();
-        return red_fold_sum(*red, (int)(grid2.x * grid2.y), 1, 0, slot, s);
+        return red_fold_sum(*red, (int)(grid.x * grid.y), 1, 0, slot, s);
     }
-    const int RB8 = row_block(g.n3, rows, 2048);
-    const size_t sh8 = sizeof(float2) * ((1 << logT) + RB8 * (g.n3 / 2));
-    dim3 grid8((unsigned)(rows / RB8), ncomp);
     if (add) {
-        CL_TRY(allow_lds(k_c2r_x3<8, 1>, sh8));
-        hipLaunchKernelGGL((k_c2r_x3<8, 1>), grid8, dim3(kThreads), sh8, s, spec, out, add, g.l3,
-                           RB8, g.n, g.nspec, w.tw, logT, nullptr);
+        CL_TRY(allow_lds(k_c2r_x3<8, 1>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<8, 1>), grid, dim3(kThreads), sh, s, spec, out, add, g.l3,
+                           RB, g.n, g.nspec, w.tw, logT, nullptr);
     } else {
-        CL_TRY(allow_lds(k_c2r_x3<8, 0>, sh8));
-        hipLaunchKernelGGL((k_c2r_x3<8, 0>), grid8, dim3(kThreads), sh8, s, spec, out, nullptr,
-                           g.l3, RB8, g.n, g.nspec, w.tw, logT, nullptr);
+        CL_TRY(allow_lds(k_c2r_x3<8, 0>, sh));
+        hipLaunchKernelGGL((k_c2r_x3<8, 0>), grid, dim3(kThreads), sh, s, spec, out, nullptr,
+                           g.l3, RB, g.n, g.nspec, w.tw, logT, nullptr);
     }
     CL_LAUNCH_CHECK();
     return 0;
