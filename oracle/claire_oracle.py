@@ -700,7 +700,8 @@ class SolveStats:
 
 def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
              max_gn=50, max_pcg=100, fixed_pcg=0, forcing="superlinear",
-             c1=1e-4, max_ls=16, deriv="spectral", precond="reg", beta=0.0):
+             c1=1e-4, max_ls=16, deriv="spectral", precond="reg", beta=0.0,
+             callback=None):
     """Inexact Gauss--Newton--Krylov with Armijo line search (Algorithm 1),
     run once per regularisation weight in ``alphas`` (parameter continuation,
     Section 2.6: each level starts from the previous level's velocity and
@@ -714,6 +715,12 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
     and the Hessian carry the projection of the data term; the Armijo test
     uses the objective with the divergence penalty and its directional
     derivative <grad J, v~>. Not combined with the two-level preconditioner.
+
+    ``stats.history`` holds one record per visited iterate (level, k, J,
+    ||g||_inf) and, for each accepted step, the PCG matvec count, the PCG
+    residual history ||r_l||_inf, the accepted step length gamma and the
+    number of line-search trials. ``callback(level, k, v, st)``, if given, is
+    called after every accepted step with the new iterate and its state.
 
     Parity of the whole solve is unpinned beyond its invariants (monotone J,
     stopping rule, det grad y > 0): the tests compare it with the HIP path.
@@ -746,7 +753,7 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
                 M = TwoLevelPreconditioner(st, inner_rtol=0.1 * eta)
             else:
                 M = lambda r: precondition(grid, r, alpha, p)   # noqa: E731
-            vt, its, _, hit_max = pcg(lambda s: hessian_matvec(st, s), M,
+            vt, its, res_hist, hit_max = pcg(lambda s: hessian_matvec(st, s), M,
                                       st.g, fixed_iters=fixed_pcg,
                                       max_iters=max_pcg, forcing=forcing)
             if precond == "twolevel":
@@ -758,15 +765,20 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
             slope = grid.inner(st.grad_J, vt)
             gamma = 1.0
             accepted = False
+            trials = 0
             for _ in range(max_ls):
                 v_trial = v + gamma * vt
                 j_trial = objective(grid, m0, m1, v_trial, alpha, nt, p, beta)
                 stats.ls_trials += 1
                 stats.pde_solves += 1
+                trials += 1
                 if j_trial <= st.J + c1 * gamma * slope:
                     accepted = True
                     break
                 gamma *= 0.5
+            stats.history[-1].update(pcg_its=its, pcg_res=list(res_hist), slope=slope,
+                                     gamma=gamma if accepted else 0.0, ls=trials,
+                                     neg_curv=bool(pcg.neg_curv))
             if not accepted:
                 stats.warnings.append("linesearch")
                 break
@@ -775,6 +787,8 @@ def gn_solve(grid, m0, m1, nt, p, alphas, *, v0=None, gtol=5e-2, gabs=1e-6,
             stats.pde_solves += 2
             k += 1
             stats.gn_iters += 1
+            if callback is not None:
+                callback(li, k, v, st)
         stats.rel_grad = float(np.abs(st.g).max()) / g0 if g0 > 0 else 0.0
     stats.J = st.J
     stats.rel_mismatch = float(np.sqrt(np.sum((st.m[-1] - m1) ** 2)) / mismatch0) \
