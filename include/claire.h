@@ -315,6 +315,22 @@ int claire_solve(const float *m0, const float *m1, const int nx[3], double alpha
                  int nt, const claire_opts *opts, float *v_inout,
                  claire_stats *stats, void *stream);
 
+/* ------------------------------------------- allocation-free transport
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as claire_transport (identical kernels, bit-identical output), with
+ * every intermediate buffer in a fixed device array that the library holds
+ * per GPU until the process ends (7 float32 fields of the largest grid plus
+ * a brick table: about 57 MiB). The call makes no device allocation.
+ * Limit: n1 n2 n3 <= claire_transport_noalloc_max_voxels() (2^21, e.g.
+ * 128^3); larger grids return CLAIRE_EINVAL with nothing launched. m1_out
+ * must not alias m0. All calls on one GPU share its array and keep the last
+ * call's contents: calls that overlap in time on one GPU (several streams or
+ * threads) race, and the caller must serialise them. Synchronises stream. */
+int claire_transport_noalloc(const float *m0, const float *v, const int nx[3], int nt,
+                             float *m1_out, void *stream);
+long long claire_transport_noalloc_max_voxels(void);
+
 #ifdef __cplusplus
 }
 #endif

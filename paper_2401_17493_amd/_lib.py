@@ -89,6 +89,9 @@ SIGNATURES = {
     "claire_ctx_get_field": (c_int, [c_void_p, c_int, c_int, c_void_p]),
     "claire_ctx_time_kernel": (c_int, [c_void_p, c_int, c_int, c_double_p]),
     "claire_transport": (c_int, [c_void_p, c_void_p, c_int_p, c_int, c_void_p, c_void_p]),
+    "claire_transport_noalloc": (c_int, [c_void_p, c_void_p, c_int_p, c_int, c_void_p,
+                                         c_void_p]),
+    "claire_transport_noalloc_max_voxels": (ctypes.c_longlong, []),
     "claire_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_int_p, c_double, c_int, c_int,
                                 c_void_p, c_double_p, c_void_p]),
     "claire_hessian_matvec": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int_p, c_double,

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libclaire_gfx950.so")
 SOURCES = ["fft.hip", "sl.hip", "blas.hip", "claire_api.hip", "net.hip", "deriv.hip",
-           "precond.hip"]
+           "precond.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled for all device code.

@@ -244,6 +244,19 @@ def transport(m0: torch.Tensor, v: torch.Tensor, nt: int) -> torch.Tensor:
     return out
 
 
+def transport_noalloc(m0: torch.Tensor, v: torch.Tensor, nt: int, out: torch.Tensor) -> torch.Tensor:
+    """claire_transport_noalloc: the caller provides the output; the library
+    allocates nothing (its scratch is a fixed per-GPU device array)."""
+    n = tuple(m0.shape)
+    _check(L.load().claire_transport_noalloc(_ptr(m0, n, "m0"), _ptr(v, (3,) + n, "v"), _nx(n),
+                                             int(nt), _ptr(out, n, "m1_out"), _stream()))
+    return out
+
+
+def transport_noalloc_max_voxels() -> int:
+    return int(L.load().claire_transport_noalloc_max_voxels())
+
+
 def gradient(m0, m1, v, alpha: float, nt: int, reg_order: int = 1):
     n = tuple(m0.shape)
     g = torch.empty((3,) + n, dtype=torch.float32, device="cuda")
