@@ -17,10 +17,18 @@ forward pass, prolongation), the extra state/adjoint solve at v = 0 that
 fixes the stopping test at ||g||_inf <= gtol ||g(0)||_inf, and the solve.
 The cold mixed and float32 solves (from v = 0, same tolerance) are timed too
 and reported beside it, with the differences between the solutions. Without
-trained weights (--warmstart none) ``value`` is the cold mixed solve. The line
-also carries the Hessian matvec throughput, the HBM roofline of the dominant
-kernel (average launch duration measured here with HIP events) and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+trained weights (--warmstart none) ``value`` is the cold mixed solve.
+
+The inputs are the FP64 oracle's problem: m1 is the oracle's transport of the
+clean phantom (written by tests/golden/make_inputs.py). Each solve is reported
+with its status and, when the oracle's record of the same solve exists
+(tests/golden/make_solve_golden.py), its relative errors against it in v, J
+and the final gradient norm. A solve that ends with a warning or above the
+gradient tolerance gets no time-to-solution (and the run exits with status
+3). The line also carries the Hessian matvec throughput and its fraction of
+the HBM roofline, the roofline of the dominant kernel (average launch
+duration measured here with HIP events) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -80,45 +88,147 @@ def load_traffic(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
-def make_inputs(name, torch, C):
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def load_inputs(name):
+    """m0 and m1 (float32 host arrays) of a workload, as the FP64 oracle builds
+    them (m1 = oracle transport of the clean phantom by v*, plus noise), from
+    the file tests/golden/make_inputs.py writes; the script runs first when
+    the file is missing. Also returns v* (seeded generator, rounded to
+    float32) and the SHA-256 of m1."""
+    import subprocess
+
     import numpy as np
 
-    from synthetic import (WORKLOADS, bandlimited_velocity, ellipsoid_phantom, noise)
+    from synthetic import WORKLOADS, bandlimited_velocity
     w = WORKLOADS[name]
-    n, seed = w["n"], w["seed"]
-    clean = ellipsoid_phantom(n, seed)
-    vstar = bandlimited_velocity(n, seed + 1000, w["kmax"], w["vmax"])
-    m0 = clean + noise(n, seed + 2000, w["noise"])
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa: E731
-    # the reference image: clean template transported by v* (this library's
-    # transport), plus independent noise
-    m1 = C.transport(dev(clean), dev(vstar), w["nt"]) + dev(noise(n, seed + 3000, w["noise"]))
-    torch.cuda.synchronize()
-    return w, dev(m0), m1.contiguous(), dev(vstar), (clean, vstar)
+    n = tuple(w["n"])
+    path = os.path.join(GOLDEN_DIR, "inputs", "%s.npz" % name)
+    if not os.path.exists(path):
+        t0 = time.time()
+        subprocess.run([sys.executable, os.path.join(GOLDEN_DIR, "make_inputs.py"), name,
+                        "--out", path], check=True)
+        print("inputs of %s generated in %.1f s" % (name, time.time() - t0),
+              file=sys.stderr, flush=True)
+    with np.load(path) as z:
+        m0, m1, sha = z["m0"], z["m1"], str(z["m1_sha256"])
+    vstar = bandlimited_velocity(n, w["seed"] + 1000, min(w["kmax"], n[0] // 2 - 1), w["vmax"])
+    return w, m0, m1, vstar.astype(np.float32), sha
 
 
-def cpu_baseline(name, host_inputs):
-    """FP64 oracle on the host: one GN Hessian matvec at v = v*/2 (untimed
-    setup first). Returns the cpu_baseline record."""
+def load_golden(name, w, beta):
+    """The FP64 oracle's record of the same solve (tests/golden/make_solve_golden.py)."""
+    tag = "ni" if beta > 0 else "h%d" % w["reg_order"]
+    path = os.path.join(GOLDEN_DIR, "%s_%s_solve.json" % (name, tag))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def vs_oracle(v, stats, trace, golden, m1_sha):
+    """Relative errors of a GPU solve against the FP64 oracle's solve of the
+    same problem: v at the golden's sample voxels (max-norm), the final
+    objective and the final gradient norm (the Newton residual), and the
+    iteration counts of both."""
+    import numpy as np
+    if golden is None:
+        return None
+    if golden.get("m1_sha256") != m1_sha:
+        return {"error": "inputs differ from the oracle record's (m1 digest)"}
+    idx = np.array(golden["sample_idx"])
+    got = v[:, idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy().T
+    ref = np.array(golden["v_samples"])
+    g_gpu = trace[-1]["gnorm"] if trace else float("nan")
+    g_ora = golden["history"][-1]["gnorm"]
+    return {"v_rel_maxnorm_samples": float(np.abs(got - ref).max() / np.abs(ref).max()),
+            "J_rel": abs(stats["J"] - golden["J"]) / abs(golden["J"]),
+            "residual_rel": abs(g_gpu - g_ora) / g_ora,
+            "rel_grad": [stats["rel_grad"], golden["rel_grad"]],
+            "gn_iters": [stats["gn_iters"], golden["gn_iters"]],
+            "matvecs": [stats["matvecs"], golden["matvecs"]],
+            "samples": len(ref),
+            "oracle_seconds": round(golden["seconds"], 1),
+            "oracle_host": golden.get("host")}
+
+
+def host_info():
+    import oracle as O
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "threads": O.WORKERS}
+
+
+def median_time(fn, runs=3):
+    """Median wall time of `runs` calls after one untimed warm-up call."""
+    fn()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline(name, m0, m1, vstar):
+    """The FP64 oracle on this host: median of 3 timed runs after a warm-up of
+    one GN Hessian matvec at v = v*/2 (setup untimed), of its kernels (one
+    spectral gradient = 1 R2C + 3 C2R FFTs, one tricubic gather of a field,
+    the RK2 backtrace of one direction) and of the 32^3 one-step solve (10 PCG
+    matvecs); the oracle's time-to-solution of the 128^3 and 256^3 solves
+    quoted from its golden records (taken on the host named there)."""
     import numpy as np
 
     import oracle as O
-    from synthetic import WORKLOADS, bandlimited_velocity, noise
+    from synthetic import WORKLOADS, bandlimited_velocity, gaussian_blobs
     w = WORKLOADS[name]
-    n, seed, nt = w["n"], w["seed"], w["nt"]
-    clean, vstar = host_inputs
+    n, seed, nt = tuple(w["n"]), w["seed"], w["nt"]
     grid = O.Grid(n)
-    m0 = clean + noise(n, seed + 2000, w["noise"])
-    m1 = O.transport(grid, clean, vstar, nt) + noise(n, seed + 3000, w["noise"])
-    st = O.setup_velocity(grid, m0, m1, 0.5 * vstar, w["alphas"][-1], nt, w["reg_order"])
-    vt = bandlimited_velocity(n, seed + 4000, w["kmax"], 1.0)
-    t0 = time.perf_counter()
-    O.hessian_matvec(st, vt)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "Hessian matvecs/s", "cores": O.WORKERS,
-            "kind": "oracle", "seconds_per_matvec": dt,
-            "sample": "1 FP64 GN Hessian matvec at %dx%dx%d, nt=%d, v=v*/2, after an "
-                      "untimed setup (numpy/scipy.fft + C/OpenMP tricubic)" % (n + (nt,))}
+    m0 = m0.astype(np.float64)
+    m1 = m1.astype(np.float64)
+    v = 0.5 * vstar.astype(np.float64)
+    st = O.setup_velocity(grid, m0, m1, v, w["alphas"][-1], nt, w["reg_order"])
+    vt = bandlimited_velocity(n, seed + 4000, min(w["kmax"], n[0] // 2 - 1), 1.0)
+    t_mv = median_time(lambda: O.hessian_matvec(st, vt))
+    kernels = {
+        "spectral_gradient_s": median_time(lambda: O.gradient(grid, st.m[-1])),
+        "tricubic_gather_s": median_time(lambda: O.interpolate(st.m[-1], st.d_plus)),
+        "backtrace_s": median_time(lambda: O.departure_displacement(grid, v, nt, +1)),
+    }
+    del st
+    # config 1: 32^3 blobs, one GN step with exactly 10 PCG matvecs from v = 0
+    b = WORKLOADS["blobs32"]
+    g32 = O.Grid(b["n"])
+    b0 = gaussian_blobs(b["n"], b["seed"]).astype(np.float32).astype(np.float64)
+    bv = bandlimited_velocity(b["n"], b["seed"] + 1000, b["kmax"], b["vmax"])
+    b1 = O.transport(g32, b0, bv.astype(np.float32).astype(np.float64), b["nt"])
+    t_c1 = median_time(lambda: O.gn_solve(g32, b0, b1, b["nt"], b["reg_order"],
+                                          list(b["alphas"]), max_gn=1, fixed_pcg=10))
+    tts = {"blobs32_one_gn_step_10_matvecs_s": round(t_c1, 3)}
+    for wl, tag in (("ellipsoids128", "h2"), ("ellipsoids256", "h1")):
+        path = os.path.join(GOLDEN_DIR, "%s_%s_solve.json" % (wl, tag))
+        if os.path.exists(path):
+            with open(path) as fh:
+                gd = json.load(fh)
+            tts["%s_solve_s" % wl] = {"seconds": round(gd["seconds"], 1),
+                                      "gn_iters": gd["gn_iters"], "matvecs": gd["matvecs"],
+                                      "host": gd.get("host"), "source": "golden record"}
+    return {"value": 1.0 / t_mv, "unit": "Hessian matvecs/s", "cores": O.WORKERS,
+            "kind": "oracle", "seconds_per_matvec": t_mv,
+            "host": host_info(),
+            "kernels_s": {k: round(v_, 4) for k, v_ in kernels.items()},
+            "time_to_solution": tts,
+            "sample": "median of 3 FP64 GN Hessian matvecs at %dx%dx%d, nt=%d, v=v*/2, after "
+                      "a warm-up and an untimed setup (numpy/scipy.fft + C/OpenMP tricubic); "
+                      "kernels and the 32^3 step the same way" % (n + (nt,))}
 
 
 def main():
@@ -157,7 +267,11 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    w, m0, m1, vstar, host_inputs = make_inputs(args.workload, torch, C)
+    w, m0_h, m1_h, vstar_h, m1_sha = load_inputs(args.workload)
+    golden = load_golden(args.workload, w, args.beta) if args.precond == "reg" else None
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    m0, m1, vstar = dev(m0_h), dev(m1_h), dev(vstar_h)
+    torch.cuda.synchronize()
     n, nt = w["n"], w["nt"]
     alpha = w["alphas"][-1]
     levels = list(w["alphas"]) if len(w["alphas"]) > 1 else None
@@ -210,10 +324,12 @@ def main():
             v, stats = one_solve()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-            print("step (%s): solve %.3f s, %d GN iterations, %d matvecs, %d inner" %
-                  (label, times[-1], stats["gn_iters"], stats["matvecs"], stats["inner_iters"]),
-                  file=sys.stderr, flush=True)
-        rec = dict(tts=sum(times) / len(times), stats=stats, v=v, prec=prec)
+            print("step (%s): solve %.3f s, %d GN iterations, %d matvecs, %d inner, status %d" %
+                  (label, times[-1], stats["gn_iters"], stats["matvecs"], stats["inner_iters"],
+                   stats["status"]), file=sys.stderr, flush=True)
+        rec = dict(tts=sum(times) / len(times), stats=stats, v=v, prec=prec,
+                   trace=ctx.solve_trace())
+        rec["vs_oracle"] = vs_oracle(v, stats, rec["trace"], golden, m1_sha)
         if not warm:
             # Hessian matvec throughput at the solution, HIP events on the context stream
             ctx.set_precision(prec)
@@ -251,20 +367,42 @@ def main():
           file=sys.stderr, flush=True)
     ctx.close()
 
+    def converged(r):
+        # a time-to-solution is only reported for a solve that ended without
+        # a warning and met the gradient tolerance
+        st = r["stats"]
+        return st["status"] == 0 and st["rel_grad"] <= opts["gtol"]
+
+    def matvec_roofline(r):
+        # algorithmic fields per matvec: 29 + 21 nt float32 (incremental state
+        # 7 + 11 nt, adjoint 6 nt, assembly 4 (nt + 1) + 3, alpha L v~ 15);
+        # mixed: float16 grad m^j and sources f^j count half a field each:
+        # sources pass 2 (nt + 1) + 4, state steps 5.5 nt, adjoint 6 nt,
+        # assembly 2.5 (nt + 1) + 3, alpha L v~ 15 -> 16 nt + 26.5
+        fields = 29 + 21 * nt if r["prec"] == 0 else 16 * nt + 26.5
+        nbytes = 4.0 * fields * n[0] * n[1] * n[2]
+        gbs = nbytes / (r["ms_matvec"] * 1e-3) / 1e9
+        return {"fields": fields, "algorithmic_bytes": nbytes, "achieved": round(gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
     def solve_rec(r):
         st = r["stats"]
-        rec = {k: st[k] for k in ("gn_iters", "matvecs", "inner_iters", "pde_solves",
-                                  "linesearch_trials",
+        rec = {k: st[k] for k in ("status", "warning", "gn_iters", "matvecs", "inner_iters",
+                                  "pde_solves", "linesearch_trials",
                                   "rel_grad", "rel_mismatch", "J0", "J", "det_min", "det_max",
                                   "det_nonpositive")}
-        rec.update(time_to_solution_s=round(r["tts"], 4),
+        rec.update(converged=converged(r),
+                   time_to_solution_s=round(r["tts"], 4) if converged(r) else None,
                    hessian_matvecs_per_s=round(1000.0 / r["ms_matvec"], 2),
-                   ms_per_matvec=round(r["ms_matvec"], 4))
+                   ms_per_matvec=round(r["ms_matvec"], 4),
+                   matvec_roofline=matvec_roofline(r),
+                   vs_oracle=r["vs_oracle"])
         return rec
 
+    ok = converged(head)
     out = {
         "metric": METRIC,
-        "value": round(tts, 4),
+        "value": round(tts, 4) if ok else None,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -273,7 +411,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if head["prec"] == 0 else "f32 arithmetic, f16 storage (mixed)",
         "data": "synthetic (seeded nested-ellipsoid phantom, band-limited v*)",
         "config": {"workload": args.workload, "grid": list(n), "nt": nt,
                    "alpha": alpha if not levels else levels,
@@ -292,7 +430,13 @@ def main():
                    "parallelism": "single GPU"},
         "hessian_matvecs_per_s": round(1000.0 / ms_matvec, 2),
         "ms_per_matvec": round(ms_matvec, 4),
+        "matvec_roofline": matvec_roofline(head),
         "solve": solve_rec(head),
+        "inputs": {"m1": "FP64 oracle transport of the clean phantom by v* (+ noise), "
+                         "float32", "m1_sha256": m1_sha[:16],
+                   "oracle_record": None if golden is None else
+                   "tests/golden/%s_%s_solve.json" % (args.workload, "ni" if args.beta > 0
+                                                      else "h%d" % w["reg_order"])},
         "roofline": {"kernel": args.roofline_kernel, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -316,9 +460,15 @@ def main():
         out["fp32_solve"] = solve_rec(runs["fp32"])
         if "mixed" in runs:
             out["mixed_vs_fp32"] = compare(runs["mixed"], runs["fp32"])
+    if not ok:
+        out["error"] = ("the headline solve did not converge (status %d, rel_grad %.3g): no "
+                        "time-to-solution is reported" % (head["stats"]["status"],
+                                                          head["stats"]["rel_grad"]))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, host_inputs)
+        out["cpu_baseline"] = cpu_baseline(args.workload, m0_h, m1_h, vstar_h)
     print(json.dumps(out), flush=True)
+    if not ok:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -228,6 +228,21 @@ int claire_ctx_precond_twolevel(claire_ctx *ctx, const float *r, float *z, doubl
 int claire_ctx_solve(claire_ctx *ctx, const claire_opts *opts, float *v_inout,
                      claire_stats *stats);
 
+/* Trace of the last claire_ctx_solve on this context (Algorithm 1 with
+ * Algorithm 2), for comparing a solve step by step. iters (host, may be
+ * NULL) receives up to max_iters records of 8 doubles, one per visited
+ * iterate in order: continuation level, Gauss--Newton index k, J, ||g||_inf,
+ * PCG matvecs of the step taken from it, accepted step length (0 if the line
+ * search failed or no step was taken), line-search trials, and the number of
+ * residual values the step's PCG recorded. pcg_res (host, may be NULL)
+ * receives up to max_res values: each step's PCG residual history
+ * ||r_l||_inf from r_0 = -g through every residual update (matvecs + 1
+ * values, or fewer when PCG stopped on nonpositive curvature), concatenated
+ * in step order. counts (host int[2]) receives the numbers of records and residual
+ * values available. Copies min(count, capacity) of each. */
+int claire_ctx_solve_trace(claire_ctx *ctx, double *iters, int max_iters, double *pcg_res,
+                           int max_res, int counts[2]);
+
 /* Deformation gradient check (appendix, eq. e:def-grad): transport F with
  * d_t F + (v.grad) F = (grad v) F, F(0) = I, for the velocity of the last
  * set_velocity, and evaluate det F(1) in float64. det_out ([n] float64,

@@ -84,6 +84,7 @@ SIGNATURES = {
     "claire_ctx_solve": (c_int, [c_void_p, ctypes.POINTER(ClaireOpts), c_void_p,
                                  ctypes.POINTER(ClaireStats)]),
     "claire_ctx_detdefgrad": (c_int, [c_void_p, c_void_p, c_double_p]),
+    "claire_ctx_solve_trace": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_int_p]),
     "claire_ctx_spectral": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "claire_ctx_interpolate": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "claire_ctx_get_field": (c_int, [c_void_p, c_int, c_int, c_void_p]),

@@ -191,6 +191,27 @@ class Context:
         d["warning"] = WARNINGS.get(rc)
         return v, d
 
+    def solve_trace(self):
+        """Per-iterate records and PCG residual histories of the last solve."""
+        counts = (ctypes.c_int * 2)()
+        _check(self.lib.claire_ctx_solve_trace(self._h, None, 0, None, 0, counts))
+        ni, nr = counts[0], counts[1]
+        it = (ctypes.c_double * max(1, 8 * ni))()
+        res = (ctypes.c_double * max(1, nr))()
+        _check(self.lib.claire_ctx_solve_trace(self._h, it, ni, res, nr, counts))
+        recs = []
+        pos = 0
+        for q in range(ni):
+            r = it[8 * q:8 * q + 8]
+            rec = dict(level=int(r[0]), k=int(r[1]), J=r[2], gnorm=r[3],
+                       pcg_its=int(r[4]), gamma=r[5], ls=int(r[6]))
+            m = int(r[7])
+            if m:
+                rec["pcg_res"] = list(res[pos:pos + m])
+                pos += m
+            recs.append(rec)
+        return recs
+
     def detdefgrad(self, want_field: bool = False):
         det = self._new(self.n, torch.float64) if want_field else None
         stats = (ctypes.c_double * 4)()

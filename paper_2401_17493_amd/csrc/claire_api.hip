@@ -9,6 +9,7 @@
 
 #include "internal.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -140,6 +141,13 @@ struct claire_ctx {
     bool state_valid = false;      // dp, dm, m valid for the content of v
     bool have_velocity = false;    // full setup done: gm, A, g, J valid
     double J = 0, Jdist = 0, Jreg = 0, gnorm = 0;
+
+    // trace of the last solve (host): kTraceWidth values per visited iterate
+    // (level, k, J, ||g||_inf, PCG matvecs, step length, line-search trials,
+    // residual values recorded) and the concatenated PCG residual histories
+    // ||r_l||_inf
+    std::vector<double> trace_iters;
+    std::vector<double> trace_res;
 };
 
 namespace {
@@ -453,6 +461,8 @@ int ensure_solver_buffers(claire_ctx* c) {
     return 0;
 }
 
+constexpr int kTraceWidth = 8;
+
 struct PcgResult {
     int its = 0;
     int inner = 0;           // coarse CG iterations of the two-level preconditioner
@@ -472,6 +482,7 @@ struct PcgResult {
 // alpha L s itself, and the coarse operator takes grad m(1) of the current
 // iterate, restricted once per PCG solve; its inner CG runs to a tenth of eta.
 int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
+    c->trace_res.push_back(c->gnorm);   // ||r_0||_inf = ||g||_inf
     const long long n = c->g.n, n3 = 3 * n;
     const hipStream_t s = c->s;
     const double gn = c->gnorm;
@@ -535,11 +546,14 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(pcg_update(c->red, c->sd, c->hs, nullptr, c->r, (float)kappa, n, 1, 3, s));
         if (res.its == limit) {
             CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
+            CL_TRY(red_fetch(c->red, s));
+            c->trace_res.push_back(c->red.host[1]);
             break;
         }
         // preconditioned residual and <z, r>: one host round trip with the above
         CL_TRY(precond(2));   // z and <z, r> -> slot 2
         CL_TRY(red_fetch(c->red, s));
+        c->trace_res.push_back(c->red.host[1]);
         if (!fixed && c->red.host[1] <= tol) {
             converged = true;
             CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
@@ -578,6 +592,8 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
         if (!(a > 0.0)) { set_error("alpha levels must be positive"); return CLAIRE_EINVAL; }
     claire_stats S;
     std::memset(&S, 0, sizeof(S));
+    c->trace_iters.clear();
+    c->trace_res.clear();
     int warn = 0;
     auto note = [&](int w) { if (!warn) warn = w; };
     bool stop_all = false;
@@ -600,10 +616,15 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
         if (!o.tol_from_zero) g0 = c->gnorm;
         int k = 0;
         while (true) {
+            const size_t rec = c->trace_iters.size();
+            for (double x : {(double)li, (double)k, c->J, c->gnorm, 0.0, 0.0, 0.0, 0.0})
+                c->trace_iters.push_back(x);
             if (c->gnorm <= o.gtol * g0 || c->gnorm <= o.gabs) break;
             if (k >= o.max_gn) { note(CLAIRE_WNOTCONV); break; }
             PcgResult pr;
+            const size_t res_before = c->trace_res.size();
             CL_TRY(run_pcg(c, o, pr));
+            c->trace_iters[rec + 7] = (double)(c->trace_res.size() - res_before);
             S.matvecs += pr.its;
             S.inner_iters += pr.inner;
             S.pde_solves += 2 * pr.its;
@@ -633,6 +654,7 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
                 rb += c->cell * c->red.host[7];
             }
             const double J = c->J, Jreg = c->Jreg + c->Jdiv;
+            const int trials_before = S.linesearch_trials;
             double gamma = 1.0;
             bool accepted = false;
             for (int t = 0; t < o.max_linesearch; ++t) {
@@ -648,6 +670,9 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
                 }
                 gamma *= 0.5;
             }
+            c->trace_iters[rec + 4] = pr.its;
+            c->trace_iters[rec + 5] = accepted ? gamma : 0.0;
+            c->trace_iters[rec + 6] = S.linesearch_trials - trials_before;
             if (!accepted) {
                 note(CLAIRE_WLINESEARCH);
                 // restore the setup at the last accepted iterate
@@ -946,6 +971,21 @@ int claire_ctx_set_precision(claire_ctx* c, int precision) {
     if (precision == 1) CL_TRY(ensure_half_buffers(c));
     if (precision != c->precision) c->have_velocity = false;   // redo the setup
     c->precision = precision;
+    return 0;
+}
+
+int claire_ctx_solve_trace(claire_ctx* c, double* iters, int max_iters, double* pcg_res,
+                           int max_res, int counts[2]) {
+    if (!c || !counts) { set_error("ctx or counts is NULL"); return CLAIRE_EINVAL; }
+    const int ni = (int)(c->trace_iters.size() / kTraceWidth);
+    const int nr = (int)c->trace_res.size();
+    counts[0] = ni;
+    counts[1] = nr;
+    if (iters && max_iters > 0)
+        std::memcpy(iters, c->trace_iters.data(),
+                    sizeof(double) * kTraceWidth * (size_t)std::min(ni, max_iters));
+    if (pcg_res && max_res > 0)
+        std::memcpy(pcg_res, c->trace_res.data(), sizeof(double) * (size_t)std::min(nr, max_res));
     return 0;
 }
 

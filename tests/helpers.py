@@ -67,3 +67,32 @@ class Parity:
     def done(self):
         bad = [(n, e, t) for n, e, t in self.rows if not e <= t]
         assert not bad, bad
+
+
+def trace_parity(P, label, trace, history, tol, steps=None):
+    """Per-iterate J and ||g||_inf, PCG matvec counts and the PCG residual
+    histories ||r_l||_inf of a GPU solve against the oracle's record (the
+    first ``steps`` records if given, else all and the same count).
+
+    ||g_k||_inf is compared relative to the level's first ||g_0||_inf: g_k is
+    alpha L v + the data term, two parts of the size of g_0 that cancel as the
+    solve converges, so its float32 error scales with ||g_0||_inf."""
+    if steps is None:
+        assert len(trace) == len(history), (len(trace), len(history))
+    else:
+        trace, history = trace[:steps], history[:steps]
+        assert len(trace) == len(history) == steps, (len(trace), len(history))
+    g0 = {}
+    for t, h in zip(trace, history):
+        g0.setdefault(h.get("alpha", 0), h["gnorm"])
+        P.value("%s J k=%d" % (label, h["k"]), t["J"], h["J"], tol)
+        P.value("%s |g|/|g0| k=%d" % (label, h["k"]), 1.0 + (t["gnorm"] - h["gnorm"]) /
+                g0[h.get("alpha", 0)], 1.0, tol)
+        if "pcg_its" in h:
+            assert t["pcg_its"] == h["pcg_its"], (h["k"], t["pcg_its"], h["pcg_its"])
+            assert t["ls"] == h["ls"] and t["gamma"] == h["gamma"]
+            res, ref = np.array(t["pcg_res"]), np.array(h["pcg_res"])
+            assert res.shape == ref.shape
+            # each residual relative to the step's initial residual ||g||_inf
+            P.value("%s |r_l| k=%d (max over l)" % (label, h["k"]),
+                    1.0 + float(np.abs(res - ref).max() / ref[0]), 1.0, tol)

@@ -1,0 +1,125 @@
+"""The 256^3 headline solve (nested-ellipsoid workload, H1 seminorm,
+alpha = 1e-3, n_t = 4, gtol 5e-2, from v = 0) against the FP64 oracle's run
+of the same problem, stored in tests/golden/ellipsoids256_h1_solve.json by
+tests/golden/make_solve_golden.py (which calls only the oracle).
+
+float32 path (1e-5 bar): the gradient at v = 0 at the record's sample voxels,
+then the solve step by step -- per iterate J, ||g||_inf, PCG matvecs, the PCG
+residual histories, step lengths and line-search trials -- the iterates after
+the first three Gauss--Newton steps and the solution at the sample voxels,
+J, the relative mismatch and det F(1).
+Mixed path (1e-3 bar): the solution at the sample voxels and J.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from helpers import Parity, phantom_problem, trace_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "ellipsoids256_h1_solve.json")
+
+
+@pytest.fixture(scope="module")
+def C():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_17493_amd import claire
+    return claire
+
+
+@pytest.fixture(scope="module")
+def problem():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("no oracle record of the 256^3 solve")
+    ref = json.load(open(GOLDEN))
+    grid, m0, m1, vstar, w = phantom_problem("ellipsoids256")
+    sha = hashlib.sha256(np.ascontiguousarray(m1, dtype=np.float32).tobytes()).hexdigest()
+    assert sha == ref["m1_sha256"], "the workload's inputs differ from the oracle record's"
+    return ref, grid, m0, m1, w
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def samples(v, idx):
+    torch.cuda.synchronize()
+    t = torch.as_tensor(np.array(idx), device=v.device)
+    return v[:, t[:, 0], t[:, 1], t[:, 2]].double().cpu().numpy().T
+
+
+def test_solve256_fp32(C, problem):
+    ref, grid, m0, m1, w = problem
+    idx = ref["sample_idx"]
+    P = Parity("ellipsoids256 fp32")
+    with C.Context(grid.n, w["nt"], w["alphas"][-1], w["reg_order"]) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(torch.zeros((3,) + grid.n, device="cuda"))
+        g0, _ = ctx.gradient()
+        P.rel("g(0) samples", samples(g0, idx), np.array(ref["g0_samples"]), 1e-5)
+        v, st = ctx.solve(gtol=w["gtol"], compute_det=1)
+        trace = ctx.solve_trace()
+        vs = samples(v, idx)
+        print("GPU:", {k: st[k] for k in ("status", "gn_iters", "matvecs", "linesearch_trials",
+                                          "J0", "J", "rel_grad", "rel_mismatch", "det_min",
+                                          "det_mean", "det_max")}, flush=True)
+        print("ORACLE:", {k: ref[k] for k in ("gn_iters", "matvecs", "ls_trials", "J0", "J",
+                                              "rel_grad", "rel_mismatch", "det_min",
+                                              "det_mean", "det_max")}, flush=True)
+        print("PCG matvecs per step: GPU %s, oracle %s"
+              % ([t["pcg_its"] for t in trace], [h.get("pcg_its") for h in ref["history"]]),
+              flush=True)
+        # iterates after the first Gauss--Newton steps (deterministic: the
+        # same solve stopped after k steps)
+        for k, snap in sorted(ref["snapshots"].items()):
+            vk, sk = ctx.solve(gtol=w["gtol"], max_gn=int(k))
+            P.rel("v after %s GN steps" % k, samples(vk, idx), np.array(snap["v_samples"]), 1e-5)
+            P.value("J after %s GN steps" % k, sk["J"], snap["J"], 1e-5)
+    assert st["status"] == 0 and st["rel_grad"] <= w["gtol"]
+    trace_parity(P, "solve", trace, ref["history"], 1e-5)
+    assert st["gn_iters"] == ref["gn_iters"] and st["matvecs"] == ref["matvecs"]
+    assert st["linesearch_trials"] == ref["ls_trials"]
+    P.rel("v samples", vs, np.array(ref["v_samples"]), 1e-5)
+    P.value("J", st["J"], ref["J"], 1e-5)
+    P.value("rel mismatch", st["rel_mismatch"], ref["rel_mismatch"], 1e-5)
+    for k in ("det_min", "det_mean", "det_max"):
+        P.value(k, st[k], ref[k], 1e-5)
+    assert st["det_nonpositive"] == ref["det_nonpositive"] == 0
+    P.done()
+
+
+def test_solve256_mixed(C, problem):
+    # The mixed matvec differs from the float32 one by ~3e-4, which can move
+    # a PCG stopping decision and so the path of the solve. The comparison is
+    # therefore at matched Gauss--Newton counts: the iterates after the first
+    # three steps, and the solution when the step and matvec counts agree.
+    ref, grid, m0, m1, w = problem
+    idx = ref["sample_idx"]
+    P = Parity("ellipsoids256 mixed")
+    with C.Context(grid.n, w["nt"], w["alphas"][-1], w["reg_order"]) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        for k, snap in sorted(ref["snapshots"].items()):
+            vk, sk = ctx.solve(gtol=w["gtol"], max_gn=int(k), precision=1)
+            P.rel("v after %s GN steps" % k, samples(vk, idx), np.array(snap["v_samples"]), 1e-3)
+            P.value("J after %s GN steps" % k, sk["J"], snap["J"], 1e-3)
+        v, st = ctx.solve(gtol=w["gtol"], precision=1, compute_det=1)
+        vs = samples(v, idx)
+    same_path = st["gn_iters"] == ref["gn_iters"] and st["matvecs"] == ref["matvecs"]
+    print("GPU mixed:", {k: st[k] for k in ("status", "gn_iters", "matvecs", "J", "rel_grad")},
+          "oracle:", {k: ref[k] for k in ("gn_iters", "matvecs", "J", "rel_grad")},
+          "same path:", same_path, flush=True)
+    print("final v samples rel err %.3e, J rel err %.3e"
+          % (np.abs(vs - np.array(ref["v_samples"])).max() / np.abs(ref["v_samples"]).max(),
+             abs(st["J"] - ref["J"]) / ref["J"]), flush=True)
+    assert st["status"] == 0 and st["rel_grad"] <= w["gtol"]
+    if same_path:
+        P.rel("v samples", vs, np.array(ref["v_samples"]), 1e-3)
+        P.value("J", st["J"], ref["J"], 1e-3)
+    P.done()

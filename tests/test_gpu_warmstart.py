@@ -81,6 +81,45 @@ def test_conv3d_backward(WS, B, R, cin, cout):
     assert max(errs) <= 2e-5
 
 
+# The widths of the shipped network (channels 16, 32, 64, 128): 128 -> 128
+# (bottleneck), the decoder concatenations 192 -> 64 and 96 -> 32, whose
+# output columns span two or more 64-wide blocks and whose backward-data
+# GEMM has more than 64 rows; and the weight gradient at B = 4, R = 64, where
+# the voxel reduction is split 1024 ways (the cap).
+PRODUCTION = [(1, 8, 128, 128), (1, 8, 192, 64), (2, 8, 96, 32), (1, 4, 48, 16)]
+
+
+@pytest.mark.parametrize("B,R,cin,cout", PRODUCTION)
+def test_conv3d_production_widths(WS, B, R, cin, cout):
+    r = np.random.default_rng(400 + R + cin + cout)
+    x = f32(r.standard_normal((B, R, R, R, cin)))
+    w = f32(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    b = f32(r.standard_normal(cout))
+    dz = f32(r.standard_normal((B, R, R, R, cout)))
+    y = host(WS.conv3d(dev(x), dev(w), dev(b), act=True))
+    ref = W.leaky(W.conv3d(W.bf16(x), W.bf16(w), b))
+    dx, dw, db = (host(t) for t in WS.conv3d_backward(dev(x), dev(w), dev(dz)))
+    rdx, rdw, rdb = W.conv3d_backward(W.bf16(x), W.bf16(w), W.bf16(dz))
+    errs = rel(y, ref), rel(dx, rdx), rel(dw, rdw), rel(db, rdb)
+    print("conv3d B%d R%d %d->%d: y %.2e dx %.2e dw %.2e db %.2e" % ((B, R, cin, cout) + errs))
+    assert max(errs) <= 2e-5
+
+
+def test_wgrad_split_cap(WS):
+    # B R^3 = 4 * 64^3 voxels: 2048 chunks of 512 would be needed, the split
+    # count is capped at 1024 (chunks of 1024 voxels)
+    B, R, cin, cout = 4, 64, 8, 16
+    r = np.random.default_rng(500)
+    x = f32(r.standard_normal((B, R, R, R, cin)))
+    w = f32(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    dz = f32(r.standard_normal((B, R, R, R, cout)))
+    dx, dw, db = (host(t) for t in WS.conv3d_backward(dev(x), dev(w), dev(dz)))
+    rdx, rdw, rdb = W.conv3d_backward(W.bf16(x), W.bf16(w), W.bf16(dz))
+    errs = rel(dx, rdx), rel(dw, rdw), rel(db, rdb)
+    print("conv3d backward B%d R%d %d->%d: dx %.2e dw %.2e db %.2e" % ((B, R, cin, cout) + errs))
+    assert max(errs) <= 2e-5
+
+
 @pytest.mark.parametrize("n_src,n_dst,c", [(32, 8, 1), (8, 32, 3), (16, 64, 3), (64, 16, 2),
                                            (16, 16, 1)])
 def test_resample(WS, n_src, n_dst, c):
@@ -162,6 +201,45 @@ def test_network_forward_and_gradient(WS):
             worst = max(worst, e_gpu / max(e_q, 1e-3))
     # the GPU network sits inside the bfloat16 noise ball that the oracle's own
     # bfloat16 emulation measures against the float64 network
+    assert l2rel(v, v64) <= 2 * noise + 1e-3
+    assert abs(loss - l64) <= 1e-2 * l64
+    assert worst <= 3.0, worst
+
+
+def test_production_network_forward_and_gradient(WS):
+    # the shipped network's widths (16, 32, 64, 128) at R = 32, within the
+    # same bfloat16 noise ball as above
+    from paper_2401_17493_amd.warmstart import DEFAULT_CHANNELS
+    spec = W.NetSpec(channels=tuple(DEFAULT_CHANNELS))
+    B, R = 1, 32
+    params = random_params(spec, 17)
+    m0 = smooth_images(B, R, 41)
+    m1 = smooth_images(B, R, 42)
+    target = f32(np.random.default_rng(43).standard_normal((B, 3, R, R, R)) * 0.3)
+    with WS.Net(R, spec.channels, max_batch=B) as net:
+        net.set_params(dev(f32(spec.flatten(params))))
+        loss, v = net.loss_grad(dev(m0), dev(m1), dev(target), want_v=True)
+        g = host(net.get_grads())
+        v = host(v)
+    x = W.input_features(m0, m1)
+    t_cl = np.moveaxis(target, 1, -1)
+    lq, gq, vq = W.loss_and_grads(spec, params, x, t_cl, store=W.bf16)
+    l64, g64, v64 = W.loss_and_grads(spec, params, x, t_cl)
+    vq = np.moveaxis(vq, -1, 1)
+    v64 = np.moveaxis(v64, -1, 1)
+    noise = l2rel(vq, v64)
+    print("production net v (rel L2): gpu-float64 %.2e, emulated-float64 %.2e; loss %.6e / %.6e"
+          % (l2rel(v, v64), noise, loss, l64))
+    gd, gqd, g64d = spec.unflatten(g), spec.unflatten(spec.flatten(gq)), \
+        spec.unflatten(spec.flatten(g64))
+    worst = 0.0
+    for name, _, _ in spec.layers():
+        for k, what in ((0, "w"), (1, "b")):
+            e_gpu = l2rel(gd[name][k], g64d[name][k])
+            e_q = l2rel(gqd[name][k], g64d[name][k])
+            print("  grad %-5s %s: gpu-float64 %.2e, emulated-float64 %.2e" % (
+                name, what, e_gpu, e_q))
+            worst = max(worst, e_gpu / max(e_q, 1e-3))
     assert l2rel(v, v64) <= 2 * noise + 1e-3
     assert abs(loss - l64) <= 1e-2 * l64
     assert worst <= 3.0, worst
