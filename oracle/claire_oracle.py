@@ -390,6 +390,21 @@ class VelocityState:
     grad_J: np.ndarray = None   # L2 gradient of J (equals g when beta = 0)
 
 
+class RecomputedGradients:
+    """grad m^j computed again at every access instead of stored (the
+    memory-lean setup: at 512^3, n_t = 8 the stored gradients alone take
+    27 GiB in float64). Indexable like the list it replaces."""
+
+    def __init__(self, grid, m, deriv):
+        self.grid, self.m, self.deriv = grid, m, deriv
+
+    def __len__(self):
+        return len(self.m)
+
+    def __getitem__(self, j):
+        return gradient(self.grid, self.m[j], self.deriv)
+
+
 def objective_parts(grid, m_final, m1, v, alpha, p):
     """J = 1/2 <m(1)-m1, m(1)-m1> + alpha/2 <L v, v> (eq. e:varopt-claire)."""
     r = m_final - m1
@@ -398,13 +413,16 @@ def objective_parts(grid, m_final, m1, v, alpha, p):
     return dist, reg
 
 
-def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0):
+def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0,
+                   store_grad=True):
     """State, objective, adjoint and reduced gradient at v (Algorithm 1 lines
     3-6; eqs. e:transport, e:varopt-claire, e:adjoint, e:rgrad). ``deriv``
     selects the gradient/divergence discretisation ("spectral" or "fd8") of
     the transport and adjoint equations. ``beta`` > 0 selects the
     near-incompressible model (appendix): J gains divergence_penalty and the
-    reduced gradient is alpha L v + ni_project(data)."""
+    reduced gradient is alpha L v + ni_project(data). ``store_grad`` False:
+    grad m^j is recomputed wherever it is used (same values, less memory),
+    and the adjoint history, no longer needed once g is formed, is dropped."""
     if beta > 0.0 and p != 1:
         raise ValueError("the near-incompressible model uses the H1 seminorm (p = 1)")
     st = VelocityState(grid=grid, nt=nt, alpha=alpha, p=p, beta=beta,
@@ -417,7 +435,8 @@ def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0):
     st.m = solve_state(st.m0, st.d_plus, nt)
     st.J_dist, st.J_reg = objective_parts(grid, st.m[-1], st.m1, st.v, alpha, p)
     st.J = st.J_dist + st.J_reg
-    st.grad_m = [gradient(grid, mj, deriv) for mj in st.m]
+    st.grad_m = [gradient(grid, mj, deriv) for mj in st.m] if store_grad else \
+        RecomputedGradients(grid, st.m, deriv)
     st.div_v = divergence(grid, st.v, deriv)
     st.div_v_dep = interpolate(st.div_v, st.d_minus)
     lam = [None] * (nt + 1)
@@ -437,6 +456,8 @@ def setup_velocity(grid, m0, m1, v, alpha, nt, p, deriv="spectral", beta=0.0):
     else:
         st.g = reg + st.data
         st.grad_J = st.g
+    if not store_grad:
+        st.lam = None
     return st
 
 
@@ -457,14 +478,15 @@ def incremental_state(st, vt):
     characteristics of v: D m~/Dt = f, f^j = -grad m^j . v~ formed on the grid
     and interpolated at the departure points."""
     nt, ht = st.nt, 1.0 / st.nt
-    f = [-np.sum(st.grad_m[j] * vt, axis=0) for j in range(nt + 1)]
     mt = np.zeros(st.grid.n)
+    f_j = -np.sum(st.grad_m[0] * vt, axis=0)
     for j in range(nt):
         u_y = interpolate(mt, st.d_plus)
-        f0 = interpolate(f[j], st.d_plus)
+        f0 = interpolate(f_j, st.d_plus)
         # f does not depend on m~, so the RK2 predictor does not enter f1
-        f1 = f[j + 1]
+        f1 = -np.sum(st.grad_m[j + 1] * vt, axis=0)
         mt = u_y + 0.5 * ht * (f0 + f1)
+        f_j = f1
     return mt
 
 

@@ -90,6 +90,11 @@ struct claire_ctx {
     double alpha = 0;
     int p = 1;
     hipStream_t s = nullptr;
+    // side stream (default priority) on which a standalone Hessian matvec runs
+    // the FFTs of alpha L v~ while the main stream runs the gathers; forked
+    // and joined with the two events
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double cell = 0;   // h1 h2 h3
 
     // per-velocity state
@@ -194,6 +199,9 @@ int ctx_alloc(claire_ctx* c) {
     CL_TRY(dalloc(&c->box_m, brick_table_ints(c->g)));
     CL_TRY(spectral_init(c->sw, c->g));
     CL_TRY(reducer_init(c->red, c->g.n));
+    CL_HIP(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
+    CL_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    CL_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     return 0;
 }
 
@@ -210,6 +218,12 @@ void ctx_release(claire_ctx* c) {
     spectral_free(c->sw);
     reducer_free(c->red);
     twolevel_free(c->tl);
+    if (c->s2) {
+        (void)hipStreamSynchronize(c->s2);
+        (void)hipStreamDestroy(c->s2);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
 }
 
 int copy_d2d(float* dst, const float* src, long long count, hipStream_t s) {
@@ -342,6 +356,22 @@ int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* re
     return 0;
 }
 
+// alpha L v~ into tmp3 on the side stream, ordered after the work already
+// enqueued on the main stream; join_reg() makes the main stream wait for it.
+// The FFT passes are bound by HBM streaming, the gathers they overlap by the
+// LDS and the VALU. Uses the spectral workspace, which the gathers do not.
+int fork_reg(claire_ctx* c, const float* vt) {
+    CL_HIP(hipEventRecord(c->ev_fork, c->s));
+    CL_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s2));
+    CL_HIP(hipEventRecord(c->ev_join, c->s2));
+    return 0;
+}
+int join_reg(claire_ctx* c) {
+    CL_HIP(hipStreamWaitEvent(c->s, c->ev_join, 0));
+    return 0;
+}
+
 // scale_ready (mixed path): max|vt| is already in the reducer's kScaleSlot
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
                int dot_slot = -1, bool scale_ready = false) {
@@ -350,6 +380,8 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
     const long long n = g.n;
     const int nt = c->nt;
     const double ht = 1.0 / nt;
+    const bool fork = !reg_part;
+    if (fork) CL_TRY(fork_reg(c, vt));
     // incremental state, forward in time; the last step writes lambda~^nt = -m~^nt
     CL_TRY(launch_inc_state_first(g, c->gm, vt, c->w0, ht, c->s));
     float* src = c->w0;
@@ -372,8 +404,8 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
         CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
                                    c->lam + (long long)j * n, c->s, c->box_m));
     // H v~ = alpha L v~ + h_t sum_j c_j lambda~^j grad m^j
-    if (!reg_part) {
-        CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
+    if (fork) {
+        CL_TRY(join_reg(c));
         reg_part = c->tmp3;
     }
     if (c->beta > 0.0) {
@@ -401,6 +433,8 @@ int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* re
     const int nt = c->nt;
     const double ht = 1.0 / nt;
     const double* scale = c->red.result + kScaleSlot;
+    const bool fork = !reg_part;
+    if (fork) CL_TRY(fork_reg(c, vt));
     if (!scale_ready) CL_TRY(red_absmax(c->red, vt, 3 * n, kScaleSlot, c->s));
     CL_TRY(launch_mixed_sources(g, c->gm16, vt, scale, c->f16, c->w0, nt, c->s));
     float* src = c->w0;
@@ -421,8 +455,8 @@ int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* re
     for (int j = nt - 1; j >= 0; --j)
         CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
                                    c->lam + (long long)j * n, c->s, c->box_m));
-    if (!reg_part) {
-        CL_TRY(spectral_apply(g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s));
+    if (fork) {
+        CL_TRY(join_reg(c));
         reg_part = c->tmp3;
     }
     if (c->beta > 0.0) {

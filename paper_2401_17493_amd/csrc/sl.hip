@@ -148,8 +148,13 @@ __device__ __forceinline__ void coords(const G3& g, long long idx, int& i1, int&
 // local deformation) gathers directly from global memory instead. Bricks are
 // handed out so that each XCD sweeps a contiguous slab of the grid, keeping
 // the halo rows shared by neighbouring bricks in one L2.
+// 5080 floats of box plus the reduction scratch: eight workgroups fill a
+// CU's 160 KiB of LDS (the occupancy the kernels are compiled for). The
+// boxes of strongly deformed velocities (local spread of the stencil origins
+// of several voxels) still fit; a brick whose box does not gathers from
+// global memory at several times the cost.
 #ifndef CLAIRE_GATHER_BOXCAP
-#define CLAIRE_GATHER_BOXCAP 4096
+#define CLAIRE_GATHER_BOXCAP 5080
 #endif
 #ifndef CLAIRE_GATHER_VOX
 #define CLAIRE_GATHER_VOX 2
@@ -666,10 +671,13 @@ __global__ __launch_bounds__(kThreads) void k_interp_gen(const float* __restrict
 
 unsigned blocks_for(long long n);
 
+// brick of the single-field gathers (and of their per-brick box tables)
+Brick gather_brick(const Geo& g) { return make_brick(g); }
+
 template <class Epi>
 int launch_gather_lds(const Geo& g, const float* src, const float* disp, const int* table,
                       const Epi& epi, hipStream_t s) {
-    const Brick br = make_brick(g);
+    const Brick br = gather_brick(g);
     if (!g.pow2)
         hipLaunchKernelGGL((k_gather_lds<Epi, true>), dim3(br.nbricks), dim3(kThreads), 0, s, src,
                            disp, table, epi, make_g3(g), br, g.n);
@@ -997,7 +1005,7 @@ int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, 
     return 0;
 }
 
-int brick_table_ints(const Geo& g) { return 6 * make_brick(g).nbricks; }
+int brick_table_ints(const Geo& g) { return 6 * gather_brick(g).nbricks; }
 
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
     if ((n & 3) == 0 && ((reinterpret_cast<uintptr_t>(x) & 15) | (reinterpret_cast<uintptr_t>(y) & 7)) == 0)
@@ -1041,7 +1049,7 @@ int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int n
 }
 
 int launch_brick_boxes(const Geo& g, const float* disp, int* table, hipStream_t s) {
-    const Brick br = make_brick(g);
+    const Brick br = gather_brick(g);
     if (!g.pow2)
         hipLaunchKernelGGL(k_brick_boxes<true>, dim3(br.nbricks), dim3(kThreads), 0, s, disp,
                            table, make_g3(g), br, g.n);

@@ -130,3 +130,44 @@ def test_solve_512(C, data):
     for J0, J in Js:
         assert np.isfinite(J) and J < J0
     assert Js[1][1] < Js[0][1]
+
+
+def test_oracle_samples_512(C):
+    """Element-wise parity at full size: one transport and one Hessian matvec
+    against the FP64 oracle's values at 2048 sampled voxels
+    (tests/golden/ellipsoids512_samples.json, written by
+    tests/golden/make_512_golden.py), relative to the field's max-norm."""
+    import hashlib
+    import json
+    import os
+
+    from helpers import f32, phantom_problem
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "ellipsoids512_samples.json")
+    if not os.path.exists(path):
+        pytest.skip("no oracle record at 512^3")
+    ref = json.load(open(path))
+    grid, m0, m1, vstar, w = phantom_problem("ellipsoids512")
+    sha = hashlib.sha256(np.ascontiguousarray(m1, dtype=np.float32).tobytes()).hexdigest()
+    assert sha == ref["m1_sha256"]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa
+    idx = torch.as_tensor(np.array(ref["sample_idx"]), device="cuda")
+    at = lambda t: t[..., idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()  # noqa
+    clean = dev(f32(ellipsoid_phantom(N, W["seed"])))
+    vs = dev(vstar)
+    mt = C.transport(clean, vs, W["nt"])
+    e_t = float(np.abs(at(mt) - np.array(ref["transport_clean_by_vstar"])).max() /
+                np.abs(ref["transport_clean_by_vstar"]).max())
+    del clean, mt
+    vt = dev(f32(bandlimited_velocity(N, W["seed"] + 4000, W["kmax"], 1.0)))
+    with C.Context(N, W["nt"], W["alphas"][-1], W["reg_order"]) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(f32(0.5 * vstar)))
+        g, J = ctx.gradient()
+        e_g = float(np.abs(at(g).T - np.array(ref["g"])).max() / ref["g_max"])
+        hv = ctx.hessian_matvec(vt)
+        e_h = float(np.abs(at(hv).T - np.array(ref["Hv"])).max() / ref["Hv_max"])
+    e_j = abs(J - ref["J"]) / abs(ref["J"])
+    print("512^3 vs oracle at %d voxels: transport %.2e, g %.2e, J %.2e, Hv %.2e"
+          % (len(ref["sample_idx"]), e_t, e_g, e_j, e_h))
+    assert e_t <= 1e-5 and e_g <= 1e-5 and e_j <= 1e-5 and e_h <= 1e-5

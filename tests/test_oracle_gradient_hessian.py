@@ -17,6 +17,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 import oracle as O
+from helpers import blob_problem
 from synthetic import bandlimited_velocity, gaussian_blobs
 
 
@@ -191,3 +192,17 @@ def test_pcg_stops_on_nonpositive_curvature():
     # positive definite: unaffected
     O.pcg(lambda s: 2.0 * s, ident, g)
     assert not O.pcg.neg_curv
+
+
+def test_memory_lean_setup_matches_stored():
+    # grad m^j recomputed on access (the 512^3 setting) gives bit-identical
+    # gradient and Hessian matvec to the stored gradients
+    grid, m0, m1, vstar = blob_problem()
+    v = 0.5 * vstar
+    vt = bandlimited_velocity(grid.n, 91, 4, 0.5)
+    for deriv in ("spectral", "fd8"):
+        st = O.setup_velocity(grid, m0, m1, v, 1e-2, 4, 1, deriv)
+        lean = O.setup_velocity(grid, m0, m1, v, 1e-2, 4, 1, deriv, store_grad=False)
+        assert isinstance(lean.grad_m, O.RecomputedGradients) and lean.lam is None
+        assert np.array_equal(st.g, lean.g) and st.J == lean.J
+        assert np.array_equal(O.hessian_matvec(st, vt), O.hessian_matvec(lean, vt))
