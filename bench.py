@@ -10,8 +10,8 @@ inputs resident in HBM. Prints one JSON line.
                   [--precision mixed|fp32|both] [--warmstart WEIGHTS|none]
 
 ``value`` is the time-to-solution (seconds) of the mixed-precision solve
-(float16 storage of grad m and the incremental sources in the Hessian matvec,
-float32 arithmetic) started from the learned warm start: the timed region
+(the Hessian matvec reads grad m^j from a float16 copy; float32 arithmetic
+and fields) started from the learned warm start: the timed region
 holds the network's inference (restriction to its working resolution,
 forward pass, prolongation), the extra state/adjoint solve at v = 0 that
 fixes the stopping test at ||g||_inf <= gtol ||g(0)||_inf, and the solve.
@@ -376,10 +376,10 @@ def main():
     def matvec_roofline(r):
         # algorithmic fields per matvec: 29 + 21 nt float32 (incremental state
         # 7 + 11 nt, adjoint 6 nt, assembly 4 (nt + 1) + 3, alpha L v~ 15);
-        # mixed: float16 grad m^j and sources f^j count half a field each:
-        # sources pass 2 (nt + 1) + 4, state steps 5.5 nt, adjoint 6 nt,
-        # assembly 2.5 (nt + 1) + 3, alpha L v~ 15 -> 16 nt + 26.5
-        fields = 29 + 21 * nt if r["prec"] == 0 else 16 * nt + 26.5
+        # mixed: each read of a float16 grad m^j component counts half a field:
+        # state 5.5 + 9.5 nt, adjoint 6 nt, assembly 2.5 (nt + 1) + 3, alpha
+        # L v~ 15 -> 18 nt + 26
+        fields = 29 + 21 * nt if r["prec"] == 0 else 18 * nt + 26
         nbytes = 4.0 * fields * n[0] * n[1] * n[2]
         gbs = nbytes / (r["ms_matvec"] * 1e-3) / 1e9
         return {"fields": fields, "algorithmic_bytes": nbytes, "achieved": round(gbs, 1),
@@ -421,7 +421,7 @@ def main():
                    "gtol": opts["gtol"],
                    "preconditioner": "(alpha L)^-1" if args.precond == "reg" else
                    "two-level zero-velocity H0 (coarse grid n/2, inner CG to 0.1 eta)",
-                   "precision": "mixed: float16 grad m and incremental sources in the "
+                   "precision": "mixed: float16 grad m^j read by the "
                                 "Hessian matvec, float32 arithmetic/FFTs, float64 reductions"
                    if head["prec"] == 1 else "float32 fields and FFTs, float64 reductions",
                    "initial_guess": "learned warm start (%s), stopping test against "

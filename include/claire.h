@@ -64,9 +64,9 @@ enum claire_status {
 typedef struct claire_opts {
     int reg_order;              /* 1: H1 seminorm (symbol |k|^2); 2: H2 seminorm (|k|^4) */
     int precision;              /* 0: float32 fields and FFTs; 1: mixed -- the Hessian
-                                   matvec stores grad m^j and the incremental-state
-                                   sources in float16 (float32 arithmetic and FFTs);
-                                   gradient, objective, PCG dots and det F unchanged */
+                                   matvec reads grad m^j from a float16 copy (float32
+                                   arithmetic, fields and FFTs); gradient, objective,
+                                   PCG dots and det F unchanged */
     double gtol;                /* stop when ||g||_inf <= gtol ||g_0||_inf (default 5e-2) */
     double gabs;                /* ... or when ||g||_inf <= gabs (default 1e-6) */
     int forcing;                /* PCG forcing: 0 superlinear eta = min(1/2, sqrt||g||_inf),
@@ -180,9 +180,9 @@ int claire_ctx_objective(claire_ctx *ctx, const float *v, double *J);
 int claire_ctx_hessian_matvec(claire_ctx *ctx, const float *vt, float *Hvt);
 
 /* Select the Hessian matvec's storage precision for later set_velocity /
- * hessian_matvec calls: 0 float32, 1 mixed (float16 storage of grad m^j and
- * of the incremental-state sources -grad m^j . v~; float32 arithmetic and
- * FFTs; the gradient path stays float32). Invalidates the cached setup (call
+ * hessian_matvec calls: 0 float32, 1 mixed (the matvec reads grad m^j from a
+ * float16 copy made at set_velocity; float32 arithmetic, fields and FFTs;
+ * the gradient path stays float32). Invalidates the cached setup (call
  * set_velocity again). */
 int claire_ctx_set_precision(claire_ctx *ctx, int precision);
 

@@ -119,7 +119,6 @@ struct claire_ctx {
     // mixed precision (half storage in the Hessian matvec), allocated on demand
     int precision = 0;       // 0 float32, 1 mixed
     __half* gm16 = nullptr;  // [nt+1][3][n] grad m^j
-    __half* f16 = nullptr;   // [nt+1][n] incremental-state sources (scaled)
     bool half_valid = false; // gm16 belongs to the current setup
     SpectralWork sw;
     Reducer red;
@@ -210,8 +209,7 @@ void ctx_release(claire_ctx* c) {
                      c->regv, c->lam, c->w0, c->w1, c->tmp3, c->vt, c->r, c->z, c->sd, c->hs,
                      c->vtrial, c->als, c->ni_tmp, c->gradJ};
     for (float* b : bufs) dfree(b);
-    __half* hbufs[] = {c->gm16, c->f16};
-    for (__half* b : hbufs) dfree(b);
+    dfree(c->gm16);
     dfree(c->flag);
     dfree(c->box_p);
     dfree(c->box_m);
@@ -258,7 +256,6 @@ int ensure_half_buffers(claire_ctx* c) {
     const long long n = c->g.n;
     const int nt = c->nt;
     if (!c->gm16) CL_TRY(dalloc(&c->gm16, 3 * (nt + 1) * n));
-    if (!c->f16) CL_TRY(dalloc(&c->f16, (nt + 1) * n));
     return 0;
 }
 
@@ -337,24 +334,10 @@ int run_setup(claire_ctx* c) {
 
 // Gauss--Newton Hessian matvec (eqs. e:matvec, e:incstate, e:incadj).
 // reg_part: alpha L vt when the caller already has it (PCG), else NULL and
-// it is computed here by FFT. dot_slot >= 0: also <vt, out> into that
-// reduction slot.
-// Reducer slot of the mixed matvec's scale max|v~| (used by its kernels on
-// the device)
-constexpr int kScaleSlot = 7;
-
-int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
-                     int dot_slot, bool scale_ready);
-
-// out = reg_part + K ni_tmp (near-incompressible projection of the data term
-// in ni_tmp), and <vt, out> -> dot_slot when >= 0
+// it is computed here by FFT (on the side stream, beside the gathers).
+// dot_slot >= 0: also <vt, out> into that reduction slot.
 int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part,
-                     int dot_slot) {
-    CL_TRY(spectral_ni(c->g, c->sw, NI_PROJECT, c->ni_tmp, out, c->alpha, c->beta, c->s,
-                       reg_part));
-    if (dot_slot >= 0) CL_TRY(red_dot(c->red, vt, out, 3 * c->g.n, dot_slot, c->s));
-    return 0;
-}
+                     int dot_slot);
 
 // alpha L v~ into tmp3 on the side stream, ordered after the work already
 // enqueued on the main stream; join_reg() makes the main stream wait for it.
@@ -372,10 +355,13 @@ int join_reg(claire_ctx* c) {
     return 0;
 }
 
-// scale_ready (mixed path): max|vt| is already in the reducer's kScaleSlot
-int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
-               int dot_slot = -1, bool scale_ready = false) {
-    if (c->precision == 1) return run_matvec_mixed(c, vt, out, reg_part, dot_slot, scale_ready);
+// GT: storage of grad m^j read by the matvec (float; __half in the mixed
+// path, whose only difference is these 16-bit reads -- the sources
+// f^j = -grad m^j . v~, the fields m~, lam~, A and the displacements stay
+// float32, R23).
+template <typename GT>
+int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
+                 const float* reg_part, int dot_slot) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -383,11 +369,11 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
     const bool fork = !reg_part;
     if (fork) CL_TRY(fork_reg(c, vt));
     // incremental state, forward in time; the last step writes lambda~^nt = -m~^nt
-    CL_TRY(launch_inc_state_first(g, c->gm, vt, c->w0, ht, c->s));
+    CL_TRY(launch_inc_state_first(g, gm, vt, c->w0, ht, c->s));
     float* src = c->w0;
     float* nxt = c->w1;
     for (int j = 0; j < nt; ++j) {
-        const float* gnext = c->gm + (long long)(j + 1) * 3 * n;
+        const GT* gnext = gm + (long long)(j + 1) * 3 * n;
         if (j + 1 < nt) {
             CL_TRY(launch_inc_state_step(g, src, c->dp, gnext, vt, nxt, (float)ht, 1.0f, c->s,
                                          c->box_p));
@@ -399,76 +385,39 @@ int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part
                                          (float)(0.5 * ht), -1.0f, c->s, c->box_p));
         }
     }
-    // incremental adjoint (GN), backward in time
-    for (int j = nt - 1; j >= 0; --j)
-        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
-                                   c->lam + (long long)j * n, c->s, c->box_m));
-    // H v~ = alpha L v~ + h_t sum_j c_j lambda~^j grad m^j
     if (fork) {
         CL_TRY(join_reg(c));
         reg_part = c->tmp3;
     }
+    // incremental adjoint (GN), backward in time, then
+    // H v~ = alpha L v~ + h_t sum_j c_j lambda~^j grad m^j in one pass
+    for (int j = nt - 1; j >= 0; --j)
+        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
+                                   c->lam + (long long)j * n, c->s, c->box_m));
     if (c->beta > 0.0) {
         // near-incompressible model: the data term projected by K
-        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, nullptr, c->ni_tmp, c->s));
+        CL_TRY(launch_assemble(g, c->lam, gm, nt, (const float*)nullptr, c->ni_tmp, c->s));
         return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
     }
     if (dot_slot >= 0)
-        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot));
-    else
-        CL_TRY(launch_assemble(g, c->lam, c->gm, nt, reg_part, out, c->s));
+        return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot);
+    return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s);
+}
+
+// out = reg_part + K ni_tmp (near-incompressible projection of the data term
+// in ni_tmp), and <vt, out> -> dot_slot when >= 0
+int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part,
+                     int dot_slot) {
+    CL_TRY(spectral_ni(c->g, c->sw, NI_PROJECT, c->ni_tmp, out, c->alpha, c->beta, c->s,
+                       reg_part));
+    if (dot_slot >= 0) CL_TRY(red_dot(c->red, vt, out, 3 * c->g.n, dot_slot, c->s));
     return 0;
 }
 
-// Mixed-precision Gauss--Newton matvec: the same steps as run_matvec with
-// grad m^j and the incremental-state sources f^j = -grad m^j . v~ stored in
-// half (float arithmetic; the per-step fields, A and the displacements stay
-// float). The sources of all time levels are formed in one pass; v~ is
-// normalised by max|v~| (a device scalar, no host round trip) so no stored
-// value can overflow, and the assembly multiplies the scale back in.
-int run_matvec_mixed(claire_ctx* c, const float* vt, float* out, const float* reg_part,
-                     int dot_slot, bool scale_ready) {
-    const Geo& g = c->g;
-    const long long n = g.n;
-    const int nt = c->nt;
-    const double ht = 1.0 / nt;
-    const double* scale = c->red.result + kScaleSlot;
-    const bool fork = !reg_part;
-    if (fork) CL_TRY(fork_reg(c, vt));
-    if (!scale_ready) CL_TRY(red_absmax(c->red, vt, 3 * n, kScaleSlot, c->s));
-    CL_TRY(launch_mixed_sources(g, c->gm16, vt, scale, c->f16, c->w0, nt, c->s));
-    float* src = c->w0;
-    float* nxt = c->w1;
-    for (int j = 0; j < nt; ++j) {
-        const __half* fnext = c->f16 + (long long)(j + 1) * n;
-        if (j + 1 < nt) {
-            CL_TRY(launch_inc_state_step_mixed(g, src, c->dp, fnext, nxt, (float)ht, 1.0f, c->s,
-                                               c->box_p));
-            float* t = src;
-            src = nxt;
-            nxt = t;
-        } else {
-            CL_TRY(launch_inc_state_step_mixed(g, src, c->dp, fnext, c->lam + (long long)nt * n,
-                                               (float)(0.5 * ht), -1.0f, c->s, c->box_p));
-        }
-    }
-    for (int j = nt - 1; j >= 0; --j)
-        CL_TRY(launch_adjoint_step(g, c->lam + (long long)(j + 1) * n, c->dm, c->A,
-                                   c->lam + (long long)j * n, c->s, c->box_m));
-    if (fork) {
-        CL_TRY(join_reg(c));
-        reg_part = c->tmp3;
-    }
-    if (c->beta > 0.0) {
-        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, nullptr, c->ni_tmp, c->s));
-        return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
-    }
-    if (dot_slot >= 0)
-        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, reg_part, out, c->s, vt,
-                                 &c->red, dot_slot));
-    else
-        CL_TRY(launch_assemble_h(g, c->lam, c->gm16, nt, scale, reg_part, out, c->s));
-    return 0;
+int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
+               int dot_slot = -1) {
+    if (c->precision == 1) return matvec_steps(c, c->gm16, vt, out, reg_part, dot_slot);
+    return matvec_steps(c, c->gm, vt, out, reg_part, dot_slot);
 }
 
 // Objective of a trial velocity held in c->v: backtrace, state, mismatch.
@@ -554,10 +503,8 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
     }
     bool converged = false;
-    bool scale_ready = false;   // max|s| already reduced by the direction update
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0,   // <s, Hs> -> slot 0
-                          scale_ready));
+        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
         ++res.its;
         CL_TRY(red_fetch(c->red, s));
         const double shs = c->red.host[0];
@@ -596,11 +543,9 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         const double rz_new = c->red.host[2];
         const double mu = rz_new / rz;
         for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
-        // v~ += kappa s, s = z + mu s; the mixed matvec scales its float16
-        // sources by max|s|, reduced in the same pass
-        CL_TRY(launch_pcg_direction(c->precision == 1 ? &c->red : nullptr, c->z, c->sd,
-                                    (float)mu, c->vt, (float)kappa, n3, kScaleSlot, s));
-        scale_ready = c->precision == 1;
+        // v~ += kappa s, s = z + mu s
+        CL_TRY(launch_pcg_direction(nullptr, c->z, c->sd, (float)mu, c->vt, (float)kappa, n3,
+                                    0, s));
         if (!two) CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
         rz = rz_new;
     }

@@ -153,30 +153,25 @@ int launch_final_adjoint(const Geo& g, const float* mT, const float* m1, float* 
                          hipStream_t s);
 int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus,
                         const float* A, float* lam, hipStream_t s, const int* boxes = nullptr);
-int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt,
-                           float* w0, double ht, hipStream_t s);
+// Hessian matvec kernels; GT is the storage type of grad m^j: float, or
+// __half in the mixed-precision matvec (arithmetic in float either way).
+// w^0 = -(h_t/2) grad m^0 . v~
+template <typename GT>
+int launch_inc_state_first(const Geo& g, const GT* gradm0, const float* vt, float* w0,
+                           double ht, hipStream_t s);
+// out = sign (w_prev(y+) + coef f), f = -grad m^{j+1} . v~ formed on the grid
+template <typename GT>
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
-                          const float* gradm_next, const float* vt, float* out,
-                          float coef, float sign, hipStream_t s, const int* boxes = nullptr);
+                          const GT* gradm_next, const float* vt, float* out, float coef,
+                          float sign, hipStream_t s, const int* boxes = nullptr);
 // out = add + h_t sum_j c_j lam^j grad m^j; with dot_with (nullable), also
 // <dot_with, out> summed into red.result[slot]
-int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt,
+template <typename GT>
+int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt,
                     const float* add, float* out, hipStream_t s,
                     const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
-// Mixed precision for the Hessian matvec: grad m^j and the incremental
-// sources f^j in half, everything else float.
+// float16 copy of grad m^j for the mixed-precision matvec
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s);
-// f^j = -grad m^j . v~ / scale (j >= 1, half) and w^0 = (h_t/2) f^0 (float);
-// scale: device double
-int launch_mixed_sources(const Geo& g, const __half* gm, const float* vt, const double* scale,
-                         __half* f, float* w0, int nt, hipStream_t s);
-int launch_inc_state_step_mixed(const Geo& g, const float* w_prev, const float* dplus,
-                                const __half* f_next, float* out, float coef, float sign,
-                                hipStream_t s, const int* boxes);
-// out = add + scale h_t sum_j c_j lam^j grad m^j (+ <dot_with, out> into red slot)
-int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int nt,
-                      const double* scale, const float* add, float* out, hipStream_t s,
-                      const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
 
 // one RK2 step of the deformation-gradient transport from gathered F_y, G_y
 // (Fy NULL: F^0 = I); F may alias Fy

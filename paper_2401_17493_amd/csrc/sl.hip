@@ -232,8 +232,9 @@ struct EpiScale {        // out = A u  (continuity-equation step along -v)
     __device__ Pre load(unsigned i) const { return Pre{ldi(A, i)}; }
     __device__ void store(unsigned i, float u, const Pre& p) const { sti(out, i, p.a * u); }
 };
+template <typename GT>      // GT: storage of grad m (float, or half in the mixed matvec)
 struct EpiIncState {     // out = sign (u + coef f), f = -grad m . v~
-    const float* gm;
+    const GT* gm;
     const float* vt;
     float* out;
     long long n;
@@ -255,19 +256,6 @@ struct EpiMakeA {        // out = 1 + (h_t/2)(D(y-) + D + h_t D(y-) D)
     __device__ Pre load(unsigned i) const { return Pre{ldi(D, i)}; }
     __device__ void store(unsigned i, float u, const Pre& p) const {
         sti(out, i, 1.0f + 0.5f * ht * (u + p.dx + ht * u * p.dx));
-    }
-};
-
-// Mixed precision: incremental-state step whose grid source f^{j+1} is
-// stored in half (float arithmetic, float gathered field and output).
-struct EpiIncStateMixed {    // out = sign (u + coef f)
-    const __half* f;
-    float* out;
-    float coef, sign;
-    struct Pre { float f; };
-    __device__ Pre load(unsigned i) const { return Pre{ldi(f, i)}; }
-    __device__ void store(unsigned i, float u, const Pre& p) const {
-        sti(out, i, sign * (u + coef * p.f));
     }
 };
 
@@ -712,21 +700,23 @@ __global__ __launch_bounds__(kThreads) void k_final_adjoint(const float* __restr
     if (idx < n) lam[idx] = m1[idx] - mT[idx];
 }
 
-// w^0 = (h_t/2) f^0 with f^0 = -grad m^0 . v~
-__global__ __launch_bounds__(kThreads) void k_inc_first(const float* __restrict__ gm,
+// w^0 = (h_t/2) f^0 with f^0 = -grad m^0 . v~ (grad m stored as GT)
+template <typename GT>
+__global__ __launch_bounds__(kThreads) void k_inc_first(const GT* __restrict__ gm,
                                                         const float* __restrict__ vt,
                                                         float* __restrict__ w, long long n,
                                                         float half_ht) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= n) return;
-    const float f = gm[idx] * vt[idx] + gm[n + idx] * vt[n + idx] + gm[2 * n + idx] * vt[2 * n + idx];
+    const float f = ldf(gm + idx) * vt[idx] + ldf(gm + n + idx) * vt[n + idx] +
+                    ldf(gm + 2 * n + idx) * vt[2 * n + idx];
     w[idx] = -half_ht * f;
 }
 
 // out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2)
-template <bool DOT>
+template <bool DOT, typename GT>
 __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__ lam,
-                                                       const float* __restrict__ gm, int nt,
+                                                       const GT* __restrict__ gm, int nt,
                                                        const float* __restrict__ add,
                                                        float* __restrict__ out, long long n,
                                                        float ht, const float* __restrict__ dv,
@@ -738,10 +728,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__
         for (int j = 0; j <= nt; ++j) {
             const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
             const float l = c * lam[(long long)j * n + idx];
-            const float* gj = gm + (long long)j * 3 * n;
-            acc0 = fmaf(l, gj[idx], acc0);
-            acc1 = fmaf(l, gj[n + idx], acc1);
-            acc2 = fmaf(l, gj[2 * n + idx], acc2);
+            const GT* gj = gm + (long long)j * 3 * n;
+            acc0 = fmaf(l, ldf(gj + idx), acc0);
+            acc1 = fmaf(l, ldf(gj + n + idx), acc1);
+            acc2 = fmaf(l, ldf(gj + 2 * n + idx), acc2);
         }
         if (add) {
             acc0 += add[idx];
@@ -815,30 +805,6 @@ __global__ __launch_bounds__(kThreads) void k_det(const float* __restrict__ F,
 }
 
 // ----------------------------------------------------------- mixed precision
-// Incremental-state sources for all time levels in one pass:
-// f^j = -grad m^j . v~ / sc (j = 1..nt, stored in half) and
-// w^0 = (h_t/2) f^0 (float); sc = max|v~| (device scalar) keeps every stored
-// value O(|grad m|), far inside the half range.
-__global__ __launch_bounds__(kThreads) void k_mixed_sources(const __half* __restrict__ gm,
-                                                            const float* __restrict__ vt,
-                                                            const double* __restrict__ scale,
-                                                            __half* __restrict__ f,
-                                                            float* __restrict__ w0, int nt,
-                                                            long long n, float half_ht) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= n) return;
-    const double sc = *scale;
-    const float inv = sc > 0.0 ? (float)(1.0 / sc) : 0.f;
-    const float v0 = vt[idx] * inv, v1 = vt[n + idx] * inv, v2 = vt[2 * n + idx] * inv;
-    for (int j = 0; j <= nt; ++j) {
-        const __half* gj = gm + (long long)j * 3 * n;
-        const float fj = -(__half2float(gj[idx]) * v0 + __half2float(gj[n + idx]) * v1 +
-                           __half2float(gj[2 * n + idx]) * v2);
-        if (j == 0) w0[idx] = half_ht * fj;
-        else f[(long long)j * n + idx] = __float2half(fj);
-    }
-}
-
 // 8-byte stores of four halves (round to nearest, as __float2half)
 __device__ __forceinline__ uint2 pack_h4(const float o[4]) {
     const __half2 lo = __floats2half2_rn(o[0], o[1]);
@@ -856,51 +822,6 @@ __global__ __launch_bounds__(kThreads) void k_to_half4(const float4* __restrict_
     const float4 v = x[q];
     const float o[4] = {v.x, v.y, v.z, v.w};
     y[q] = pack_h4(o);
-}
-
-// out = add + sc h_t sum_j c_j lam^j grad m^j with grad m^j in half; optional
-// <dv, out> per block.
-template <bool DOT>
-__global__ __launch_bounds__(kThreads) void k_assemble_h(const float* __restrict__ lam,
-                                                         const __half* __restrict__ gm, int nt,
-                                                         const float* __restrict__ add,
-                                                         float* __restrict__ out, long long n,
-                                                         float ht, const double* __restrict__ scale,
-                                                         const float* __restrict__ dv,
-                                                         double* __restrict__ partial) {
-    const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-    double dot = 0.0;
-    if (idx < n) {
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-        for (int j = 0; j <= nt; ++j) {
-            const float c = (j == 0 || j == nt) ? 0.5f * ht : ht;
-            const float l = c * lam[(long long)j * n + idx];
-            const __half* gj = gm + (long long)j * 3 * n;
-            acc0 = fmaf(l, __half2float(gj[idx]), acc0);
-            acc1 = fmaf(l, __half2float(gj[n + idx]), acc1);
-            acc2 = fmaf(l, __half2float(gj[2 * n + idx]), acc2);
-        }
-        const float sc = (float)*scale;
-        acc0 *= sc;
-        acc1 *= sc;
-        acc2 *= sc;
-        if (add) {
-            acc0 += add[idx];
-            acc1 += add[n + idx];
-            acc2 += add[2 * n + idx];
-        }
-        out[idx] = acc0;
-        out[n + idx] = acc1;
-        out[2 * n + idx] = acc2;
-        if (DOT)
-            dot = (double)dv[idx] * acc0 + (double)dv[n + idx] * acc1 +
-                  (double)dv[2 * n + idx] * acc2;
-    }
-    if (DOT) {
-        __shared__ double sh[4];
-        const double t = block_sum_256(dot, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x] = t;
-    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_to_half(const float* __restrict__ x,
@@ -975,35 +896,52 @@ int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus
     return launch_gather_lds(g, lam_next, dminus, boxes, EpiScale{A, lam}, s);
 }
 
-int launch_inc_state_first(const Geo& g, const float* gradm0, const float* vt, float* w0,
+template <typename GT>
+int launch_inc_state_first(const Geo& g, const GT* gradm0, const float* vt, float* w0,
                            double ht, hipStream_t s) {
-    hipLaunchKernelGGL(k_inc_first, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0, vt, w0,
-                       g.n, (float)(0.5 * ht));
+    hipLaunchKernelGGL(k_inc_first<GT>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0, vt,
+                       w0, g.n, (float)(0.5 * ht));
     CL_LAUNCH_CHECK();
     return 0;
 }
+template int launch_inc_state_first<float>(const Geo&, const float*, const float*, float*,
+                                           double, hipStream_t);
+template int launch_inc_state_first<__half>(const Geo&, const __half*, const float*, float*,
+                                            double, hipStream_t);
 
+template <typename GT>
 int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
-                          const float* gradm_next, const float* vt, float* out, float coef,
+                          const GT* gradm_next, const float* vt, float* out, float coef,
                           float sign, hipStream_t s, const int* boxes) {
     return launch_gather_lds(g, w_prev, dplus, boxes,
-                             EpiIncState{gradm_next, vt, out, g.n, coef, sign}, s);
+                             EpiIncState<GT>{gradm_next, vt, out, g.n, coef, sign}, s);
 }
+template int launch_inc_state_step<float>(const Geo&, const float*, const float*, const float*,
+                                          const float*, float*, float, float, hipStream_t,
+                                          const int*);
+template int launch_inc_state_step<__half>(const Geo&, const float*, const float*,
+                                           const __half*, const float*, float*, float, float,
+                                           hipStream_t, const int*);
 
-int launch_assemble(const Geo& g, const float* lam, const float* gradm, int nt, const float* add,
+template <typename GT>
+int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt, const float* add,
                     float* out, hipStream_t s, const float* dot_with, Reducer* red, int slot) {
     const unsigned nb = blocks_for(g.n);
     if (dot_with) {
-        hipLaunchKernelGGL(k_assemble<true>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
-                           out, g.n, (float)(1.0 / nt), dot_with, red->partial);
+        hipLaunchKernelGGL((k_assemble<true, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt,
+                           add, out, g.n, (float)(1.0 / nt), dot_with, red->partial);
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
     }
-    hipLaunchKernelGGL(k_assemble<false>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add, out,
-                       g.n, (float)(1.0 / nt), nullptr, nullptr);
+    hipLaunchKernelGGL((k_assemble<false, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt,
+                       add, out, g.n, (float)(1.0 / nt), nullptr, nullptr);
     CL_LAUNCH_CHECK();
     return 0;
 }
+template int launch_assemble<float>(const Geo&, const float*, const float*, int, const float*,
+                                    float*, hipStream_t, const float*, Reducer*, int);
+template int launch_assemble<__half>(const Geo&, const float*, const __half*, int, const float*,
+                                     float*, hipStream_t, const float*, Reducer*, int);
 
 int brick_table_ints(const Geo& g) { return 6 * gather_brick(g).nbricks; }
 
@@ -1013,37 +951,6 @@ int launch_to_half(const float* x, __half* y, long long n, hipStream_t s) {
                            reinterpret_cast<const float4*>(x), reinterpret_cast<uint2*>(y), n / 4);
     else
         hipLaunchKernelGGL(k_to_half, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
-    CL_LAUNCH_CHECK();
-    return 0;
-}
-
-int launch_mixed_sources(const Geo& g, const __half* gm, const float* vt, const double* scale,
-                         __half* f, float* w0, int nt, hipStream_t s) {
-    hipLaunchKernelGGL(k_mixed_sources, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gm, vt, scale,
-                       f, w0, nt, g.n, (float)(0.5 / nt));
-    CL_LAUNCH_CHECK();
-    return 0;
-}
-
-int launch_inc_state_step_mixed(const Geo& g, const float* w_prev, const float* dplus,
-                                const __half* f_next, float* out, float coef, float sign,
-                                hipStream_t s, const int* boxes) {
-    return launch_gather_lds(g, w_prev, dplus, boxes, EpiIncStateMixed{f_next, out, coef, sign},
-                             s);
-}
-
-int launch_assemble_h(const Geo& g, const float* lam, const __half* gradm, int nt,
-                      const double* scale, const float* add, float* out, hipStream_t s,
-                      const float* dot_with, Reducer* red, int slot) {
-    const unsigned nb = blocks_for(g.n);
-    if (dot_with) {
-        hipLaunchKernelGGL(k_assemble_h<true>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
-                           out, g.n, (float)(1.0 / nt), scale, dot_with, red->partial);
-        CL_LAUNCH_CHECK();
-        return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
-    }
-    hipLaunchKernelGGL(k_assemble_h<false>, dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt, add,
-                       out, g.n, (float)(1.0 / nt), scale, nullptr, nullptr);
     CL_LAUNCH_CHECK();
     return 0;
 }
