@@ -14,11 +14,11 @@
  * Grid:    n1 x n2 x n3 nodes x_i = i * 2*pi / n_a (Section 2.5.1), each
  *          extent in [8, 1024]. n3 (the contiguous axis) must be a power of
  *          two; n1 and n2 may be any even product of 2, 3 and 5 (e.g. the
- *          256 x 300 x 256 grid of the paper's NIREP runs). Grids with every
- *          extent a power of two run the LDS-staged gathers and fused FFT
- *          passes; other grids run direct gathers with a modulo wrap and
- *          mixed-radix (4, 2, 3, 5) column transforms. The warm-start network
- *          (claire_net.h) takes power-of-two grids only.
+ *          256 x 300 x 256 grid of the paper's NIREP runs). Every grid runs
+ *          the LDS-staged gathers (ragged bricks and a wrapped stencil on
+ *          extents other than powers of two); power-of-two grids run fused
+ *          FFT passes, others mixed-radix (4, 2, 3, 5) column transforms. The
+ *          warm-start network (claire_net.h) takes power-of-two grids only.
  * Layout:  scalar fields are float32, C-contiguous [n1][n2][n3] (x3 fastest);
  *          vector fields are structure-of-arrays [3][n1][n2][n3].
  * Memory:  every float/double array argument is a DEVICE pointer unless its

@@ -6,8 +6,10 @@
 // origin floor(d) is exact and a zero displacement returns grid values
 // bit-for-bit. One thread per output voxel, x3 fastest across the wavefront;
 // the 4x4x4 stencil is read with wrapped indices: a mask when the extents are
-// powers of two (the LDS-staged kernels), a modulo along x1 and x2 on grids
-// with other extents (direct gathers, below).
+// powers of two, a wrap by subtraction (box staging) or modulo (direct
+// gathers) along x1 and x2 on grids with other extents. Single-field gathers
+// and the backtrace are LDS-staged on every grid (ragged bricks on general
+// ones); multi-field interpolation reads its stencils directly.
 
 #include "internal.h"
 
