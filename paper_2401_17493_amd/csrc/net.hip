@@ -145,6 +145,99 @@ __global__ __launch_bounds__(256) void k_conv(ConvIn in, const bf16* __restrict_
     }
 }
 
+// Output element of a convolution tile (shared by both convolution kernels).
+template <int EPI>
+__device__ __forceinline__ void conv_store(const ConvOut& out, int cout, long long mo, int co,
+                                           float a) {
+    if (EPI == EPI_ACT) {
+        const float z = a + (out.bias ? out.bias[co] : 0.f);
+        out.y16[(size_t)mo * cout + co] = (bf16)(z > 0.f ? z : kLeak * z);
+    } else if (EPI == EPI_LINEAR) {
+        out.y32[(size_t)mo * cout + co] = a + (out.bias ? out.bias[co] : 0.f);
+    } else if (EPI == EPI_ACT32) {
+        const float z = a + (out.bias ? out.bias[co] : 0.f);
+        out.y32[(size_t)mo * cout + co] = z > 0.f ? z : kLeak * z;
+    } else if (EPI == EPI_DGRAD_ACT) {
+        out.y16[(size_t)mo * cout + co] = (bf16)(a * slope(out.yprev[(size_t)mo * cout + co]));
+    } else {
+        if (co < out.csplit) out.y32[(size_t)mo * out.csplit + co] = a;
+        else out.y32b[(size_t)mo * (cout - out.csplit) + (co - out.csplit)] = a;
+    }
+}
+
+// Halo-staged implicit GEMM for grids of at least 4^3: a workgroup owns a
+// 4 x 4 x 4 brick of one batch item (64 voxels, 16 per wave) and 64 output
+// channels. The brick's periodic 6 x 6 x 6 neighbourhood with all cin input
+// channels is copied into LDS once (16-byte loads through the same input
+// view as k_conv: concatenation and nearest upsampling), and the A
+// fragments of all 27 taps are read from there: each input value is fetched
+// from global memory ~3.4 times per brick instead of 27 times per voxel.
+// Same K order (k = t cin + ci), MFMA and epilogues as k_conv.
+constexpr int kHaloPos = 216;
+constexpr int kHaloMaxC = 144;                 // input channels the LDS tile may hold (62 KB)
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __restrict__ wt,
+                                                   int kpad, int nrows, int cout, int l,
+                                                   ConvOut out) {
+    extern __shared__ __align__(16) bf16 halo[];   // [216][cin]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int lb = l - 2;                      // log2 of bricks per axis
+    const int bid = blockIdx.x;
+    const int o3 = (bid & ((1 << lb) - 1)) << 2;
+    const int o2 = ((bid >> lb) & ((1 << lb) - 1)) << 2;
+    const int o1 = ((bid >> (2 * lb)) & ((1 << lb) - 1)) << 2;
+    const int bb = bid >> (3 * lb);
+    const int n0 = blockIdx.y * 64;
+    const int cin = in.ca + in.cb;
+    const int c8 = cin >> 3;                   // 16-byte channel groups per voxel
+    // stage the neighbourhood: position p = (a, b, c) in 6^3, voxel o + (a, b, c) - 1
+    for (int e = threadIdx.x; e < kHaloPos * c8; e += 256) {
+        const int p = e / c8, cg = e - p * c8;
+        const int a = p / 36, b = (p / 6) % 6, c = p % 6;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+            in_ptr(in, l, bb, (o1 + a - 1) & mask, (o2 + b - 1) & mask, (o3 + c - 1) & mask,
+                   8 * cg));
+        *reinterpret_cast<bf16x8*>(halo + p * cin + 8 * cg) = v;
+    }
+    __syncthreads();
+    // this lane's A row: brick voxel (wave, li / 4, li % 4)
+    const int prow = wave * 36 + (li >> 2) * 6 + (li & 3);
+    int t = 0, ci = 8 * g;
+    while (ci >= cin) { ci -= cin; ++t; }
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < kpad; kc += 32) {
+        bf16x8 av = {};
+        if (t < 27) {
+            const int pt = (t / 9) * 36 + ((t / 3) % 3) * 6 + t % 3;
+            av = *reinterpret_cast<const bf16x8*>(halo + (prow + pt) * cin + ci);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int r0 = n0 + nt * 16;
+            if (r0 < nrows) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(
+                    wt + (size_t)(r0 + li) * kpad + kc + 8 * g);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+            }
+        }
+        ci += 32;
+        while (ci >= cin) { ci -= cin; ++t; }
+    }
+    // results: rows 4 g + r of the wave's 16 voxels = brick voxel (wave, g, r)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int co = n0 + nt * 16 + li;
+        if (n0 + nt * 16 >= nrows || co >= cout) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            conv_store<EPI>(out, cout, vox(bb, o1 + wave, o2 + g, o3 + r, l), co, acc[nt][r]);
+    }
+}
+
 // Weight-gradient GEMM: partial[s][row][k] = sum over the voxels of split s
 // of dz[m][row] x(m + o_t)[ci], k = t cin + ci. A workgroup covers 16 rows x
 // 256 columns (64 per wave, 4 MFMA tiles), grid (rowtiles * ktiles, splits);
@@ -710,12 +803,25 @@ int reset_adam(claire_net* n) {
     return 0;
 }
 
+#ifndef CLAIRE_CONV_HALO
+#define CLAIRE_CONV_HALO 1
+#endif
+
 template <int EPI>
 int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
          const ConvOut& out, hipStream_t s) {
+    const int cin = in.ca + in.cb;
     const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64));
-    hipLaunchKernelGGL(k_conv<EPI>, grid, dim3(256), 0, s, in, wt, kpad, nrows, cout, l,
-                       (int)mtot, out);
+    // the halo kernel tiles the grid by 4^3 bricks (mtot = batch 8^l is a multiple of 64)
+    if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
+        (mtot & 63) == 0) {
+        const size_t lds = sizeof(bf16) * kHaloPos * cin;
+        hipLaunchKernelGGL(k_conv_halo<EPI>, grid, dim3(256), lds, s, in, wt, kpad, nrows, cout,
+                           l, out);
+    } else {
+        hipLaunchKernelGGL(k_conv<EPI>, grid, dim3(256), 0, s, in, wt, kpad, nrows, cout, l,
+                           (int)mtot, out);
+    }
     CL_LAUNCH_CHECK();
     return 0;
 }
