@@ -95,6 +95,7 @@ struct claire_ctx {
     // and joined with the two events
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<hipEvent_t> ev_state;   // [nt + 1]: state m^j written (setup overlap)
     double cell = 0;   // h1 h2 h3
 
     // per-velocity state
@@ -143,6 +144,7 @@ struct claire_ctx {
     int deriv = CLAIRE_DERIV_SPECTRAL;   // first-derivative discretisation
     bool have_images = false;
     bool state_valid = false;      // dp, dm, m valid for the content of v
+    bool gm0_valid = false;        // gm slot 0 holds grad m0 (independent of v)
     bool have_velocity = false;    // full setup done: gm, A, g, J valid
     double J = 0, Jdist = 0, Jreg = 0, gnorm = 0;
 
@@ -201,6 +203,8 @@ int ctx_alloc(claire_ctx* c) {
     CL_HIP(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
     CL_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     CL_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    c->ev_state.assign(c->nt + 1, nullptr);
+    for (auto& e : c->ev_state) CL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return 0;
 }
 
@@ -222,6 +226,8 @@ void ctx_release(claire_ctx* c) {
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : c->ev_state)
+        if (e) (void)hipEventDestroy(e);
 }
 
 int copy_d2d(float* dst, const float* src, long long count, hipStream_t s) {
@@ -230,18 +236,40 @@ int copy_d2d(float* dst, const float* src, long long count, hipStream_t s) {
     return 0;
 }
 
+// First derivatives with the context's discretisation (Section 2.5.3), on
+// stream st.
+int ctx_grad(claire_ctx* c, const float* u, float* out, hipStream_t st) {
+    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_grad(c->g, u, out, st);
+    return spectral_apply(c->g, c->sw, SPEC_GRAD, u, out, c->alpha, c->p, st);
+}
+int ctx_div(claire_ctx* c, const float* v, float* out, hipStream_t st) {
+    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_div(c->g, v, out, st);
+    return spectral_apply(c->g, c->sw, SPEC_DIV, v, out, c->alpha, c->p, st);
+}
+
+// grad m^j on the side stream once the main stream has written m^j
+int side_grad(claire_ctx* c, int j) {
+    const long long n = c->g.n;
+    CL_HIP(hipEventRecord(c->ev_state[j], c->s));
+    CL_HIP(hipStreamWaitEvent(c->s2, c->ev_state[j], 0));
+    return ctx_grad(c, c->m + (long long)j * n, c->gm + (long long)j * 3 * n, c->s2);
+}
+
 // Backtrace and state solve for the velocity held in c->v (Section 2.5.2,
-// eq. e:transport): m^0 = m0, m^{j+1} = m^j(y+).
-int run_state(claire_ctx* c) {
+// eq. e:transport): m^0 = m0, m^{j+1} = m^j(y+). grads_on_side: hand each
+// new m^j to the side stream for its gradient (the setup's overlap).
+int run_state(claire_ctx* c, bool grads_on_side = false) {
     const Geo& g = c->g;
     const double ht = 1.0 / c->nt;
     CL_TRY(launch_backtrace(g, c->v, c->dp, c->dm, ht, c->s));
     CL_TRY(launch_brick_boxes(g, c->dp, c->box_p, c->s));
     CL_TRY(launch_brick_boxes(g, c->dm, c->box_m, c->s));
     CL_TRY(copy_d2d(c->m, c->m0, g.n, c->s));
-    for (int j = 0; j < c->nt; ++j)
+    for (int j = 0; j < c->nt; ++j) {
         CL_TRY(launch_interp(g, c->m + (long long)j * g.n, 1, c->dp, c->m + (long long)(j + 1) * g.n,
                              c->s, c->box_p));
+        if (grads_on_side) CL_TRY(side_grad(c, j + 1));
+    }
     c->state_valid = true;
     return 0;
 }
@@ -261,31 +289,36 @@ int ensure_half_buffers(claire_ctx* c) {
 
 // Full per-velocity setup; the state is reused when state_valid says the
 // backtrace and m^j already belong to c->v (accepted line-search trial).
-// First derivatives with the context's discretisation (Section 2.5.3).
-int ctx_grad(claire_ctx* c, const float* u, float* out) {
-    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_grad(c->g, u, out, c->s);
-    return spectral_apply(c->g, c->sw, SPEC_GRAD, u, out, c->alpha, c->p, c->s);
-}
-int ctx_div(claire_ctx* c, const float* v, float* out) {
-    if (c->deriv == CLAIRE_DERIV_FD8) return launch_fd8_div(c->g, v, out, c->s);
-    return spectral_apply(c->g, c->sw, SPEC_DIV, v, out, c->alpha, c->p, c->s);
-}
 
 int run_setup(claire_ctx* c) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
     const double ht = 1.0 / nt;
-    if (!c->state_valid) CL_TRY(run_state(c));
+    // The Fourier work runs on the side stream beside the state solve's
+    // gathers: alpha L v, div v and grad m0 (which does not depend on v and is
+    // kept across setups) at once, grad m^j (Section 2.5.3; stored, not
+    // recomputed per matvec) as soon as m^j exists.
+    CL_HIP(hipEventRecord(c->ev_fork, c->s));
+    CL_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    CL_TRY(spectral_apply(g, c->sw, SPEC_REG, c->v, c->regv, c->alpha, c->p, c->s2));
+    CL_TRY(ctx_div(c, c->v, c->divv, c->s2));
+    if (!c->gm0_valid) {
+        CL_TRY(ctx_grad(c, c->m0, c->gm, c->s2));
+        c->gm0_valid = true;
+    }
+    if (!c->state_valid) {
+        CL_TRY(run_state(c, true));
+    } else {
+        for (int j = 1; j <= nt; ++j)
+            CL_TRY(ctx_grad(c, c->m + (long long)j * n, c->gm + (long long)j * 3 * n, c->s2));
+    }
+    CL_HIP(hipEventRecord(c->ev_join, c->s2));
     // objective parts: 1/2 ||m^nt - m1||^2 and 1/2 <alpha L v, v>
     CL_TRY(red_sumsq_diff(c->red, c->m + nt * n, c->m1, n, 0, c->s));
-    CL_TRY(spectral_apply(g, c->sw, SPEC_REG, c->v, c->regv, c->alpha, c->p, c->s));
+    CL_HIP(hipStreamWaitEvent(c->s, c->ev_join, 0));
     CL_TRY(red_dot(c->red, c->regv, c->v, 3 * n, 1, c->s));
-    // grad m^j (Section 2.5.3; stored, not recomputed per matvec)
-    for (int j = 0; j <= nt; ++j)
-        CL_TRY(ctx_grad(c, c->m + (long long)j * n, c->gm + (long long)j * 3 * n));
-    // div v and the adjoint step factor
-    CL_TRY(ctx_div(c, c->v, c->divv));
+    // the adjoint step factor
     CL_TRY(launch_make_A(g, c->divv, c->dm, c->A, ht, c->s, c->box_m));
     // adjoint (eq. e:adjoint): lam^nt = -(m^nt - m1), lam^j = A lam^{j+1}(y-)
     CL_TRY(launch_final_adjoint(g, c->m + nt * n, c->m1, c->lam + nt * n, c->s));
@@ -787,6 +820,7 @@ int claire_ctx_set_images(claire_ctx* c, const float* m0, const float* m1) {
     c->have_images = true;
     c->state_valid = false;
     c->have_velocity = false;
+    c->gm0_valid = false;
     return 0;
 }
 
@@ -905,11 +939,15 @@ int claire_ctx_solve(claire_ctx* c, const claire_opts* opts, float* v_inout,
     const int saved_deriv = c->deriv;
     const double saved_beta = c->beta;
     c->precision = o.precision;
+    if (o.derivative != c->deriv) c->gm0_valid = false;
     c->deriv = o.derivative;
     c->beta = o.beta;
     const int rc = run_solve(c, o, v_inout, stats);
     c->precision = saved;
-    if (c->deriv != saved_deriv) c->have_velocity = false;   // setup used the other operators
+    if (c->deriv != saved_deriv) {   // setup used the other operators
+        c->have_velocity = false;
+        c->gm0_valid = false;
+    }
     c->deriv = saved_deriv;
     if (c->beta != saved_beta) c->have_velocity = false;
     c->beta = saved_beta;
@@ -936,7 +974,10 @@ int claire_ctx_set_derivative(claire_ctx* c, int derivative) {
         set_error("derivative must be CLAIRE_DERIV_SPECTRAL or CLAIRE_DERIV_FD8");
         return CLAIRE_EINVAL;
     }
-    if (derivative != c->deriv) c->have_velocity = false;   // redo the setup
+    if (derivative != c->deriv) {   // redo the setup, grad m0 included
+        c->have_velocity = false;
+        c->gm0_valid = false;
+    }
     c->deriv = derivative;
     return 0;
 }
@@ -998,7 +1039,7 @@ int claire_ctx_detdefgrad(claire_ctx* c, double* det_out, double stats[4]) {
     }
     const double ht = 1.0 / c->nt;
     for (int a = 0; a < 3 && rc >= 0; ++a)
-        rc = ctx_grad(c, c->v + (long long)a * n, G + (long long)a * 3 * n);
+        rc = ctx_grad(c, c->v + (long long)a * n, G + (long long)a * 3 * n, c->s);
     for (int q = 0; q < 9 && rc >= 0; ++q)
         rc = launch_interp(g, G + (long long)q * n, 1, c->dp, Gy + (long long)q * n, c->s, c->box_p);
     if (rc >= 0) rc = launch_defgrad_update(g, nullptr, Gy, G, F, ht, c->s);
