@@ -52,9 +52,25 @@ HBM_PEAK_GBS = 8000.0
 #   adjoint step:   gather source (4), y- displacement (12), A (4), output (4);
 #   assembly:       lambda~^j (4 (nt+1)), grad m^j (12 (nt+1)), alpha L v~ (12), output (12);
 #   copy:           3 floats in, 3 floats out.
+#   backtrace:      v (12), y+ and y- displacements (24).
 def kernel_bytes_per_voxel(kernel, nt):
     return {"inc_state_step": 44, "adjoint_step": 24,
-            "assemble": 16 * (nt + 1) + 24, "copy": 24}[kernel]
+            "assemble": 16 * (nt + 1) + 24, "copy": 24, "backtrace": 36}[kernel]
+
+
+def kernel_table(ctx, C, nt, voxels, reps=20):
+    """Average launch time (HIP events on the context stream) and algorithmic
+    HBM rate of each hot-path kernel at the context's current velocity."""
+    ids = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
+           "assemble": C.KERNEL_ASSEMBLE, "backtrace": C.KERNEL_BACKTRACE,
+           "copy": C.KERNEL_COPY}
+    out = {}
+    for name, k in ids.items():
+        ms = ctx.time_kernel(k, reps=reps)
+        gbs = kernel_bytes_per_voxel(name, nt) * voxels / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "bytes_per_voxel": kernel_bytes_per_voxel(name, nt),
+                     "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 # HIP sources that define each timed kernel (its code and launch)
@@ -251,6 +267,9 @@ def main():
                     help="> 0: near-incompressible model with this divergence-penalty weight")
     ap.add_argument("--warmstart", default=WEIGHTS,
                     help="trained warm-start weights (.npz) or 'none'")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="matvec throughput and the kernel table only, at v = v*/2 (for "
+                         "workloads whose solve has no time-to-solution, e.g. 512^3)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up at v = v*/2 and launch only the roofline kernel and the copy "
                          "kernel (for hardware-counter runs); prints their timings")
@@ -296,6 +315,41 @@ def main():
         ctx.close()
         return
     precisions = {"mixed": [1], "fp32": [0], "both": [1, 0]}[args.precision]
+    if args.no_solve:
+        voxels = n[0] * n[1] * n[2]
+        rec = {"metric": METRIC, "value": None, "unit": "s", "n_gpus": 1, "steps": 0,
+               "warmup": 0, "higher_is_better": False, "dtype": "f32",
+               "data": "synthetic (seeded nested-ellipsoid phantom, band-limited v*)",
+               "config": {"workload": args.workload, "grid": list(n), "nt": nt,
+                          "alpha": alpha, "velocity": "v*/2"},
+               "note": "matvec throughput and kernel table only, no solve"}
+        vt = (0.5 * vstar).contiguous()
+        hv = torch.empty_like(vt)
+        for prec in precisions:
+            ctx.set_precision(prec)
+            ctx.set_velocity((0.5 * vstar).contiguous())
+            ctx.hessian_matvec(vt, hv)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            for _ in range(args.matvecs):
+                ctx.hessian_matvec(vt, hv)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / args.matvecs
+            fields = 29 + 21 * nt if prec == 0 else 18 * nt + 26
+            gbs = 4.0 * fields * voxels / (ms * 1e-3) / 1e9
+            rec["fp32" if prec == 0 else "mixed"] = {
+                "ms_per_matvec": round(ms, 3), "hessian_matvecs_per_s": round(1000.0 / ms, 2),
+                "matvec_roofline": {"fields": fields, "achieved": round(gbs, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        ctx.set_precision(0)
+        ctx.set_velocity((0.5 * vstar).contiguous())
+        rec["kernels"] = kernel_table(ctx, C, nt, voxels)
+        ctx.close()
+        print(json.dumps(rec), flush=True)
+        return
     net = None
     # the warm-start network takes power-of-two grids only
     pow2 = all(k & (k - 1) == 0 for k in n)
@@ -362,6 +416,7 @@ def main():
     achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
     ms_copy = ctx.time_kernel(C.KERNEL_COPY, reps=50)
     copy_gbs = 24 * voxels / (ms_copy * 1e-3) / 1e9
+    ktable = kernel_table(ctx, C, nt, voxels)
     print("kernel %s: %.4f ms/launch, %.0f GB/s algorithmic; copy kernel %.0f GB/s; "
           "matvec %.3f ms" % (args.roofline_kernel, ms_kernel, achieved, copy_gbs, ms_matvec),
           file=sys.stderr, flush=True)
@@ -432,6 +487,7 @@ def main():
         "ms_per_matvec": round(ms_matvec, 4),
         "matvec_roofline": matvec_roofline(head),
         "solve": solve_rec(head),
+        "kernels": ktable,
         "inputs": {"m1": "FP64 oracle transport of the clean phantom by v* (+ noise), "
                          "float32", "m1_sha256": m1_sha[:16],
                    "oracle_record": None if golden is None else

@@ -307,37 +307,66 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvIn in, const bf16* __restrict
     }
 }
 
-// pb[s][c] = sum over the voxels of split s of dz[m][c]
+// pb[s][c] = sum over the voxels of split s of dz[m][c]: the 256 threads
+// form (voxel lane, channel) pairs, channels fastest (coalesced rows), and
+// the voxel lanes are folded in a fixed tree.
 __global__ __launch_bounds__(256) void k_bias_partial(const bf16* __restrict__ dz, int cdz,
                                                       int mtot, int chunk,
                                                       float* __restrict__ pb) {
+    __shared__ float sh[256];
     const int s = blockIdx.x;
     const int mstart = s * chunk, mend = min(mtot, mstart + chunk);
-    for (int c = threadIdx.x; c < cdz; c += 256) {
-        float acc = 0.f;
-        for (int m = mstart; m < mend; ++m) acc += (float)dz[(size_t)m * cdz + c];
-        pb[(size_t)s * cdz + c] = acc;
+    if (cdz > 256) {                           // wider than a workgroup: one thread per channel
+        for (int c = threadIdx.x; c < cdz; c += 256) {
+            float acc = 0.f;
+            for (int m = mstart; m < mend; ++m) acc += (float)dz[(size_t)m * cdz + c];
+            pb[(size_t)s * cdz + c] = acc;
+        }
+        return;
     }
+    int cp = 1;
+    while (cp < cdz) cp <<= 1;                 // channel lanes
+    const int rows = 256 / cp;
+    const int c = threadIdx.x & (cp - 1), r = threadIdx.x / cp;
+    float acc = 0.f;
+    if (c < cdz)
+        for (int m = mstart + r; m < mend; m += rows) acc += (float)dz[(size_t)m * cdz + c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = rows >> 1; w > 0; w >>= 1) {
+        if (r < w) sh[threadIdx.x] += sh[threadIdx.x + w * cp];
+        __syncthreads();
+    }
+    if (r == 0 && c < cdz) pb[(size_t)s * cdz + c] = sh[c];
 }
 
-// gw[co][k] = sum_s partial[s][co][k] (co < cout, k < ktot), gb[co] = sum_s pb[s][co]
+// gw[co][k] = sum_s partial[s][co][k] (co < cout, k < ktot), gb[co] = sum_s pb[s][co]:
+// a workgroup takes 64 consecutive outputs, its 4 waves every 4th split, and
+// the 4 partial sums are added in a fixed order (float64 throughout).
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
                                                       const float* __restrict__ pb, int splits,
                                                       int nrows, int kpad, int cout, int ktot,
                                                       int cdz, float* __restrict__ gw,
                                                       float* __restrict__ gb) {
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    __shared__ double sh[256];
+    const long long idx = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int sg = threadIdx.x >> 6;
     const long long nw = (long long)cout * ktot;
+    double acc = 0.0;
     if (idx < nw) {
         const int co = (int)(idx / ktot), k = (int)(idx - (long long)co * ktot);
-        double acc = 0.0;
-        for (int s = 0; s < splits; ++s) acc += partial[((size_t)s * nrows + co) * kpad + k];
-        gw[idx] = (float)acc;
+        for (int s = sg; s < splits; s += 4) acc += partial[((size_t)s * nrows + co) * kpad + k];
     } else if (idx < nw + cout) {
         const int co = (int)(idx - nw);
-        double acc = 0.0;
-        for (int s = 0; s < splits; ++s) acc += pb[(size_t)s * cdz + co];
-        gb[co] = (float)acc;
+        for (int s = sg; s < splits; s += 4) acc += pb[(size_t)s * cdz + co];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (sg == 0) {
+        const int t = threadIdx.x;
+        const double sum = (sh[t] + sh[t + 64]) + (sh[t + 128] + sh[t + 192]);
+        if (idx < nw) gw[idx] = (float)sum;
+        else if (idx < nw + cout) gb[idx - nw] = (float)sum;
     }
 }
 
@@ -893,7 +922,8 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
                        chunk, n->pb);
     CL_LAUNCH_CHECK();
     const long long nw = (long long)L.cout * L.ktot;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + L.cout)), dim3(256), 0, n->s, n->partial,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + L.cout + 63) / 64)), dim3(256), 0,
+                       n->s, n->partial,
                        n->pb, splits, L.nrows, L.kpad, L.cout, L.ktot, L.coutE, n->g + L.off,
                        n->g + L.off + nw);
     CL_LAUNCH_CHECK();
@@ -1336,7 +1366,8 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
         hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout, (int)mt,
                            chunk, pb);
         const long long nw = (long long)cout * L.ktot;
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + cout)), dim3(256), 0, s, partial, pb,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + cout + 63) / 64)), dim3(256), 0,
+                           s, partial, pb,
                            splits, L.nrows, L.kpad, cout, L.ktot, cout, dw, db);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "weight gradient", __FILE__, __LINE__);
