@@ -307,6 +307,91 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvIn in, const bf16* __restrict
     }
 }
 
+// The same weight-gradient GEMM with both operands staged through LDS: per
+// step of 32 voxels, the workgroup copies dz^T (16 output channels x 32
+// voxels) and the transposed im2col block (its 256 k-columns x 32 voxels,
+// one 16-byte load of 8 channels per voxel and k-group) into LDS, so every
+// MFMA fragment is one 16-byte LDS read instead of eight 2-byte global
+// loads. Same grid, partial-sum layout and summation order per lane as
+// k_wgrad. Needs both input channel counts and cdz to be multiples of 8.
+__global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __restrict__ dz,
+                                                   int cdz, int l, int mtot, int kpad,
+                                                   int ktiles, int chunk,
+                                                   float* __restrict__ partial, int nrows) {
+    __shared__ __align__(16) bf16 sa[16 * 32];     // [co][m]
+    __shared__ __align__(16) bf16 sb[256 * 32];    // [k][m]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int row0 = (blockIdx.x / ktiles) * 16;
+    const int kblk = (blockIdx.x % ktiles) * 256;
+    const int split = blockIdx.y;
+    const int mstart = split * chunk;
+    const int mend = min(mtot, mstart + chunk);
+    const int cin = in.ca + in.cb;
+    const int ktot = 27 * cin;
+    // this thread's staging items: voxel lane mloc, k-groups kg = tid/32 + 8 q
+    const int mloc = threadIdx.x & 31;
+    int tq[4], cq[4];
+    bool kq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k0 = kblk + ((threadIdx.x >> 5) + 8 * q) * 8;
+        kq[q] = k0 < ktot;
+        tq[q] = kq[q] ? k0 / cin : 0;
+        cq[q] = k0 - tq[q] * cin;
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int mc = mstart; mc < mend; mc += 32) {
+        const int mm = mc + mloc;
+        const bool mv = mm < mend;
+        if (threadIdx.x < 64) {
+            const int m2 = mc + (threadIdx.x >> 1), cg = (threadIdx.x & 1) * 8;
+            bf16x8 v = {};
+            if (m2 < mend && row0 + cg < cdz)
+                v = *reinterpret_cast<const bf16x8*>(dz + (size_t)m2 * cdz + row0 + cg);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sa[(cg + j) * 32 + (threadIdx.x >> 1)] = v[j];
+        }
+        const int i3 = mm & mask, i2 = (mm >> l) & mask, i1 = (mm >> (2 * l)) & mask;
+        const int bb = mm >> (3 * l);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bf16x8 v = {};
+            if (mv && kq[q]) {
+                const int t = tq[q];
+                const int o1 = t / 9 - 1, o2 = (t / 3) % 3 - 1, o3 = t % 3 - 1;
+                v = *reinterpret_cast<const bf16x8*>(in_ptr(in, l, bb, (i1 + o1) & mask,
+                                                            (i2 + o2) & mask, (i3 + o3) & mask,
+                                                            cq[q]));
+            }
+            const int kr = ((threadIdx.x >> 5) + 8 * q) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sb[(kr + j) * 32 + mloc] = v[j];
+        }
+        __syncthreads();
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(sa + li * 32 + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (kblk + wave * 64 + nt * 16 >= kpad) continue;
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8*>(sb + (wave * 64 + nt * 16 + li) * 32 + 8 * g);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int kc = kblk + wave * 64 + nt * 16;
+        if (kc >= kpad) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            partial[((size_t)split * nrows + row0 + 4 * g + r) * kpad + kc + li] = acc[nt][r];
+    }
+}
+
 // pb[s][c] = sum over the voxels of split s of dz[m][c]: the 256 threads
 // form (voxel lane, channel) pairs, channels fastest (coalesced rows), and
 // the voxel lanes are folded in a fixed tree.
@@ -835,6 +920,10 @@ int reset_adam(claire_net* n) {
 #ifndef CLAIRE_CONV_HALO
 #define CLAIRE_CONV_HALO 1
 #endif
+#ifndef CLAIRE_WGRAD_LDS
+#define CLAIRE_WGRAD_LDS 1
+#endif
+constexpr bool kWgradLds = CLAIRE_WGRAD_LDS;
 
 template <int EPI>
 int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
@@ -915,8 +1004,12 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
     wgrad_split(mt, splits, chunk);
     const int ktiles = (L.kpad + 255) / 256;
     const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level, (int)mt,
-                       L.kpad, ktiles, chunk, n->partial, L.nrows);
+    if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0)
+        hipLaunchKernelGGL(k_wgrad_lds, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
+                           (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows);
+    else
+        hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
+                           (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows);
     CL_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, n->s, dz, L.coutE, (int)mt,
                        chunk, n->pb);
@@ -1360,9 +1453,13 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
     }
     if (rc >= 0) {
         const int ktiles = (L.kpad + 255) / 256;
-        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits),
-                           dim3(256), 0, s, one(S.x16, cin), S.dz16, cout, l, (int)mt, L.kpad,
-                           ktiles, chunk, partial, L.nrows);
+        const dim3 wgrid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
+        if (kWgradLds && cin % 8 == 0 && cout % 8 == 0)
+            hipLaunchKernelGGL(k_wgrad_lds, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16,
+                               cout, l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows);
+        else
+            hipLaunchKernelGGL(k_wgrad, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16, cout,
+                               l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows);
         hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout, (int)mt,
                            chunk, pb);
         const long long nw = (long long)cout * L.ktot;
