@@ -379,7 +379,9 @@ int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* re
 int fork_reg(claire_ctx* c, const float* vt) {
     CL_HIP(hipEventRecord(c->ev_fork, c->s));
     CL_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
-    CL_TRY(spectral_apply(c->g, c->sw, SPEC_REG, vt, c->tmp3, c->alpha, c->p, c->s2));
+    // the mixed matvec transforms in float32 (the gradient keeps SPEC_REG)
+    const SpecMode mode = c->precision == 1 ? SPEC_REG32 : SPEC_REG;
+    CL_TRY(spectral_apply(c->g, c->sw, mode, vt, c->tmp3, c->alpha, c->p, c->s2));
     CL_HIP(hipEventRecord(c->ev_join, c->s2));
     return 0;
 }

@@ -451,8 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_x1_reg64(const double2* __restrict
     }
 }
 
-// float32 multipliers: SPEC_REG_INV (per component, grid z = component),
-// SPEC_GRAD (1 -> 3), SPEC_DIV (3 -> 1). Column tiles along x1 for fixed k2.
+// float32 multipliers: SPEC_REG_INV, SPEC_REG_ISQRT and SPEC_REG32 (per
+// component, grid z = component), SPEC_GRAD (1 -> 3), SPEC_DIV (3 -> 1). Column tiles along x1 for fixed k2.
 template <int MODE, int E>
 __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict__ in,
                                                        float2* __restrict__ out, int l1, int CW,
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         }
     };
 
-    if (MODE == SPEC_REG_INV || MODE == SPEC_REG_ISQRT) {
+    if (MODE == SPEC_REG_INV || MODE == SPEC_REG_ISQRT || MODE == SPEC_REG32) {
         const int comp = bt.z;
         load_tile(A, in + comp * nspec);
         __syncthreads();
@@ -497,9 +497,12 @@ __global__ __launch_bounds__(kThreads) void k_x1_fused(const float2* __restrict_
         for (int e = tid; e < N * CW; e += kThreads) {
             const int r = e >> lcw, c = e & (CW - 1);
             const float sym = (float)reg_symbol(m.p, signed_k(r, m.n1), k2, c0 + c);
-            const float f = (sym == 0.f) ? norm
-                            : (MODE == SPEC_REG_INV ? norm / (alpha * sym)
-                                                    : norm / sqrtf(alpha * sym));
+            float f;
+            if (MODE == SPEC_REG32) f = norm * alpha * sym;
+            else
+                f = (sym == 0.f) ? norm
+                                 : (MODE == SPEC_REG_INV ? norm / (alpha * sym)
+                                                         : norm / sqrtf(alpha * sym));
             A[e] = cscale(A[e], f);
         }
         __syncthreads();
@@ -1321,8 +1324,8 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         return CLAIRE_EINVAL;
     }
     if (!g.pow2) {
-        static const int gm[] = {GM_GRAD, GM_DIV, GM_REG, GM_REG_INV, GM_REG_ISQRT};
-        if ((int)mode < 0 || (int)mode > 4) {
+        static const int gm[] = {GM_GRAD, GM_DIV, GM_REG, GM_REG_INV, GM_REG_ISQRT, GM_REG};
+        if ((int)mode < 0 || (int)mode > 5) {
             set_error("unknown spectral mode %d", (int)mode);
             return CLAIRE_EINVAL;
         }
@@ -1357,6 +1360,13 @@ int spectral_apply(const Geo& g, SpectralWork& w, SpecMode mode, const float* in
         CL_TRY(fwd_x3(g, w.tw64, w.tw_n, in, w.spec64, 3, s));
         CL_TRY(cols_x2<-1>(g, w.tw64, w.tw_n, w.spec64, 3, s));
         CL_TRY(reg_x1(g, w, w.spec64, S, m, s));
+        CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
+        CL_TRY(inv_x3(g, w, S, out, add, 3, s));
+        break;
+    case SPEC_REG32:
+        CL_TRY(fwd_x3(g, w.tw, w.tw_n, in, S, 3, s));
+        CL_TRY(cols_x2<-1>(g, w.tw, w.tw_n, S, 3, s));
+        CL_TRY(fused_x1<SPEC_REG32>(g, w.tw, w.tw_n, S, S, m, 3, s));
         CL_TRY(cols_x2<+1>(g, w.tw, w.tw_n, S, 3, s));
         CL_TRY(inv_x3(g, w, S, out, add, 3, s));
         break;

@@ -92,6 +92,8 @@ enum SpecMode {
     SPEC_REG = 2,      // 3 -> 3: alpha |k|^{2p}
     SPEC_REG_INV = 3,  // 3 -> 3: 1/(alpha |k|^{2p}), 1 at k = 0
     SPEC_REG_ISQRT = 4,  // 3 -> 3: (alpha |k|^{2p})^{-1/2}, 1 at k = 0
+    SPEC_REG32 = 5,    // 3 -> 3: alpha |k|^{2p} with a float32 forward transform
+                       // (power-of-two grids; others take SPEC_REG)
 };
 
 // out = F^{-1}[ sigma F[in] ] for the mode above; in and out are real fields
