@@ -91,16 +91,24 @@ __global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __rest
     }
 }
 
+__device__ __forceinline__ bool pcg_curv_ok(const PcgDev& p) {
+    const double shs = p.sc[p.shs];
+    return shs > 0.0 && shs <= DBL_MAX;   // false for NaN and infinity too
+}
+
 // (VT: v~ += kappa s;) r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0),
+// kappa from the device slots when pd.sc is set,
 // with per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
 template <bool VT>
 __global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restrict__ sd,
                                                          const float4* __restrict__ hs,
                                                          float4* __restrict__ vt,
                                                          float4* __restrict__ r, float kappa,
-                                                         long long n4, double* __restrict__ partial) {
+                                                         long long n4, double* __restrict__ partial,
+                                                         PcgDev pd) {
     __shared__ double sh[kThreads / kWave];
     double mx = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (pd.sc) kappa = pcg_curv_ok(pd) ? (float)(pd.sc[pd.rz] / pd.sc[pd.shs]) : 0.f;
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
         const float4 h = hs[i];
@@ -184,8 +192,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_direction(const float4* __rest
                                                             float4* __restrict__ sd, float mu,
                                                             float4* __restrict__ vt, float kappa,
                                                             long long n4, long long n,
-                                                            double* __restrict__ partial) {
+                                                            double* __restrict__ partial,
+                                                            PcgDev pd) {
     __shared__ double sh[kThreads / kWave];
+    if (pd.sc) {
+        if (!pcg_curv_ok(pd)) return;   // uniform over the grid
+        kappa = (float)(pd.sc[pd.rz] / pd.sc[pd.shs]);
+        mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
+    }
     double mx = identity<OP_MAX>();
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride) {
@@ -228,10 +242,23 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ 
 }
 
 // als_a = (r_a - mean_a) + mu als_a for the three components of a vector field
+// (with pd.sc: mu and the means from the device slots, a no-op on a bad curvature)
+__device__ __forceinline__ bool als_scalars(const PcgDev& pd, float& m0, float& m1, float& m2,
+                                            float& mu) {
+    if (!pd.sc) return true;
+    if (!pcg_curv_ok(pd)) return false;
+    mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
+    m0 = (float)(pd.sc[pd.ssum] / (double)pd.n);
+    m1 = (float)(pd.sc[pd.ssum + 1] / (double)pd.n);
+    m2 = (float)(pd.sc[pd.ssum + 2] / (double)pd.n);
+    return true;
+}
+
 __global__ __launch_bounds__(kThreads) void k_als_update(const float* __restrict__ r,
                                                          float* __restrict__ als, float m0,
                                                          float m1, float m2, float mu,
-                                                         long long n) {
+                                                         long long n, PcgDev pd) {
+    if (!als_scalars(pd, m0, m1, m2, mu)) return;
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= 3 * n) return;
     const float mean = (i < n) ? m0 : (i < 2 * n ? m1 : m2);
@@ -258,7 +285,8 @@ __global__ __launch_bounds__(kThreads) void k_xpby4(const float4* __restrict__ x
 __global__ __launch_bounds__(kThreads) void k_als_update4(const float4* __restrict__ r,
                                                           float4* __restrict__ als, float m0,
                                                           float m1, float m2, float mu,
-                                                          long long n4) {
+                                                          long long n4, PcgDev pd) {
+    if (!als_scalars(pd, m0, m1, m2, mu)) return;
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
         const float mean = (i < n4) ? m0 : (i < 2 * n4 ? m1 : m2);
@@ -385,20 +413,21 @@ int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t 
     return 0;
 }
 
-int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
-               float kappa, long long n, int smax, int ssum, hipStream_t st) {
+static int pcg_update_impl(Reducer& red, const float* s_dir, const float* hs, float* vt,
+                           float* r, float kappa, const PcgDev& pd, long long n, int smax,
+                           int ssum, hipStream_t st) {
     const long long n4 = n / 4;
     unsigned nb = red_blocks(3 * n4);
     if (vt)
         hipLaunchKernelGGL(k_pcg_update<true>, dim3(nb), dim3(kThreads), 0, st,
                            reinterpret_cast<const float4*>(s_dir),
                            reinterpret_cast<const float4*>(hs), reinterpret_cast<float4*>(vt),
-                           reinterpret_cast<float4*>(r), kappa, n4, red.partial);
+                           reinterpret_cast<float4*>(r), kappa, n4, red.partial, pd);
     else
         hipLaunchKernelGGL(k_pcg_update<false>, dim3(nb), dim3(kThreads), 0, st,
                            reinterpret_cast<const float4*>(s_dir),
                            reinterpret_cast<const float4*>(hs), nullptr,
-                           reinterpret_cast<float4*>(r), kappa, n4, red.partial);
+                           reinterpret_cast<float4*>(r), kappa, n4, red.partial, pd);
     CL_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, st, red.partial, (int)nb, 4, 0,
                        red.result, smax, red.mirror);
@@ -407,6 +436,16 @@ int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, flo
                            1 + a, red.result, ssum + a, red.mirror);
     CL_LAUNCH_CHECK();
     return 0;
+}
+
+int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
+               float kappa, long long n, int smax, int ssum, hipStream_t st) {
+    return pcg_update_impl(red, s_dir, hs, vt, r, kappa, PcgDev(), n, smax, ssum, st);
+}
+
+int pcg_update_dev(Reducer& red, const float* hs, float* r, const PcgDev& pd, long long n,
+                   int smax, int ssum, hipStream_t st) {
+    return pcg_update_impl(red, nullptr, hs, nullptr, r, 0.f, pd, n, smax, ssum, st);
 }
 
 // every fold also wrote its slot to the mapped host mirror r.host: waiting
@@ -450,15 +489,30 @@ int launch_pcg_direction(Reducer* r, const float* z, float* sd, float mu, float*
     if (r) {
         hipLaunchKernelGGL(k_pcg_direction<true>, dim3(nb), dim3(kThreads), 0, s,
                            reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
-                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, r->partial);
+                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, r->partial,
+                           PcgDev());
         CL_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r->partial, (int)nb,
                            1, 0, r->result, slot, r->mirror);
     } else {
         hipLaunchKernelGGL(k_pcg_direction<false>, dim3(nb), dim3(kThreads), 0, s,
                            reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
-                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, nullptr);
+                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, nullptr, PcgDev());
     }
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
+int launch_pcg_direction_dev(const float* z, float* sd, float* vt, const PcgDev& pd,
+                             long long n, hipStream_t s) {
+    if ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(sd) |
+         reinterpret_cast<uintptr_t>(vt)) & 15u) {
+        set_error("pcg direction update needs 16-byte aligned vectors");
+        return CLAIRE_EINVAL;
+    }
+    hipLaunchKernelGGL(k_pcg_direction<false>, dim3(red_blocks(n)), dim3(kThreads), 0, s,
+                       reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), 0.f,
+                       reinterpret_cast<float4*>(vt), 0.f, n / 4, n, nullptr, pd);
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -469,17 +523,28 @@ int launch_lincomb(const float* x, const float* z, float* y, float b, long long 
     return 0;
 }
 
-int launch_als_update(const float* r, float* als, const double mean[3], float mu, long long n,
-                      hipStream_t s) {
+static int als_update_impl(const float* r, float* als, const double mean[3], float mu,
+                           const PcgDev& pd, long long n, hipStream_t s) {
     if (vec4(r, als, n))
         hipLaunchKernelGGL(k_als_update4, dim3(red_blocks(3 * n)), dim3(kThreads), 0, s,
                            reinterpret_cast<const float4*>(r), reinterpret_cast<float4*>(als),
-                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n / 4);
+                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n / 4, pd);
     else
         hipLaunchKernelGGL(k_als_update, dim3(blocks_for(3 * n)), dim3(kThreads), 0, s, r, als,
-                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n);
+                           (float)mean[0], (float)mean[1], (float)mean[2], mu, n, pd);
     CL_LAUNCH_CHECK();
     return 0;
+}
+
+int launch_als_update(const float* r, float* als, const double mean[3], float mu, long long n,
+                      hipStream_t s) {
+    return als_update_impl(r, als, mean, mu, PcgDev(), n, s);
+}
+
+int launch_als_update_dev(const float* r, float* als, const PcgDev& pd, long long n,
+                          hipStream_t s) {
+    const double none[3] = {0.0, 0.0, 0.0};
+    return als_update_impl(r, als, none, 0.f, pd, n, s);
 }
 
 int launch_fill(float* y, float value, long long n, hipStream_t s) {

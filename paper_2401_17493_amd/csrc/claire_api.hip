@@ -95,6 +95,7 @@ struct claire_ctx {
     // and joined with the two events
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_pcg = nullptr;   // after a PCG iteration's preconditioner
     std::vector<hipEvent_t> ev_state;   // [nt + 1]: state m^j written (setup overlap)
     double cell = 0;   // h1 h2 h3
 
@@ -203,6 +204,7 @@ int ctx_alloc(claire_ctx* c) {
     CL_HIP(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
     CL_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     CL_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    CL_HIP(hipEventCreateWithFlags(&c->ev_pcg, hipEventDisableTiming));
     c->ev_state.assign(c->nt + 1, nullptr);
     for (auto& e : c->ev_state) CL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return 0;
@@ -226,6 +228,7 @@ void ctx_release(claire_ctx* c) {
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_pcg) (void)hipEventDestroy(c->ev_pcg);
     for (hipEvent_t e : c->ev_state)
         if (e) (void)hipEventDestroy(e);
 }
@@ -525,64 +528,83 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         res.inner += its;
         return red_dot(c->red, c->z, c->r, n3, slot, s);
     };
+    // Slots of the reducer: 0 <s, Hs>, 1 max|r|, 3..5 the component sums of r,
+    // 6 and 7 <z, r> of alternate iterations. kappa, mu and the means are
+    // taken on the device (PcgDev), so within an iteration the host waits
+    // once, for the event after the preconditioner, while the direction and
+    // als updates already run; it then checks the curvature and the residual.
+    int rz_slot = 6;
     CL_TRY(launch_fill(c->vt, 0.f, n3, s));
     CL_TRY(launch_scale_copy(c->grad, c->r, -1.f, n3, s));
-    CL_TRY(precond(0));   // z and <z, r> -> slot 0
+    CL_TRY(precond(rz_slot));   // z and <z, r>
     CL_TRY(copy_d2d(c->sd, c->z, n3, s));
     for (int a = 0; a < 3; ++a) CL_TRY(red_sum(c->red, c->r + a * n, n, 3 + a, s));
     CL_TRY(red_fetch(c->red, s));
-    double rz = c->red.host[0];
+    double rz = c->red.host[rz_slot];
     double mean[3] = {c->red.host[3] / n, c->red.host[4] / n, c->red.host[5] / n};
     if (!two) {
         CL_TRY(launch_fill(c->als, 0.f, n3, s));
         CL_TRY(launch_als_update(c->r, c->als, mean, 0.f, n, s));
     }
     bool converged = false;
-    while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
-        ++res.its;
-        CL_TRY(red_fetch(c->red, s));
-        const double shs = c->red.host[0];
+    auto curvature_stop = [&](double shs) -> int {
         if (!std::isfinite(shs)) {
             set_error("PCG curvature <s, Hs> = %g is not finite", shs);
             return CLAIRE_ENONFINITE;
         }
+        // nonpositive curvature (the discrete Gauss--Newton Hessian is
+        // semidefinite only up to discretisation error): truncated CG -- keep
+        // the current step (the device updates were no-ops), or take s itself
+        // on the first direction
         if (shs <= 0.0) {
-            // nonpositive curvature (the discrete Gauss--Newton Hessian is
-            // semidefinite only up to discretisation error): truncated CG --
-            // keep the current step, or take s itself on the first direction
             if (res.its == 1) CL_TRY(copy_d2d(c->vt, c->sd, n3, s));
             res.neg_curv = true;
-            break;
+            return 1;
         }
-        const double kappa = rz / shs;
-        // r -= kappa Hs, with max|r| -> slot 1 and the residual's component
-        // sums -> slots 3..5; v~ += kappa s follows in the direction update,
-        // which reads s anyway (or directly, when the iteration ends here)
-        CL_TRY(pcg_update(c->red, c->sd, c->hs, nullptr, c->r, (float)kappa, n, 1, 3, s));
+        return 0;
+    };
+    while (res.its < limit) {
+        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
+        ++res.its;
         if (res.its == limit) {
+            // last matvec: r -= kappa Hs and v~ += kappa s, no preconditioner
+            CL_TRY(red_fetch(c->red, s));
+            const int st = curvature_stop(c->red.host[0]);
+            if (st < 0) return st;
+            if (st) break;
+            const double kappa = rz / c->red.host[0];
+            CL_TRY(pcg_update(c->red, c->sd, c->hs, nullptr, c->r, (float)kappa, n, 1, 3, s));
             CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
             CL_TRY(red_fetch(c->red, s));
             c->trace_res.push_back(c->red.host[1]);
             break;
         }
-        // preconditioned residual and <z, r>: one host round trip with the above
-        CL_TRY(precond(2));   // z and <z, r> -> slot 2
-        CL_TRY(red_fetch(c->red, s));
+        PcgDev pd;
+        pd.sc = c->red.result;
+        pd.shs = 0;
+        pd.rz = rz_slot;
+        pd.rz_new = rz_slot ^ 1;   // 6 <-> 7
+        pd.ssum = 3;
+        pd.n = n;
+        // r -= kappa Hs, with max|r| -> slot 1 and the residual's component sums
+        CL_TRY(pcg_update_dev(c->red, c->hs, c->r, pd, n, 1, 3, s));
+        CL_TRY(precond(pd.rz_new));   // z and <z, r>
+        CL_HIP(hipEventRecord(c->ev_pcg, s));
+        // v~ += kappa s, s = z + mu s, als: needed unless the test below stops
+        // the solve, and v~ is right in that case too
+        CL_TRY(launch_pcg_direction_dev(c->z, c->sd, c->vt, pd, n3, s));
+        if (!two) CL_TRY(launch_als_update_dev(c->r, c->als, pd, n, s));
+        CL_HIP(hipEventSynchronize(c->ev_pcg));
+        const int st = curvature_stop(c->red.host[0]);
+        if (st < 0) return st;
+        if (st) break;
         c->trace_res.push_back(c->red.host[1]);
         if (!fixed && c->red.host[1] <= tol) {
             converged = true;
-            CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
             break;
         }
-        const double rz_new = c->red.host[2];
-        const double mu = rz_new / rz;
-        for (int a = 0; a < 3; ++a) mean[a] = c->red.host[3 + a] / n;
-        // v~ += kappa s, s = z + mu s
-        CL_TRY(launch_pcg_direction(nullptr, c->z, c->sd, (float)mu, c->vt, (float)kappa, n3,
-                                    0, s));
-        if (!two) CL_TRY(launch_als_update(c->r, c->als, mean, (float)mu, n, s));
-        rz = rz_new;
+        rz_slot = pd.rz_new;
+        rz = c->red.host[rz_slot];
     }
     if (!fixed && !converged && !res.neg_curv && res.its >= limit) {
         // the last residual was not tested inside the loop

@@ -217,6 +217,28 @@ int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
 int red_fetch(Reducer& r, hipStream_t s);
 // fold nb partial sums (r.partial[i*stride + off]) into r.result[slot]
 int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s);
+// PCG scalars taken on the device from the reducer's result slots, so the
+// host need not wait for them: kappa = rz / <s, Hs>, mu = rz_new / rz, and the
+// means of the residual's components (their sums / n). A curvature <s, Hs>
+// that is not positive and finite turns every update that reads these into a
+// no-op (the host, reading the same slot afterwards, ends the iteration).
+struct PcgDev {
+    const double* sc = nullptr;   // Reducer::result (device)
+    int shs = 0;                  // slot of <s, Hs>
+    int rz = 0, rz_new = 0;       // slots of <z, r> before and after the update
+    int ssum = 0;                 // first of the three component sums of r
+    long long n = 0;              // voxels (the means' divisor)
+};
+// r -= kappa Hs with kappa from the device slots (no v~ update), the same
+// reductions as pcg_update
+int pcg_update_dev(Reducer& red, const float* hs, float* r, const PcgDev& pd, long long n,
+                   int smax, int ssum, hipStream_t st);
+// v~ += kappa sd, sd = z + mu sd and als_a = (r_a - mean_a) + mu als_a with
+// the device scalars
+int launch_pcg_direction_dev(const float* z, float* sd, float* vt, const PcgDev& pd,
+                             long long n, hipStream_t s);
+int launch_als_update_dev(const float* r, float* als, const PcgDev& pd, long long n,
+                          hipStream_t s);
 // PCG update (v~ += kappa s when vt is given,) r -= kappa Hs on [3][n]
 // vectors, fused with the reductions of the new residual: max |r| -> slot
 // smax, sum of each component of r -> slots ssum..ssum+2
