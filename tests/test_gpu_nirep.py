@@ -85,3 +85,35 @@ def test_nirep_grid_first_steps(C):
     assert st["status"] != 0 and st["det_nonpositive"] > 0 and st["rel_grad"] > w["gtol"]
     assert abs(st["gn_iters"] - ref["gn_iters"]) <= 2
     assert abs(st["matvecs"] - ref["matvecs"]) <= 0.1 * ref["matvecs"]
+
+
+NI_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "ellipsoids_nirep_ni_solve.json")
+
+
+def test_nirep_grid_ni_first_steps(C):
+    """The near-incompressible model (beta = 1e-4, the paper's model for its
+    NIREP runs) on the same grid: the oracle's first three Gauss--Newton
+    steps (its record stops there) at the 1e-5 bar."""
+    if not os.path.exists(NI_GOLDEN):
+        pytest.skip("no oracle record of the near-incompressible 256x300x256 solve")
+    ref = json.load(open(NI_GOLDEN))
+    grid, m0, m1, vstar, w = phantom_problem("ellipsoids_nirep")
+    sha = hashlib.sha256(np.ascontiguousarray(m1, dtype=np.float32).tobytes()).hexdigest()
+    assert sha == ref["m1_sha256"] and ref["beta"] > 0
+    idx = ref["sample_idx"]
+    P = Parity("256x300x256 beta %g" % ref["beta"])
+    with C.Context(grid.n, w["nt"], w["alphas"][-1], w["reg_order"]) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_beta(ref["beta"])
+        ctx.set_velocity(torch.zeros((3,) + grid.n, device="cuda"))
+        g0, _ = ctx.gradient()
+        P.rel("g(0) samples", samples(g0, idx), np.array(ref["g0_samples"]), 1e-5)
+        for k, snap in sorted(ref["snapshots"].items()):
+            vk, sk = ctx.solve(gtol=w["gtol"], max_gn=int(k), beta=ref["beta"])
+            trace = ctx.solve_trace()
+            P.rel("v after %s GN steps" % k, samples(vk, idx), np.array(snap["v_samples"]), 1e-5)
+            P.value("J after %s GN steps" % k, sk["J"], snap["J"], 1e-5)
+    steps = min(3, ref["max_gn"])
+    trace_parity(P, "first steps", trace, ref["history"], 1e-5, steps=steps)
+    P.done()
