@@ -91,11 +91,6 @@ __global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __rest
     }
 }
 
-__device__ __forceinline__ bool pcg_curv_ok(const PcgDev& p) {
-    const double shs = p.sc[p.shs];
-    return shs > 0.0 && shs <= DBL_MAX;   // false for NaN and infinity too
-}
-
 // (VT: v~ += kappa s;) r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0),
 // kappa from the device slots when pd.sc is set,
 // with per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
@@ -245,13 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(const float* __restrict__ 
 // (with pd.sc: mu and the means from the device slots, a no-op on a bad curvature)
 __device__ __forceinline__ bool als_scalars(const PcgDev& pd, float& m0, float& m1, float& m2,
                                             float& mu) {
-    if (!pd.sc) return true;
-    if (!pcg_curv_ok(pd)) return false;
-    mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
-    m0 = (float)(pd.sc[pd.ssum] / (double)pd.n);
-    m1 = (float)(pd.sc[pd.ssum + 1] / (double)pd.n);
-    m2 = (float)(pd.sc[pd.ssum + 2] / (double)pd.n);
-    return true;
+    return !pd.sc || pcg_als_scalars(pd, m0, m1, m2, mu);
 }
 
 __global__ __launch_bounds__(kThreads) void k_als_update(const float* __restrict__ r,

@@ -399,7 +399,7 @@ int join_reg(claire_ctx* c) {
 // float32, R23).
 template <typename GT>
 int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
-                 const float* reg_part, int dot_slot) {
+                 const float* reg_part, int dot_slot, const PcgDev* als_pd) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -438,7 +438,8 @@ int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
         return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
     }
     if (dot_slot >= 0)
-        return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot);
+        return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot,
+                               als_pd, c->r);
     return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s);
 }
 
@@ -452,10 +453,17 @@ int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* re
     return 0;
 }
 
+// als_pd (PCG, plain model): the assembly first advances the alpha L s
+// recursion in reg_part (= c->als) with the device scalars of the previous
+// iteration and the residual c->r
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
-               int dot_slot = -1) {
-    if (c->precision == 1) return matvec_steps(c, c->gm16, vt, out, reg_part, dot_slot);
-    return matvec_steps(c, c->gm, vt, out, reg_part, dot_slot);
+               int dot_slot = -1, const PcgDev* als_pd = nullptr) {
+    if (als_pd && (c->beta > 0.0 || reg_part != c->als || dot_slot < 0)) {
+        set_error("the als update rides only on the plain model's PCG matvec");
+        return CLAIRE_EINVAL;
+    }
+    if (c->precision == 1) return matvec_steps(c, c->gm16, vt, out, reg_part, dot_slot, als_pd);
+    return matvec_steps(c, c->gm, vt, out, reg_part, dot_slot, als_pd);
 }
 
 // Objective of a trial velocity held in c->v: backtrace, state, mismatch.
@@ -563,8 +571,15 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         }
         return 0;
     };
+    // plain model, (alpha L)^{-1}: the als update of each direction after the
+    // first rides on the next matvec's assembly
+    const bool als_fused = !two && !(c->beta > 0.0);
+    PcgDev prev;
+    bool have_prev = false;
     while (res.its < limit) {
-        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0));   // <s, Hs> -> slot 0
+        // <s, Hs> -> slot 0
+        CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0,
+                          als_fused && have_prev ? &prev : nullptr));
         ++res.its;
         if (res.its == limit) {
             // last matvec: r -= kappa Hs and v~ += kappa s, no preconditioner
@@ -593,7 +608,7 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         // v~ += kappa s, s = z + mu s, als: needed unless the test below stops
         // the solve, and v~ is right in that case too
         CL_TRY(launch_pcg_direction_dev(c->z, c->sd, c->vt, pd, n3, s));
-        if (!two) CL_TRY(launch_als_update_dev(c->r, c->als, pd, n, s));
+        if (!two && !als_fused) CL_TRY(launch_als_update_dev(c->r, c->als, pd, n, s));
         CL_HIP(hipEventSynchronize(c->ev_pcg));
         const int st = curvature_stop(c->red.host[0]);
         if (st < 0) return st;
@@ -605,6 +620,8 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         }
         rz_slot = pd.rz_new;
         rz = c->red.host[rz_slot];
+        prev = pd;
+        have_prev = true;
     }
     if (!fixed && !converged && !res.neg_curv && res.its >= limit) {
         // the last residual was not tested inside the loop

@@ -47,6 +47,33 @@ int check_extents(const int nx[3]);
 
 struct Reducer;
 
+// PCG scalars taken on the device from the reducer's result slots, so the
+// host need not wait for them: kappa = rz / <s, Hs>, mu = rz_new / rz, and the
+// means of the residual's components (their sums / n). A curvature <s, Hs>
+// that is not positive and finite turns every update that reads these into a
+// no-op (the host, reading the same slot afterwards, ends the iteration).
+struct PcgDev {
+    const double* sc = nullptr;   // Reducer::result (device)
+    int shs = 0;                  // slot of <s, Hs>
+    int rz = 0, rz_new = 0;       // slots of <z, r> before and after the update
+    int ssum = 0;                 // first of the three component sums of r
+    long long n = 0;              // voxels (the means' divisor)
+};
+__device__ __forceinline__ bool pcg_curv_ok(const PcgDev& p) {
+    const double shs = p.sc[p.shs];
+    return shs > 0.0 && shs <= 1.7976931348623157e308;   // false for NaN and infinity too
+}
+// mu and the residual means from the device slots (false on a bad curvature)
+__device__ __forceinline__ bool pcg_als_scalars(const PcgDev& pd, float& m0, float& m1,
+                                                float& m2, float& mu) {
+    if (!pcg_curv_ok(pd)) return false;
+    mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
+    m0 = (float)(pd.sc[pd.ssum] / (double)pd.n);
+    m1 = (float)(pd.sc[pd.ssum + 1] / (double)pd.n);
+    m2 = (float)(pd.sc[pd.ssum + 2] / (double)pd.n);
+    return true;
+}
+
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
@@ -167,11 +194,14 @@ int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const GT* gradm_next, const float* vt, float* out, float coef,
                           float sign, hipStream_t s, const int* boxes = nullptr);
 // out = add + h_t sum_j c_j lam^j grad m^j; with dot_with (nullable), also
-// <dot_with, out> summed into red.result[slot]
+// <dot_with, out> summed into red.result[slot]. With als_pd (PCG), `add` is
+// the alpha L s recursion als, first advanced in place to
+// (r - mean(r)) + mu als with the device scalars (r: the residual).
 template <typename GT>
 int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt,
                     const float* add, float* out, hipStream_t s,
-                    const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0);
+                    const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0,
+                    const PcgDev* als_pd = nullptr, const float* r = nullptr);
 // float16 copy of grad m^j for the mixed-precision matvec
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s);
 
@@ -217,18 +247,6 @@ int red_stats_f64(Reducer& r, const double* a, long long n, hipStream_t s);
 int red_fetch(Reducer& r, hipStream_t s);
 // fold nb partial sums (r.partial[i*stride + off]) into r.result[slot]
 int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t s);
-// PCG scalars taken on the device from the reducer's result slots, so the
-// host need not wait for them: kappa = rz / <s, Hs>, mu = rz_new / rz, and the
-// means of the residual's components (their sums / n). A curvature <s, Hs>
-// that is not positive and finite turns every update that reads these into a
-// no-op (the host, reading the same slot afterwards, ends the iteration).
-struct PcgDev {
-    const double* sc = nullptr;   // Reducer::result (device)
-    int shs = 0;                  // slot of <s, Hs>
-    int rz = 0, rz_new = 0;       // slots of <z, r> before and after the update
-    int ssum = 0;                 // first of the three component sums of r
-    long long n = 0;              // voxels (the means' divisor)
-};
 // r -= kappa Hs with kappa from the device slots (no v~ update), the same
 // reductions as pcg_update
 int pcg_update_dev(Reducer& red, const float* hs, float* r, const PcgDev& pd, long long n,

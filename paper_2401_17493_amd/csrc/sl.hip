@@ -715,16 +715,52 @@ __global__ __launch_bounds__(kThreads) void k_inc_first(const GT* __restrict__ g
     w[idx] = -half_ht * f;
 }
 
-// out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2)
-template <bool DOT, typename GT>
+// four consecutive elements q*4 .. q*4+3 of a float or half field, as float4
+__device__ __forceinline__ float4 ld4(const float* p, long long q) {
+    return reinterpret_cast<const float4*>(p)[q];
+}
+__device__ __forceinline__ float4 ld4(const __half* p, long long q) {
+    const uint2 u = reinterpret_cast<const uint2*>(p)[q];
+    const float2 lo = __half22float2(*reinterpret_cast<const __half2*>(&u.x));
+    const float2 hi = __half22float2(*reinterpret_cast<const __half2*>(&u.y));
+    return make_float4(lo.x, lo.y, hi.x, hi.y);
+}
+
+// k_inc_first on four voxels per thread (16-byte float and 8-byte half loads;
+// n a multiple of 4)
+template <typename GT>
+__global__ __launch_bounds__(kThreads) void k_inc_first4(const GT* __restrict__ gm,
+                                                         const float* __restrict__ vt,
+                                                         float* __restrict__ w, long long n,
+                                                         float half_ht) {
+    const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (n >> 2)) return;
+    const float4 g0 = ld4(gm, q), g1 = ld4(gm + n, q), g2 = ld4(gm + 2 * n, q);
+    const float4 a0 = ld4(vt, q), a1 = ld4(vt + n, q), a2 = ld4(vt + 2 * n, q);
+    float4 o;
+    o.x = -half_ht * (g0.x * a0.x + g1.x * a1.x + g2.x * a2.x);
+    o.y = -half_ht * (g0.y * a0.y + g1.y * a1.y + g2.y * a2.y);
+    o.z = -half_ht * (g0.z * a0.z + g1.z * a1.z + g2.z * a2.z);
+    o.w = -half_ht * (g0.w * a0.w + g1.w * a1.w + g2.w * a2.w);
+    reinterpret_cast<float4*>(w)[q] = o;
+}
+
+// out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2).
+// ALS: `add` is the PCG recursion als (alpha L s), advanced here in place to
+// (r_a - mean_a) + mu als_a before it is added.
+template <bool DOT, bool ALS, typename GT>
 __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__ lam,
                                                        const GT* __restrict__ gm, int nt,
-                                                       const float* __restrict__ add,
+                                                       const float* add,
                                                        float* __restrict__ out, long long n,
                                                        float ht, const float* __restrict__ dv,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial,
+                                                       const float* __restrict__ r, PcgDev pd) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     double dot = 0.0;
+    float am[3] = {0.f, 0.f, 0.f}, mu = 0.f;
+    bool adv = false;
+    if (ALS) adv = pcg_als_scalars(pd, am[0], am[1], am[2], mu);
     if (idx < n) {
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
         for (int j = 0; j <= nt; ++j) {
@@ -735,7 +771,20 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__
             acc1 = fmaf(l, ldf(gj + n + idx), acc1);
             acc2 = fmaf(l, ldf(gj + 2 * n + idx), acc2);
         }
-        if (add) {
+        if (ALS) {
+            float a[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[c] = add[c * n + idx];
+                if (adv) {
+                    a[c] = fmaf(mu, a[c], r[c * n + idx] - am[c]);
+                    const_cast<float*>(add)[c * n + idx] = a[c];
+                }
+            }
+            acc0 += a[0];
+            acc1 += a[1];
+            acc2 += a[2];
+        } else if (add) {
             acc0 += add[idx];
             acc1 += add[n + idx];
             acc2 += add[2 * n + idx];
@@ -901,8 +950,15 @@ int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus
 template <typename GT>
 int launch_inc_state_first(const Geo& g, const GT* gradm0, const float* vt, float* w0,
                            double ht, hipStream_t s) {
-    hipLaunchKernelGGL(k_inc_first<GT>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0, vt,
-                       w0, g.n, (float)(0.5 * ht));
+    const bool vec = (g.n & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(vt) | reinterpret_cast<uintptr_t>(w0)) & 15u) == 0 &&
+                     (reinterpret_cast<uintptr_t>(gradm0) & (4 * sizeof(GT) - 1)) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_inc_first4<GT>, dim3(blocks_for(g.n / 4)), dim3(kThreads), 0, s,
+                           gradm0, vt, w0, g.n, (float)(0.5 * ht));
+    else
+        hipLaunchKernelGGL(k_inc_first<GT>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0,
+                           vt, w0, g.n, (float)(0.5 * ht));
     CL_LAUNCH_CHECK();
     return 0;
 }
@@ -927,23 +983,38 @@ template int launch_inc_state_step<__half>(const Geo&, const float*, const float
 
 template <typename GT>
 int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt, const float* add,
-                    float* out, hipStream_t s, const float* dot_with, Reducer* red, int slot) {
+                    float* out, hipStream_t s, const float* dot_with, Reducer* red, int slot,
+                    const PcgDev* als_pd, const float* r) {
     const unsigned nb = blocks_for(g.n);
-    if (dot_with) {
-        hipLaunchKernelGGL((k_assemble<true, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt,
-                           add, out, g.n, (float)(1.0 / nt), dot_with, red->partial);
+    const float ht = (float)(1.0 / nt);
+    if (als_pd && (!add || !r || !dot_with)) {
+        set_error("the als update in the assembly needs als, r and the dot product");
+        return CLAIRE_EINVAL;
+    }
+    if (als_pd) {
+        hipLaunchKernelGGL((k_assemble<true, true, GT>), dim3(nb), dim3(kThreads), 0, s, lam,
+                           gradm, nt, add, out, g.n, ht, dot_with, red->partial, r, *als_pd);
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
     }
-    hipLaunchKernelGGL((k_assemble<false, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm, nt,
-                       add, out, g.n, (float)(1.0 / nt), nullptr, nullptr);
+    if (dot_with) {
+        hipLaunchKernelGGL((k_assemble<true, false, GT>), dim3(nb), dim3(kThreads), 0, s, lam,
+                           gradm, nt, add, out, g.n, ht, dot_with, red->partial, nullptr,
+                           PcgDev());
+        CL_LAUNCH_CHECK();
+        return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
+    }
+    hipLaunchKernelGGL((k_assemble<false, false, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm,
+                       nt, add, out, g.n, ht, nullptr, nullptr, nullptr, PcgDev());
     CL_LAUNCH_CHECK();
     return 0;
 }
 template int launch_assemble<float>(const Geo&, const float*, const float*, int, const float*,
-                                    float*, hipStream_t, const float*, Reducer*, int);
+                                    float*, hipStream_t, const float*, Reducer*, int,
+                                    const PcgDev*, const float*);
 template int launch_assemble<__half>(const Geo&, const float*, const __half*, int, const float*,
-                                     float*, hipStream_t, const float*, Reducer*, int);
+                                     float*, hipStream_t, const float*, Reducer*, int,
+                                     const PcgDev*, const float*);
 
 int brick_table_ints(const Geo& g) { return 6 * gather_brick(g).nbricks; }
 
