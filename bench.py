@@ -140,7 +140,9 @@ def load_golden(name, w, beta):
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        return json.load(fh)
+        g = json.load(fh)
+    # a record of the first Gauss--Newton steps only is no whole-solve reference
+    return g if g.get("max_gn", 50) >= 50 else None
 
 
 def vs_oracle(v, stats, trace, golden, m1_sha):
