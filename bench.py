@@ -54,14 +54,18 @@ HBM_PEAK_GBS = 8000.0
 #   copy:           3 floats in, 3 floats out.
 #   backtrace:      v (12), y+ and y- displacements (24).
 def kernel_bytes_per_voxel(kernel, nt):
-    return {"inc_state_step": 44, "adjoint_step": 24,
+    # inc-state step: w^j 4 + displacement 12 + grad m^{j+1} 12 (float16: 6)
+    # + v~ 12 + out 4; adjoint step: lambda~ 4 + displacement 12 + A 4 + out 4
+    return {"inc_state_step": 44, "inc_state_step_mixed": 38, "adjoint_step": 24,
             "assemble": 16 * (nt + 1) + 24, "copy": 24, "backtrace": 36}[kernel]
 
 
 def kernel_table(ctx, C, nt, voxels, reps=20):
     """Average launch time (HIP events on the context stream) and algorithmic
     HBM rate of each hot-path kernel at the context's current velocity."""
-    ids = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
+    ids = {"inc_state_step": C.KERNEL_INC_STATE_STEP,
+           "inc_state_step_mixed": C.KERNEL_INC_STATE_STEP_MIXED,
+           "adjoint_step": C.KERNEL_ADJOINT_STEP,
            "assemble": C.KERNEL_ASSEMBLE, "backtrace": C.KERNEL_BACKTRACE,
            "copy": C.KERNEL_COPY}
     out = {}
@@ -75,6 +79,7 @@ def kernel_table(ctx, C, nt, voxels, reps=20):
 
 # HIP sources that define each timed kernel (its code and launch)
 KERNEL_SOURCES = {"inc_state_step": ["sl.hip", "internal.h"],
+                  "inc_state_step_mixed": ["sl.hip", "internal.h"],
                   "adjoint_step": ["sl.hip", "internal.h"],
                   "assemble": ["sl.hip", "internal.h"],
                   "copy": ["blas.hip", "internal.h"]}
@@ -256,11 +261,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ellipsoids256")
     ap.add_argument("--matvecs", type=int, default=40, help="timed Hessian matvecs")
-    # the adjoint (continuity) step is the largest kernel by GPU time in the
-    # mixed-precision solves (8 of the matvec's gathers are it or the
-    # incremental-state step; the adjoint step also runs in every setup)
-    ap.add_argument("--roofline-kernel", default="adjoint_step",
-                    choices=["inc_state_step", "adjoint_step", "assemble", "copy"])
+    # the mixed incremental-state step is the largest kernel by GPU time in the
+    # mixed-precision solves (n_t per matvec, 167 us at 256^3), ahead of the
+    # adjoint step (n_t per matvec and per setup, 130-150 us)
+    ap.add_argument("--roofline-kernel", default="inc_state_step_mixed",
+                    choices=["inc_state_step", "inc_state_step_mixed", "adjoint_step",
+                             "assemble", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["mixed", "fp32", "both"])
     ap.add_argument("--precond", default="reg", choices=["reg", "twolevel"],
@@ -306,9 +312,13 @@ def main():
     ctx.set_images(m0, m1)
     if args.beta > 0:
         ctx.set_beta(args.beta)   # the matvec timing uses the same model as the solve
-    kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP, "adjoint_step": C.KERNEL_ADJOINT_STEP,
+    kid = {"inc_state_step": C.KERNEL_INC_STATE_STEP,
+           "inc_state_step_mixed": C.KERNEL_INC_STATE_STEP_MIXED,
+           "adjoint_step": C.KERNEL_ADJOINT_STEP,
            "assemble": C.KERNEL_ASSEMBLE, "copy": C.KERNEL_COPY}[args.roofline_kernel]
     if args.kernels_only:
+        # the kernels' state at v = v*/2, with the float16 copy for the mixed step
+        ctx.set_precision(1)
         ctx.set_velocity((0.5 * vstar).contiguous())
         ms_k = ctx.time_kernel(kid, reps=5)
         ms_c = ctx.time_kernel(C.KERNEL_COPY, reps=5)
@@ -346,7 +356,7 @@ def main():
                 "matvec_roofline": {"fields": fields, "achieved": round(gbs, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(gbs / HBM_PEAK_GBS, 4)}}
-        ctx.set_precision(0)
+        ctx.set_precision(1)
         ctx.set_velocity((0.5 * vstar).contiguous())
         rec["kernels"] = kernel_table(ctx, C, nt, voxels)
         ctx.close()
@@ -408,8 +418,9 @@ def main():
     head = runs[modes[0][0]]
     tts, stats, ms_matvec = head["tts"], head["stats"], head["ms_matvec"]
     # roofline of the dominant kernel at v = v*/2, the state the counter runs
-    # (--kernels-only) use: algorithmic bytes / live launch duration
-    ctx.set_precision(0)
+    # (--kernels-only) use: algorithmic bytes / live launch duration (the
+    # mixed setup also holds the float32 fields the other kernels read)
+    ctx.set_precision(1)
     ctx.set_velocity((0.5 * vstar).contiguous())
 
     ms_kernel = ctx.time_kernel(kid, reps=50)

@@ -84,7 +84,9 @@ typedef struct claire_opts {
     int tol_from_zero;          /* 1: g_0 of the gtol test is the gradient at v = 0 (one
                                    extra state + adjoint solve per level) instead of the
                                    gradient at the initial guess, so a warm-started solve
-                                   stops at the same gradient norm as one from v = 0 */
+                                   stops at the same gradient norm as one from v = 0; an
+                                   initial guess whose objective is not finite or exceeds
+                                   J(v = 0) is then replaced by v = 0 (first level) */
     int derivative;             /* first derivatives (grad m, div v, grad v):
                                    CLAIRE_DERIV_SPECTRAL (default) or CLAIRE_DERIV_FD8 */
     int precond;                /* PCG preconditioner (Section 2.5.6):
@@ -131,6 +133,9 @@ typedef struct claire_stats {
     long long det_nonpositive;  /* voxels with det F(1) <= 0 */
     double seconds;             /* wall time of the solve (host clock) */
     int inner_iters;            /* coarse CG iterations of the two-level preconditioner */
+    int initial_rejected;       /* 1: with tol_from_zero, the initial guess gave an
+                                   objective that was not finite or above J(v = 0), and
+                                   the solve started from v = 0 instead */
 } claire_stats;
 
 typedef struct claire_ctx claire_ctx;
@@ -292,6 +297,10 @@ int claire_ctx_get_field(claire_ctx *ctx, int which, int index, float *out);
  * arguments the Hessian matvec uses (needs a prior set_velocity). kernel:
  *   CLAIRE_KERNEL_INC_STATE_STEP  one incremental-state SL step (gather of
  *                                 w^j at y+, source -grad m^{j+1}.v~)
+ *   CLAIRE_KERNEL_INC_STATE_STEP_MIXED  the same step of the mixed-precision
+ *                                 matvec, grad m^{j+1} read from the float16
+ *                                 copy (needs set_precision(1) before the
+ *                                 set_velocity; CLAIRE_EINVAL otherwise)
  *   CLAIRE_KERNEL_ADJOINT_STEP    one (incremental) adjoint SL step
  *   CLAIRE_KERNEL_ASSEMBLE        h_t sum_j c_j lambda~^j grad m^j + alpha L v~
  *   CLAIRE_KERNEL_COPY            a plain copy of 3n floats (bandwidth and
@@ -302,7 +311,8 @@ int claire_ctx_get_field(claire_ctx *ctx, int which, int index, float *out);
  * context's scratch buffers (incremental fields, adjoint history), not v, g
  * or the state. */
 enum { CLAIRE_KERNEL_INC_STATE_STEP = 0, CLAIRE_KERNEL_ADJOINT_STEP = 1,
-       CLAIRE_KERNEL_ASSEMBLE = 2, CLAIRE_KERNEL_COPY = 3, CLAIRE_KERNEL_BACKTRACE = 4 };
+       CLAIRE_KERNEL_ASSEMBLE = 2, CLAIRE_KERNEL_COPY = 3, CLAIRE_KERNEL_BACKTRACE = 4,
+       CLAIRE_KERNEL_INC_STATE_STEP_MIXED = 5 };
 int claire_ctx_time_kernel(claire_ctx *ctx, int kernel, int reps, double *avg_ms);
 
 /* --------------------------------------------- stateless convenience calls

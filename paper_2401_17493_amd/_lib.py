@@ -57,6 +57,7 @@ class ClaireStats(ctypes.Structure):
         ("det_nonpositive", ctypes.c_longlong),
         ("seconds", c_double),
         ("inner_iters", c_int),
+        ("initial_rejected", c_int),
     ]
 
     def as_dict(self):

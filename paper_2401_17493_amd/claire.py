@@ -21,7 +21,8 @@ OP_GRAD, OP_DIV, OP_REG, OP_REG_INV, OP_FD8_GRAD, OP_FD8_DIV = 0, 1, 2, 3, 4, 5
 OP_NI_PROJECT, OP_NI_PENALTY = 6, 7
 DERIV_SPECTRAL, DERIV_FD8 = 0, 1
 PRECOND_REG, PRECOND_TWOLEVEL = 0, 1
-KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE = range(5)
+(KERNEL_INC_STATE_STEP, KERNEL_ADJOINT_STEP, KERNEL_ASSEMBLE, KERNEL_COPY, KERNEL_BACKTRACE,
+ KERNEL_INC_STATE_STEP_MIXED) = range(6)
 FIELD_DISP_PLUS, FIELD_DISP_MINUS, FIELD_STATE, FIELD_GRAD_STATE, FIELD_ADJOINT, FIELD_DIVV = range(6)
 
 WARNINGS = {1: "gauss-newton max iterations", 2: "line search failed",

@@ -653,6 +653,7 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
     double g0 = 0.0;
     for (size_t li = 0; li < levels.size() && !stop_all; ++li) {
         c->alpha = levels[li];
+        double J_zero = 0.0;
         if (o.tol_from_zero) {
             // reference gradient at v = 0 for the stopping test
             CL_TRY(launch_fill(c->v, 0.f, n3, s));
@@ -660,11 +661,24 @@ int run_solve(claire_ctx* c, const claire_opts& o, float* v_io, claire_stats* st
             CL_TRY(run_setup(c));
             S.pde_solves += 2;
             g0 = c->gnorm;
+            J_zero = c->J;
         }
         CL_TRY(copy_d2d(c->v, v_io, n3, s));
         c->state_valid = false;
-        CL_TRY(run_setup(c));
+        const bool may_reject = o.tol_from_zero && li == 0;
+        const int rc0 = run_setup(c);
+        if (rc0 < 0 && !(may_reject && rc0 == CLAIRE_ENONFINITE)) return rc0;
         S.pde_solves += 2;
+        if (may_reject && (rc0 < 0 || !(c->J <= J_zero))) {
+            // a (learned) initial guess no better than v = 0: the plain solve
+            // from v = 0 takes over (v_io is the iterate the steps update)
+            S.initial_rejected = 1;
+            CL_TRY(launch_fill(v_io, 0.f, n3, s));
+            CL_TRY(launch_fill(c->v, 0.f, n3, s));
+            c->state_valid = false;
+            CL_TRY(run_setup(c));
+            S.pde_solves += 2;
+        }
         if (li == 0) S.J0 = c->J;
         if (!o.tol_from_zero) g0 = c->gnorm;
         int k = 0;
@@ -1172,8 +1186,13 @@ int claire_ctx_time_kernel(claire_ctx* c, int kernel, int reps, double* avg_ms) 
     CL_TRY(need(c, true));
     if (!avg_ms) { set_error("avg_ms is NULL"); return CLAIRE_EINVAL; }
     if (reps < 1 || reps > 100000) { set_error("reps must be in [1, 100000]"); return CLAIRE_EINVAL; }
-    if (kernel < CLAIRE_KERNEL_INC_STATE_STEP || kernel > CLAIRE_KERNEL_BACKTRACE) {
+    if (kernel < CLAIRE_KERNEL_INC_STATE_STEP || kernel > CLAIRE_KERNEL_INC_STATE_STEP_MIXED) {
         set_error("unknown kernel id %d", kernel);
+        return CLAIRE_EINVAL;
+    }
+    if (kernel == CLAIRE_KERNEL_INC_STATE_STEP_MIXED &&
+        (c->precision != 1 || !c->gm16 || !c->half_valid)) {
+        set_error("the mixed incremental-state step needs set_precision(1) before set_velocity");
         return CLAIRE_EINVAL;
     }
     const Geo& g = c->g;
@@ -1183,6 +1202,9 @@ int claire_ctx_time_kernel(claire_ctx* c, int kernel, int reps, double* avg_ms) 
         switch (kernel) {
         case CLAIRE_KERNEL_INC_STATE_STEP:
             return launch_inc_state_step(g, c->w0, c->dp, c->gm + 3 * n, c->regv, c->w1,
+                                         (float)ht, 1.0f, c->s, c->box_p);
+        case CLAIRE_KERNEL_INC_STATE_STEP_MIXED:
+            return launch_inc_state_step(g, c->w0, c->dp, c->gm16 + 3 * n, c->regv, c->w1,
                                          (float)ht, 1.0f, c->s, c->box_p);
         case CLAIRE_KERNEL_ADJOINT_STEP:
             return launch_adjoint_step(g, c->lam + n, c->dm, c->A, c->lam, c->s, c->box_m);

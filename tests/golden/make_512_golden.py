@@ -10,11 +10,12 @@ matvec, for element-wise comparison with the GPU at full size.
 
 The setup keeps the state m^j but recomputes grad m^j where it is used
 (store_grad=False): the stored float64 gradients alone would take 27 GiB.
-Calls only oracle/ and synthetic/ (through tests/helpers.py). About an hour
-and 50 GiB of memory on eight cores.
+Calls only oracle/ and synthetic/ (through tests/helpers.py). About 50 GiB
+of memory; minutes on a 16-core host, about an hour on eight slower cores.
 
-    python tests/golden/make_512_golden.py
+    python tests/golden/make_512_golden.py [--out PATH]
 """
+import argparse
 import hashlib
 import json
 import os
@@ -41,6 +42,9 @@ def digest(a):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "ellipsoids512_samples.json"))
+    args = ap.parse_args()
     name = "ellipsoids512"
     w = WORKLOADS[name]
     t0 = time.time()
@@ -87,7 +91,7 @@ def main():
         "seconds": {"transport": t_transport, "setup": t_setup, "matvec": t_matvec},
         "host": {"nproc": os.cpu_count(), "cpu_model": model, "threads": O.WORKERS},
     }
-    path = os.path.join(HERE, "ellipsoids512_samples.json")
+    path = args.out
     with open(path, "w") as fh:
         json.dump(out, fh)
     print("wrote", path, "in %.0f s" % (time.time() - t0))

@@ -110,3 +110,20 @@ def test_mixed_continuation_solve_128(C):
     assert abs(st["gn_iters"] - ref["gn_iters"]) <= 2
     assert abs(st["matvecs"] - ref["matvecs"]) <= 0.1 * ref["matvecs"]
     assert st["det_nonpositive"] == 0
+
+
+def test_time_kernel_mixed_step(C):
+    """The mixed incremental-state step can be timed only with the float16
+    copy in place (set_precision(1) before set_velocity)."""
+    grid, m0, m1, vstar = blob_problem()
+    with C.Context(grid.n, 4, 1e-2, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        ctx.set_velocity(dev(f32(0.5 * vstar)))
+        with pytest.raises(C.ClaireError) as e:
+            ctx.time_kernel(C.KERNEL_INC_STATE_STEP_MIXED, reps=2)
+        assert e.value.code == -1
+        ctx.set_precision(1)
+        ctx.set_velocity(dev(f32(0.5 * vstar)))
+        for k in (C.KERNEL_INC_STATE_STEP_MIXED, C.KERNEL_INC_STATE_STEP,
+                  C.KERNEL_ADJOINT_STEP, C.KERNEL_COPY):
+            assert ctx.time_kernel(k, reps=2) > 0.0

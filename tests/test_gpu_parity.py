@@ -222,6 +222,28 @@ def test_full_solve_blobs32(C):
     P.done()
 
 
+def test_initial_guess_fallback(C):
+    """A warm-started solve (tol_from_zero) whose initial guess is no better
+    than v = 0 -- non-finite, or with J above J(0) -- runs the plain solve from
+    v = 0 instead and reports it; a good initial guess is kept."""
+    nt, alpha = 4, 1e-2
+    grid, m0, m1, vstar = blob_problem()
+    with C.Context(grid.n, nt, alpha, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v_cold, s_cold = ctx.solve()
+        assert s_cold["status"] == 0 and s_cold["initial_rejected"] == 0
+        for bad in (torch.full((3,) + grid.n, float("nan"), device="cuda"),
+                    dev(f32(-40.0 * vstar))):
+            v, st = ctx.solve(bad, tol_from_zero=1)
+            assert st["status"] == 0 and st["initial_rejected"] == 1
+            assert torch.equal(v, v_cold)
+            assert (st["gn_iters"], st["matvecs"]) == (s_cold["gn_iters"], s_cold["matvecs"])
+        # near the solution (as a trained network's prediction is): kept
+        v, st = ctx.solve(0.8 * v_cold, tol_from_zero=1)
+        assert st["status"] == 0 and st["initial_rejected"] == 0
+        assert st["J0"] < s_cold["J0"]
+
+
 def test_detdefgrad(C):
     nt = 4
     grid, m0, m1, vstar = blob_problem()
