@@ -715,36 +715,6 @@ __global__ __launch_bounds__(kThreads) void k_inc_first(const GT* __restrict__ g
     w[idx] = -half_ht * f;
 }
 
-// four consecutive elements q*4 .. q*4+3 of a float or half field, as float4
-__device__ __forceinline__ float4 ld4(const float* p, long long q) {
-    return reinterpret_cast<const float4*>(p)[q];
-}
-__device__ __forceinline__ float4 ld4(const __half* p, long long q) {
-    const uint2 u = reinterpret_cast<const uint2*>(p)[q];
-    const float2 lo = __half22float2(*reinterpret_cast<const __half2*>(&u.x));
-    const float2 hi = __half22float2(*reinterpret_cast<const __half2*>(&u.y));
-    return make_float4(lo.x, lo.y, hi.x, hi.y);
-}
-
-// k_inc_first on four voxels per thread (16-byte float and 8-byte half loads;
-// n a multiple of 4)
-template <typename GT>
-__global__ __launch_bounds__(kThreads) void k_inc_first4(const GT* __restrict__ gm,
-                                                         const float* __restrict__ vt,
-                                                         float* __restrict__ w, long long n,
-                                                         float half_ht) {
-    const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= (n >> 2)) return;
-    const float4 g0 = ld4(gm, q), g1 = ld4(gm + n, q), g2 = ld4(gm + 2 * n, q);
-    const float4 a0 = ld4(vt, q), a1 = ld4(vt + n, q), a2 = ld4(vt + 2 * n, q);
-    float4 o;
-    o.x = -half_ht * (g0.x * a0.x + g1.x * a1.x + g2.x * a2.x);
-    o.y = -half_ht * (g0.y * a0.y + g1.y * a1.y + g2.y * a2.y);
-    o.z = -half_ht * (g0.z * a0.z + g1.z * a1.z + g2.z * a2.z);
-    o.w = -half_ht * (g0.w * a0.w + g1.w * a1.w + g2.w * a2.w);
-    reinterpret_cast<float4*>(w)[q] = o;
-}
-
 // out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2).
 // ALS: `add` is the PCG recursion als (alpha L s), advanced here in place to
 // (r_a - mean_a) + mu als_a before it is added.
@@ -950,15 +920,8 @@ int launch_adjoint_step(const Geo& g, const float* lam_next, const float* dminus
 template <typename GT>
 int launch_inc_state_first(const Geo& g, const GT* gradm0, const float* vt, float* w0,
                            double ht, hipStream_t s) {
-    const bool vec = (g.n & 3) == 0 &&
-                     ((reinterpret_cast<uintptr_t>(vt) | reinterpret_cast<uintptr_t>(w0)) & 15u) == 0 &&
-                     (reinterpret_cast<uintptr_t>(gradm0) & (4 * sizeof(GT) - 1)) == 0;
-    if (vec)
-        hipLaunchKernelGGL(k_inc_first4<GT>, dim3(blocks_for(g.n / 4)), dim3(kThreads), 0, s,
-                           gradm0, vt, w0, g.n, (float)(0.5 * ht));
-    else
-        hipLaunchKernelGGL(k_inc_first<GT>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0,
-                           vt, w0, g.n, (float)(0.5 * ht));
+    hipLaunchKernelGGL(k_inc_first<GT>, dim3(blocks_for(g.n)), dim3(kThreads), 0, s, gradm0, vt,
+                       w0, g.n, (float)(0.5 * ht));
     CL_LAUNCH_CHECK();
     return 0;
 }
