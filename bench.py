@@ -254,6 +254,42 @@ def cpu_baseline(name, m0, m1, vstar):
                       "kernels and the 32^3 step the same way" % (n + (nt,))}
 
 
+def net_train_timing(steps, R=64, B=4):
+    """Milliseconds per training step of the warm-start network (forward,
+    loss, backward, Adam; the library's MFMA kernels) on random inputs, and
+    the step's convolution flops: 2 x 27 cin cout per output voxel for the
+    forward pass, as much again for the data and the weight gradients (not
+    the first layer's data gradient)."""
+    import torch
+
+    from paper_2401_17493_amd.warmstart import Net
+    ch = (16, 32, 64, 128)
+    net = Net(R, ch, max_batch=B, seed=1)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x0 = torch.rand((B, R, R, R), device="cuda", generator=g)
+    x1 = torch.rand((B, R, R, R), device="cuda", generator=g)
+    tg = 0.1 * torch.randn((B, 3, R, R, R), device="cuda", generator=g)
+    net.train_step(x0, x1, tg, 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x0, x1, tg, 1e-3)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    net.close()
+    c1, c2, c3, c4 = ch
+    layers = [(8, c1, 0), (c1, c1, 0), (c1, c2, 1), (c2, c2, 1), (c2, c3, 2), (c3, c3, 2),
+              (c3, c4, 3), (c4, c4, 3), (c4 + c3, c3, 2), (c3, c3, 2), (c3 + c2, c2, 1),
+              (c2, c2, 1), (c2 + c1, c1, 0), (c1, c1, 0), (c1, 3, 0)]
+    fwd = [2.0 * 27 * ci * co * B * (R >> lv) ** 3 for ci, co, lv in layers]
+    flops = 3 * sum(fwd) - fwd[0]
+    tflops = flops / (ms * 1e-3) / 1e12
+    return {"net_train_ms_per_step": round(ms, 3), "gflop_per_step": round(flops / 1e9, 1),
+            "tflops": round(tflops, 1), "bf16_peak_tflops": 2500.0,
+            "mfma_frac": round(tflops / 2500.0, 4),
+            "config": {"resolution": R, "batch": B, "channels": list(ch)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +317,9 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up at v = v*/2 and launch only the roofline kernel and the copy "
                          "kernel (for hardware-counter runs); prints their timings")
+    ap.add_argument("--net-train-steps", type=int, default=0,
+                    help="> 0: only time this many warm-start network training steps (64^3, "
+                         "batch 4, channels 16-128, random inputs) after one warm-up step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this engine has no multi-GPU path "
@@ -294,6 +333,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.net_train_steps > 0:
+        print(json.dumps(net_train_timing(args.net_train_steps)), flush=True)
+        return
     w, m0_h, m1_h, vstar_h, m1_sha = load_inputs(args.workload)
     golden = load_golden(args.workload, w, args.beta) if args.precond == "reg" else None
     dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
