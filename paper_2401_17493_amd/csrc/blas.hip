@@ -91,15 +91,13 @@ __global__ __launch_bounds__(kThreads) void k_partial_stats(const double* __rest
     }
 }
 
-// (VT: v~ += kappa s;) r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0),
-// kappa from the device slots when pd.sc is set,
-// with per-block max |r| and per-component sums of r -> partial[4 block + {0,1,2,3}]
-template <bool VT>
-__global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restrict__ sd,
-                                                         const float4* __restrict__ hs,
-                                                         float4* __restrict__ vt,
+// r -= kappa Hs over [3][n] (float4 lanes; n % 4 == 0), kappa from the
+// device slots when pd.sc is set, with per-block max |r| and per-component
+// sums of r -> partial[4 block + {0,1,2,3}]
+__global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restrict__ hs,
                                                          float4* __restrict__ r, float kappa,
-                                                         long long n4, double* __restrict__ partial,
+                                                         long long n4,
+                                                         double* __restrict__ partial,
                                                          PcgDev pd) {
     __shared__ double sh[kThreads / kWave];
     double mx = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -108,13 +106,6 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(const float4* __restric
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < 3 * n4; i += stride) {
         const float4 h = hs[i];
         float4 q = r[i];
-        if (VT) {
-            const float4 a = sd[i];
-            float4 v = vt[i];
-            v.x = fmaf(kappa, a.x, v.x); v.y = fmaf(kappa, a.y, v.y);
-            v.z = fmaf(kappa, a.z, v.z); v.w = fmaf(kappa, a.w, v.w);
-            vt[i] = v;
-        }
         q.x = fmaf(-kappa, h.x, q.x); q.y = fmaf(-kappa, h.y, q.y);
         q.z = fmaf(-kappa, h.z, q.z); q.w = fmaf(-kappa, h.w, q.w);
         r[i] = q;
@@ -178,24 +169,17 @@ __global__ __launch_bounds__(kThreads) void k_xpby(const float* __restrict__ x,
     if (i < n) y[i] = fmaf(b, y[i], x[i]);
 }
 
-// PCG direction update with the previous direction s: v~ += kappa s, then
-// s = z + mu s (n4 float4 groups, then the tail of n - 4 n4 floats); MAX: the
-// block's max |s| -> partial[block] (the scale of the mixed matvec's float16
-// sources).
-template <bool MAX>
+// PCG direction update with the previous direction s and the device
+// scalars: v~ += kappa s, then s = z + mu s (n4 float4 groups, then the tail of
+// n - 4 n4 floats); a no-op on a curvature that is not positive and finite.
 __global__ __launch_bounds__(kThreads) void k_pcg_direction(const float4* __restrict__ z,
-                                                            float4* __restrict__ sd, float mu,
-                                                            float4* __restrict__ vt, float kappa,
+                                                            float4* __restrict__ sd,
+                                                            float4* __restrict__ vt,
                                                             long long n4, long long n,
-                                                            double* __restrict__ partial,
                                                             PcgDev pd) {
-    __shared__ double sh[kThreads / kWave];
-    if (pd.sc) {
-        if (!pcg_curv_ok(pd)) return;   // uniform over the grid
-        kappa = (float)(pd.sc[pd.rz] / pd.sc[pd.shs]);
-        mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
-    }
-    double mx = identity<OP_MAX>();
+    if (!pcg_curv_ok(pd)) return;   // uniform over the grid
+    const float kappa = (float)(pd.sc[pd.rz] / pd.sc[pd.shs]);
+    const float mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
     const long long stride = (long long)gridDim.x * kThreads;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n4; i += stride) {
         const float4 a = z[i];
@@ -208,9 +192,6 @@ __global__ __launch_bounds__(kThreads) void k_pcg_direction(const float4* __rest
         v.w = fmaf(mu, v.w, a.w);
         vt[i] = t;
         sd[i] = v;
-        if (MAX)
-            mx = fmax(mx, fmax(fmax(fabs((double)v.x), fabs((double)v.y)),
-                               fmax(fabs((double)v.z), fabs((double)v.w))));
     }
     const float* zs = reinterpret_cast<const float*>(z);
     float* ss = reinterpret_cast<float*>(sd);
@@ -218,13 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_direction(const float4* __rest
     for (long long i = 4 * n4 + (long long)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += stride) {
         ts[i] = fmaf(kappa, ss[i], ts[i]);
-        const float v = fmaf(mu, ss[i], zs[i]);
-        ss[i] = v;
-        if (MAX) mx = fmax(mx, fabs((double)v));
-    }
-    if (MAX) {
-        mx = block_reduce<OP_MAX>(mx, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x] = mx;
+        ss[i] = fmaf(mu, ss[i], zs[i]);
     }
 }
 
@@ -402,21 +377,13 @@ int red_fold_sum(Reducer& r, int nb, int stride, int off, int slot, hipStream_t 
     return 0;
 }
 
-static int pcg_update_impl(Reducer& red, const float* s_dir, const float* hs, float* vt,
-                           float* r, float kappa, const PcgDev& pd, long long n, int smax,
-                           int ssum, hipStream_t st) {
+static int pcg_update_impl(Reducer& red, const float* hs, float* r, float kappa,
+                           const PcgDev& pd, long long n, int smax, int ssum, hipStream_t st) {
     const long long n4 = n / 4;
     unsigned nb = red_blocks(3 * n4);
-    if (vt)
-        hipLaunchKernelGGL(k_pcg_update<true>, dim3(nb), dim3(kThreads), 0, st,
-                           reinterpret_cast<const float4*>(s_dir),
-                           reinterpret_cast<const float4*>(hs), reinterpret_cast<float4*>(vt),
-                           reinterpret_cast<float4*>(r), kappa, n4, red.partial, pd);
-    else
-        hipLaunchKernelGGL(k_pcg_update<false>, dim3(nb), dim3(kThreads), 0, st,
-                           reinterpret_cast<const float4*>(s_dir),
-                           reinterpret_cast<const float4*>(hs), nullptr,
-                           reinterpret_cast<float4*>(r), kappa, n4, red.partial, pd);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kThreads), 0, st,
+                       reinterpret_cast<const float4*>(hs), reinterpret_cast<float4*>(r), kappa,
+                       n4, red.partial, pd);
     CL_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, st, red.partial, (int)nb, 4, 0,
                        red.result, smax, red.mirror);
@@ -427,14 +394,14 @@ static int pcg_update_impl(Reducer& red, const float* s_dir, const float* hs, fl
     return 0;
 }
 
-int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
-               float kappa, long long n, int smax, int ssum, hipStream_t st) {
-    return pcg_update_impl(red, s_dir, hs, vt, r, kappa, PcgDev(), n, smax, ssum, st);
+int pcg_update(Reducer& red, const float* hs, float* r, float kappa, long long n, int smax,
+               int ssum, hipStream_t st) {
+    return pcg_update_impl(red, hs, r, kappa, PcgDev(), n, smax, ssum, st);
 }
 
 int pcg_update_dev(Reducer& red, const float* hs, float* r, const PcgDev& pd, long long n,
                    int smax, int ssum, hipStream_t st) {
-    return pcg_update_impl(red, nullptr, hs, nullptr, r, 0.f, pd, n, smax, ssum, st);
+    return pcg_update_impl(red, hs, r, 0.f, pd, n, smax, ssum, st);
 }
 
 // every fold also wrote its slot to the mapped host mirror r.host: waiting
@@ -467,31 +434,6 @@ int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s) {
     return 0;
 }
 
-int launch_pcg_direction(Reducer* r, const float* z, float* sd, float mu, float* vt,
-                         float kappa, long long n, int slot, hipStream_t s) {
-    if ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(sd) |
-         reinterpret_cast<uintptr_t>(vt)) & 15u) {
-        set_error("pcg direction update needs 16-byte aligned vectors");
-        return CLAIRE_EINVAL;
-    }
-    const unsigned nb = red_blocks(n);
-    if (r) {
-        hipLaunchKernelGGL(k_pcg_direction<true>, dim3(nb), dim3(kThreads), 0, s,
-                           reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
-                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, r->partial,
-                           PcgDev());
-        CL_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_fold<OP_MAX>, dim3(1), dim3(kFoldThreads), 0, s, r->partial, (int)nb,
-                           1, 0, r->result, slot, r->mirror);
-    } else {
-        hipLaunchKernelGGL(k_pcg_direction<false>, dim3(nb), dim3(kThreads), 0, s,
-                           reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), mu,
-                           reinterpret_cast<float4*>(vt), kappa, n / 4, n, nullptr, PcgDev());
-    }
-    CL_LAUNCH_CHECK();
-    return 0;
-}
-
 int launch_pcg_direction_dev(const float* z, float* sd, float* vt, const PcgDev& pd,
                              long long n, hipStream_t s) {
     if ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(sd) |
@@ -499,9 +441,9 @@ int launch_pcg_direction_dev(const float* z, float* sd, float* vt, const PcgDev&
         set_error("pcg direction update needs 16-byte aligned vectors");
         return CLAIRE_EINVAL;
     }
-    hipLaunchKernelGGL(k_pcg_direction<false>, dim3(red_blocks(n)), dim3(kThreads), 0, s,
-                       reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd), 0.f,
-                       reinterpret_cast<float4*>(vt), 0.f, n / 4, n, nullptr, pd);
+    hipLaunchKernelGGL(k_pcg_direction, dim3(red_blocks(n)), dim3(kThreads), 0, s,
+                       reinterpret_cast<const float4*>(z), reinterpret_cast<float4*>(sd),
+                       reinterpret_cast<float4*>(vt), n / 4, n, pd);
     CL_LAUNCH_CHECK();
     return 0;
 }

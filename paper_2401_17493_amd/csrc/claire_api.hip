@@ -588,7 +588,7 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
             if (st < 0) return st;
             if (st) break;
             const double kappa = rz / c->red.host[0];
-            CL_TRY(pcg_update(c->red, c->sd, c->hs, nullptr, c->r, (float)kappa, n, 1, 3, s));
+            CL_TRY(pcg_update(c->red, c->hs, c->r, (float)kappa, n, 1, 3, s));
             CL_TRY(launch_axpy(c->sd, c->vt, (float)kappa, n3, s));
             CL_TRY(red_fetch(c->red, s));
             c->trace_res.push_back(c->red.host[1]);

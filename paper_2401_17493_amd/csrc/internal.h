@@ -257,11 +257,11 @@ int launch_pcg_direction_dev(const float* z, float* sd, float* vt, const PcgDev&
                              long long n, hipStream_t s);
 int launch_als_update_dev(const float* r, float* als, const PcgDev& pd, long long n,
                           hipStream_t s);
-// PCG update (v~ += kappa s when vt is given,) r -= kappa Hs on [3][n]
-// vectors, fused with the reductions of the new residual: max |r| -> slot
-// smax, sum of each component of r -> slots ssum..ssum+2
-int pcg_update(Reducer& red, const float* s_dir, const float* hs, float* vt, float* r,
-               float kappa, long long n, int smax, int ssum, hipStream_t st);
+// PCG residual update r -= kappa Hs on [3][n] vectors (16-byte aligned, n a
+// multiple of 4), fused with the reductions of the new residual: max |r| ->
+// slot smax, sum of each component of r -> slots ssum..ssum+2
+int pcg_update(Reducer& red, const float* hs, float* r, float kappa, long long n, int smax,
+               int ssum, hipStream_t st);
 
 // ------------------------------------------- two-level preconditioner
 // Coarse grid (half the extents) of the two-level zero-velocity
@@ -299,10 +299,6 @@ int twolevel_apply(TwoLevel& T, const Geo& gf, SpectralWork& swf, const float* r
 int launch_axpy(const float* x, float* y, float a, long long n, hipStream_t s);
 // y = x + b*y
 int launch_xpby(const float* x, float* y, float b, long long n, hipStream_t s);
-// PCG direction update with the previous direction: vt += kappa sd, then
-// sd = z + mu sd; with r, max |sd| -> r->result[slot] (16-byte aligned vectors)
-int launch_pcg_direction(Reducer* r, const float* z, float* sd, float mu, float* vt,
-                         float kappa, long long n, int slot, hipStream_t s);
 // y = x + b*z
 int launch_lincomb(const float* x, const float* z, float* y, float b, long long n,
                    hipStream_t s);

@@ -4,8 +4,9 @@
 // Departure points are stored as displacements in voxel units, d = (y - x)/h,
 // so a query is (integer grid index) + (float displacement): the stencil
 // origin floor(d) is exact and a zero displacement returns grid values
-// bit-for-bit. One thread per output voxel, x3 fastest across the wavefront;
-// the 4x4x4 stencil is read with wrapped indices: a mask when the extents are
+// bit-for-bit. Output voxels run x3 fastest across the wavefront (the
+// LDS-staged gathers take two voxels per thread); the 4x4x4 stencil is read
+// with wrapped indices: a mask when the extents are
 // powers of two, a wrap by subtraction (box staging) or modulo (direct
 // gathers) along x1 and x2 on grids with other extents. Single-field gathers
 // and the backtrace are LDS-staged on every grid (ragged bricks on general
