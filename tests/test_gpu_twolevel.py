@@ -168,11 +168,16 @@ def test_full_solve_twolevel(C):
         ctx.set_images(dev(m0), dev(m1))
         v, st = ctx.solve(precond=C.PRECOND_TWOLEVEL)
         vh = host(v)
-    print("two-level solve: GN %d/%d, matvecs %d/%d, inner %d/%d, J %.6g/%.6g, rel_grad %.3f"
-          % (st["gn_iters"], s_ref.gn_iters, st["matvecs"], s_ref.matvecs, st["inner_iters"],
-             s_ref.inner_its, st["J"], s_ref.J, st["rel_grad"]))
+    e_v, e_j = rel_err(vh, v_ref), abs(st["J"] - s_ref.J) / s_ref.J
+    print("two-level solve: GN %d/%d, matvecs %d/%d, inner %d/%d, J %.6g/%.6g (%.2e), "
+          "v %.2e, rel_grad %.3f" % (st["gn_iters"], s_ref.gn_iters, st["matvecs"], s_ref.matvecs,
+                                     st["inner_iters"], s_ref.inner_its, st["J"], s_ref.J, e_j,
+                                     e_v, st["rel_grad"]))
     assert st["status"] == 0 and st["rel_grad"] <= 5e-2
     assert st["gn_iters"] == s_ref.gn_iters
     assert abs(st["matvecs"] - s_ref.matvecs) <= s_ref.gn_iters
-    assert abs(st["J"] - s_ref.J) <= 5e-2 * s_ref.J
-    assert rel_err(vh, v_ref) < 5e-2
+    # the outer PCG is only as exact as its inexact inner solves (88 inner
+    # iterations here against the oracle's 64): observed J 1.4e-6 and v 8.0e-4
+    # with identical outer counts
+    assert e_j <= 1e-4
+    assert e_v <= 2e-3
