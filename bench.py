@@ -497,8 +497,8 @@ def main():
 
     def solve_rec(r):
         st = r["stats"]
-        rec = {k: st[k] for k in ("status", "warning", "gn_iters", "matvecs", "inner_iters",
-                                  "pde_solves", "linesearch_trials",
+        rec = {k: st[k] for k in ("status", "warning", "initial_rejected", "gn_iters", "matvecs",
+                                  "inner_iters", "pde_solves", "linesearch_trials",
                                   "rel_grad", "rel_mismatch", "J0", "J", "det_min", "det_max",
                                   "det_nonpositive")}
         rec.update(converged=converged(r),
