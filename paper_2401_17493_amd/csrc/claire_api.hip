@@ -437,9 +437,11 @@ int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
         CL_TRY(launch_assemble(g, c->lam, gm, nt, (const float*)nullptr, c->ni_tmp, c->s));
         return finish_ni_matvec(c, vt, out, reg_part, dot_slot);
     }
+    if (als_pd)   // reg_part is c->als, advanced inside the assembly
+        return launch_assemble(g, c->lam, gm, nt, (const float*)nullptr, out, c->s, vt, &c->red,
+                               dot_slot, als_pd, c->r, c->als);
     if (dot_slot >= 0)
-        return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot,
-                               als_pd, c->r);
+        return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s, vt, &c->red, dot_slot);
     return launch_assemble(g, c->lam, gm, nt, reg_part, out, c->s);
 }
 

@@ -194,14 +194,15 @@ int launch_inc_state_step(const Geo& g, const float* w_prev, const float* dplus,
                           const GT* gradm_next, const float* vt, float* out, float coef,
                           float sign, hipStream_t s, const int* boxes = nullptr);
 // out = add + h_t sum_j c_j lam^j grad m^j; with dot_with (nullable), also
-// <dot_with, out> summed into red.result[slot]. With als_pd (PCG), `add` is
-// the alpha L s recursion als, first advanced in place to
-// (r - mean(r)) + mu als with the device scalars (r: the residual).
+// <dot_with, out> summed into red.result[slot]. With als_pd (PCG; add NULL),
+// the alpha L s recursion `als` is first advanced in place to
+// (r - mean(r)) + mu als with the device scalars (r: the residual) and added.
 template <typename GT>
 int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt,
                     const float* add, float* out, hipStream_t s,
                     const float* dot_with = nullptr, Reducer* red = nullptr, int slot = 0,
-                    const PcgDev* als_pd = nullptr, const float* r = nullptr);
+                    const PcgDev* als_pd = nullptr, const float* r = nullptr,
+                    float* als = nullptr);
 // float16 copy of grad m^j for the mixed-precision matvec
 int launch_to_half(const float* x, __half* y, long long n, hipStream_t s);
 

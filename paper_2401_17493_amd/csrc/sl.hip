@@ -717,15 +717,16 @@ __global__ __launch_bounds__(kThreads) void k_inc_first(const GT* __restrict__ g
 }
 
 // out_a = add_a + h_t sum_j c_j lam^j d_a m^j  (trapezoid c_0 = c_nt = 1/2).
-// ALS: `add` is the PCG recursion als (alpha L s), advanced here in place to
-// (r_a - mean_a) + mu als_a before it is added.
+// ALS: instead of `add`, the PCG recursion als (alpha L s) is advanced in
+// place to (r_a - mean_a) + mu als_a and added.
 template <bool DOT, bool ALS, typename GT>
 __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__ lam,
                                                        const GT* __restrict__ gm, int nt,
-                                                       const float* add,
+                                                       const float* __restrict__ add,
                                                        float* __restrict__ out, long long n,
                                                        float ht, const float* __restrict__ dv,
                                                        double* __restrict__ partial,
+                                                       float* __restrict__ als,
                                                        const float* __restrict__ r, PcgDev pd) {
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     double dot = 0.0;
@@ -746,10 +747,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble(const float* __restrict__
             float a[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                a[c] = add[c * n + idx];
+                a[c] = als[c * n + idx];
                 if (adv) {
                     a[c] = fmaf(mu, a[c], r[c * n + idx] - am[c]);
-                    const_cast<float*>(add)[c * n + idx] = a[c];
+                    als[c * n + idx] = a[c];
                 }
             }
             acc0 += a[0];
@@ -948,37 +949,39 @@ template int launch_inc_state_step<__half>(const Geo&, const float*, const float
 template <typename GT>
 int launch_assemble(const Geo& g, const float* lam, const GT* gradm, int nt, const float* add,
                     float* out, hipStream_t s, const float* dot_with, Reducer* red, int slot,
-                    const PcgDev* als_pd, const float* r) {
+                    const PcgDev* als_pd, const float* r, float* als) {
     const unsigned nb = blocks_for(g.n);
     const float ht = (float)(1.0 / nt);
-    if (als_pd && (!add || !r || !dot_with)) {
-        set_error("the als update in the assembly needs als, r and the dot product");
+    if (als_pd && (add || !als || !r || !dot_with)) {
+        set_error("the als update in the assembly takes als and r in place of the addend, "
+                  "and the dot product");
         return CLAIRE_EINVAL;
     }
     if (als_pd) {
         hipLaunchKernelGGL((k_assemble<true, true, GT>), dim3(nb), dim3(kThreads), 0, s, lam,
-                           gradm, nt, add, out, g.n, ht, dot_with, red->partial, r, *als_pd);
+                           gradm, nt, nullptr, out, g.n, ht, dot_with, red->partial, als, r,
+                           *als_pd);
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
     }
     if (dot_with) {
         hipLaunchKernelGGL((k_assemble<true, false, GT>), dim3(nb), dim3(kThreads), 0, s, lam,
                            gradm, nt, add, out, g.n, ht, dot_with, red->partial, nullptr,
-                           PcgDev());
+                           nullptr, PcgDev());
         CL_LAUNCH_CHECK();
         return red_fold_sum(*red, (int)nb, 1, 0, slot, s);
     }
     hipLaunchKernelGGL((k_assemble<false, false, GT>), dim3(nb), dim3(kThreads), 0, s, lam, gradm,
-                       nt, add, out, g.n, ht, nullptr, nullptr, nullptr, PcgDev());
+                       nt, add, out, g.n, ht, nullptr, nullptr, nullptr, nullptr, PcgDev());
     CL_LAUNCH_CHECK();
     return 0;
 }
 template int launch_assemble<float>(const Geo&, const float*, const float*, int, const float*,
                                     float*, hipStream_t, const float*, Reducer*, int,
-                                    const PcgDev*, const float*);
+                                    const PcgDev*, const float*, float*);
 template int launch_assemble<__half>(const Geo&, const float*, const __half*, int, const float*,
                                      float*, hipStream_t, const float*, Reducer*, int,
-                                     const PcgDev*, const float*);
+                                     const PcgDev*, const float*, float*);
 
 int brick_table_ints(const Geo& g) { return 6 * gather_brick(g).nbricks; }
 
