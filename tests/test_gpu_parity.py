@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from helpers import Parity, blob_problem, f32, phantom_problem, rel_err, trace_parity
-from synthetic import bandlimited_velocity, ellipsoid_phantom, trig_field
+from synthetic import bandlimited_velocity, ellipsoid_phantom, gaussian_blobs, trig_field
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -220,6 +220,25 @@ def test_full_solve_blobs32(C):
     P.value("J", stats["J"], s_ref.J, TOL)
     trace_parity(P, "blobs32 solve", trace, s_ref.history, TOL)
     P.done()
+
+
+def test_solve_recovers_a_translation(C):
+    """The closed-form case of the whole solve on the GPU: m1 = m0 shifted by
+    4 voxels along x3 is reached exactly by v = 4h e3 (the oracle's pin of its
+    own solve), so the float32 solve to gtol 1e-3 must land there too."""
+    n, nt = 32, 4
+    g = O.Grid((n, n, n))
+    m0 = f32(gaussian_blobs(g.n, 11))
+    m1 = np.roll(m0, 4, axis=2)
+    c = 4 * 2 * np.pi / n
+    with C.Context(g.n, nt, 1e-2, 1) as ctx:
+        ctx.set_images(dev(m0), dev(m1))
+        v, st = ctx.solve(gtol=1e-3)
+        vh = host(v)
+    err = max(np.abs(vh[0]).max(), np.abs(vh[1]).max(), np.abs(vh[2] - c).max()) / c
+    print("translation: GN %d, matvecs %d, max|v - 4h e3| / 4h = %.2e, J/J0 = %.2e"
+          % (st["gn_iters"], st["matvecs"], err, st["J"] / st["J0"]))
+    assert st["status"] == 0 and err <= 5e-3 and st["J"] <= 1e-5 * st["J0"]
 
 
 def test_initial_guess_fallback(C):

@@ -171,6 +171,25 @@ def test_gn_solve_invariants(p):
     assert stats.pde_solves == 2 + 2 * stats.gn_iters + 2 * stats.matvecs + stats.ls_trials
 
 
+def test_gn_solve_recovers_a_translation():
+    """Closed-form solution of the whole solve (Alg. 1): m1 is m0 shifted by 4
+    voxels along x3. The constant velocity v = 4h e3 moves m0 onto m1 exactly
+    (semi-Lagrangian steps of one whole voxel interpolate exactly) and the H1
+    seminorm does not penalise constants, so it is the global minimiser with
+    J = 0. Solved to gtol 1e-3 from v = 0 the oracle lands on it; a wrong sign
+    or term in the gradient, the Hessian or the line search would not."""
+    n, nt = 32, 4
+    g = O.Grid((n, n, n))
+    m0 = gaussian_blobs(g.n, 11)
+    m1 = np.roll(m0, 4, axis=2)
+    v, st, stats = O.gn_solve(g, m0, m1, nt, 1, [1e-2], gtol=1e-3)
+    c = 4 * 2 * np.pi / n
+    err = max(np.abs(v[0]).max(), np.abs(v[1]).max(), np.abs(v[2] - c).max()) / c
+    assert stats.rel_grad <= 1e-3 and not stats.warnings
+    assert err <= 5e-3                          # observed 1.4e-3
+    assert stats.J <= 1e-5 * stats.J0           # observed 2.3e-6 J0
+
+
 def test_pcg_stops_on_nonpositive_curvature():
     """Truncated CG: <s, Hs> <= 0 stops PCG with the current iterate; on the
     first direction the preconditioned steepest-descent direction is taken."""

@@ -82,3 +82,30 @@ def test_swapped_lagrange_weights_are_caught(monkeypatch):
     d_bad[0] += 1.0                                 # off-by-one node shift
     assert np.abs(ok[2:-3] - (np.arange(12.0)[2:-3, None, None] + 0.3)).max() < 1e-12
     assert np.abs(O.interpolate(f, d_bad)[2:-3] - ok[2:-3]).max() > 0.5
+
+
+def _translation_error(max_gn=20):
+    # the whole solve's closed-form case: a 4-voxel shift recovered by v = 4h e3
+    n, nt = 32, 4
+    g = O.Grid((n, n, n))
+    m0 = gaussian_blobs(g.n, 11)
+    m1 = np.roll(m0, 4, axis=2)
+    v, _, _ = O.gn_solve(g, m0, m1, nt, 1, [1e-2], gtol=1e-3, max_gn=max_gn)
+    c = 4 * 2 * np.pi / n
+    return max(np.abs(v[0]).max(), np.abs(v[1]).max(), np.abs(v[2] - c).max()) / c
+
+
+def test_flipped_incremental_adjoint_is_caught(monkeypatch):
+    # final condition lambda~(1) = +m~(1) instead of -m~(1): the Gauss--Newton
+    # Hessian changes sign in its data term and the solve no longer lands on
+    # the translation
+    good = _translation_error()
+    orig = C.incremental_adjoint
+
+    def wrong(st, mt_final):
+        return [-x for x in orig(st, mt_final)]
+
+    monkeypatch.setattr(C, "incremental_adjoint", wrong)
+    bad = _translation_error()
+    monkeypatch.setattr(C, "incremental_adjoint", orig)
+    assert good < 5e-3 and bad > 0.5
