@@ -238,6 +238,70 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
     }
 }
 
+// Narrow layers (at most 16 output columns, e.g. the 16-channel layers at the
+// network's finest level): a workgroup owns a 4x4x16 voxel brick; wave w takes
+// its x1 plane w as four rows of 16 x3 voxels, four MFMA tiles along the
+// voxels that share each weight fragment, so one 16-byte weight load feeds
+// four MFMAs instead of one. The 6x6x18 neighbourhood of all input channels is
+// staged in LDS once. Same fragments and summation order as k_conv_halo.
+constexpr int kNarrowPos = 6 * 6 * 18;
+constexpr int kNarrowMaxC = 48;                // input channels the LDS tile may hold (62 KB)
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __restrict__ wt,
+                                                     int kpad, int cout, int l, ConvOut out) {
+    extern __shared__ __align__(16) bf16 halo[];   // [648][cin]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int lb = l - 2, lb3 = l - 4;             // log2 of bricks along x1, x2 and along x3
+    int bid = blockIdx.x;
+    const int o3 = (bid & ((1 << lb3) - 1)) << 4;
+    bid >>= lb3;
+    const int o2 = (bid & ((1 << lb) - 1)) << 2;
+    bid >>= lb;
+    const int o1 = (bid & ((1 << lb) - 1)) << 2;
+    const int bb = bid >> lb;
+    const int cin = in.ca + in.cb;
+    const int c8 = cin >> 3;                       // 16-byte channel groups per voxel
+    // stage the neighbourhood: position p = (a, b, c) in 6 x 6 x 18, voxel o + (a, b, c) - 1
+    for (int e = threadIdx.x; e < kNarrowPos * c8; e += 256) {
+        const int p = e / c8, cg = e - p * c8;
+        const int a = p / 108, b = (p / 18) % 6, c = p % 18;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+            in_ptr(in, l, bb, (o1 + a - 1) & mask, (o2 + b - 1) & mask, (o3 + c - 1) & mask,
+                   8 * cg));
+        *reinterpret_cast<bf16x8*>(halo + p * cin + 8 * cg) = v;
+    }
+    __syncthreads();
+    // this lane's A rows: voxels (wave, mt, li) of the brick, mt = 0..3
+    int t = 0, ci = 8 * g;
+    while (ci >= cin) { ci -= cin; ++t; }
+    floatx4 acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < kpad; kc += 32) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wt + (size_t)li * kpad + kc + 8 * g);
+        const int pt = t < 27 ? (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3 : 0;
+        const bf16* base = halo + (wave * 108 + li + pt) * cin + ci;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            bf16x8 av = {};
+            if (t < 27) av = *reinterpret_cast<const bf16x8*>(base + mt * 18 * cin);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mt], 0, 0, 0);
+        }
+        ci += 32;
+        while (ci >= cin) { ci -= cin; ++t; }
+    }
+    // results: rows 4 g + r of tile mt = brick voxel (wave, mt, 4 g + r), column li
+    if (li >= cout) return;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            conv_store<EPI>(out, cout, vox(bb, o1 + wave, o2 + mt, o3 + 4 * g + r, l), li,
+                            acc[mt][r]);
+}
+
 // Weight-gradient GEMM: partial[s][row][k] = sum over the voxels of split s
 // of dz[m][row] x(m + o_t)[ci], k = t cin + ci. A workgroup covers 16 rows x
 // 256 columns (64 per wave, 4 MFMA tiles), grid (rowtiles * ktiles, splits);
@@ -920,6 +984,9 @@ int reset_adam(claire_net* n) {
 #ifndef CLAIRE_CONV_HALO
 #define CLAIRE_CONV_HALO 1
 #endif
+#ifndef CLAIRE_CONV_NARROW
+#define CLAIRE_CONV_NARROW 1
+#endif
 #ifndef CLAIRE_WGRAD_LDS
 #define CLAIRE_WGRAD_LDS 1
 #endif
@@ -930,9 +997,14 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
          const ConvOut& out, hipStream_t s) {
     const int cin = in.ca + in.cb;
     const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64));
-    // the halo kernel tiles the grid by 4^3 bricks (mtot = batch 8^l is a multiple of 64)
-    if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
-        (mtot & 63) == 0) {
+    // the halo kernels tile the grid by 4x4x4 or 4x4x16 bricks (mtot = batch 8^l)
+    if (CLAIRE_CONV_NARROW && nrows == 16 && l >= 4 && cin <= kNarrowMaxC && (cin & 7) == 0 &&
+        (mtot & 255) == 0) {
+        const size_t lds = sizeof(bf16) * kNarrowPos * cin;
+        hipLaunchKernelGGL(k_conv_narrow<EPI>, dim3((unsigned)(mtot / 256)), dim3(256), lds, s,
+                           in, wt, kpad, cout, l, out);
+    } else if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
+               (mtot & 63) == 0) {
         const size_t lds = sizeof(bf16) * kHaloPos * cin;
         hipLaunchKernelGGL(k_conv_halo<EPI>, grid, dim3(256), lds, s, in, wt, kpad, nrows, cout,
                            l, out);

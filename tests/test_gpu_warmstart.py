@@ -50,8 +50,11 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
+# (1, 16, 24, 3), (2, 16, 16, 16) and (1, 16, 48, 16) take the narrow-layer
+# kernel (at most 16 output columns, 4x4x16 bricks), the others the 4^3-brick
+# or the unstaged kernel
 @pytest.mark.parametrize("B,R,cin,cout", [(2, 8, 8, 16), (1, 16, 24, 3), (2, 4, 48, 40),
-                                          (1, 2, 16, 8)])
+                                          (1, 2, 16, 8), (2, 16, 16, 16), (1, 16, 48, 16)])
 @pytest.mark.parametrize("act", [0, 1])
 def test_conv3d_forward(WS, B, R, cin, cout, act):
     r = np.random.default_rng(100 + R + cin + cout)
@@ -68,7 +71,7 @@ def test_conv3d_forward(WS, B, R, cin, cout, act):
 
 
 @pytest.mark.parametrize("B,R,cin,cout", [(2, 8, 8, 16), (1, 16, 24, 8), (2, 4, 48, 40),
-                                          (1, 2, 16, 8)])
+                                          (1, 2, 16, 8), (2, 16, 16, 16)])
 def test_conv3d_backward(WS, B, R, cin, cout):
     r = np.random.default_rng(200 + R + cin + cout)
     x = f32(r.standard_normal((B, R, R, R, cin)))
