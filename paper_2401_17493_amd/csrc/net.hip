@@ -490,32 +490,40 @@ __global__ __launch_bounds__(256) void k_bias_partial(const bf16* __restrict__ d
 }
 
 // gw[co][k] = sum_s partial[s][co][k] (co < cout, k < ktot), gb[co] = sum_s pb[s][co]:
-// a workgroup takes 64 consecutive outputs, its 4 waves every 4th split, and
-// the 4 partial sums are added in a fixed order (float64 throughout).
+// a workgroup takes kRedOut consecutive outputs and 256 / kRedOut groups of
+// threads, group q summing every (256 / kRedOut)-th split from q; the group
+// sums are then added pairwise in a fixed tree (float64 throughout). Many
+// small groups keep enough workgroups in flight for the narrow layers, whose
+// outputs are few and whose splits are many.
+constexpr int kRedOut = 16;
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
                                                       const float* __restrict__ pb, int splits,
                                                       int nrows, int kpad, int cout, int ktot,
                                                       int cdz, float* __restrict__ gw,
                                                       float* __restrict__ gb) {
+    constexpr int kGroups = 256 / kRedOut;
     __shared__ double sh[256];
-    const long long idx = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
-    const int sg = threadIdx.x >> 6;
+    const long long idx = (long long)blockIdx.x * kRedOut + (threadIdx.x % kRedOut);
+    const int sg = threadIdx.x / kRedOut;
     const long long nw = (long long)cout * ktot;
     double acc = 0.0;
     if (idx < nw) {
         const int co = (int)(idx / ktot), k = (int)(idx - (long long)co * ktot);
-        for (int s = sg; s < splits; s += 4) acc += partial[((size_t)s * nrows + co) * kpad + k];
+        for (int s = sg; s < splits; s += kGroups)
+            acc += partial[((size_t)s * nrows + co) * kpad + k];
     } else if (idx < nw + cout) {
         const int co = (int)(idx - nw);
-        for (int s = sg; s < splits; s += 4) acc += pb[(size_t)s * cdz + co];
+        for (int s = sg; s < splits; s += kGroups) acc += pb[(size_t)s * cdz + co];
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
+    for (int w = kGroups / 2; w > 0; w >>= 1) {
+        if (sg < w) sh[threadIdx.x] += sh[threadIdx.x + w * kRedOut];
+        __syncthreads();
+    }
     if (sg == 0) {
-        const int t = threadIdx.x;
-        const double sum = (sh[t] + sh[t + 64]) + (sh[t + 128] + sh[t + 192]);
-        if (idx < nw) gw[idx] = (float)sum;
-        else if (idx < nw + cout) gb[idx - nw] = (float)sum;
+        if (idx < nw) gw[idx] = (float)sh[threadIdx.x];
+        else if (idx < nw + cout) gb[idx - nw] = (float)sh[threadIdx.x];
     }
 }
 
@@ -1087,7 +1095,8 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
                        chunk, n->pb);
     CL_LAUNCH_CHECK();
     const long long nw = (long long)L.cout * L.ktot;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + L.cout + 63) / 64)), dim3(256), 0,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + L.cout + kRedOut - 1) / kRedOut)),
+                       dim3(256), 0,
                        n->s, n->partial,
                        n->pb, splits, L.nrows, L.kpad, L.cout, L.ktot, L.coutE, n->g + L.off,
                        n->g + L.off + nw);
@@ -1535,7 +1544,8 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
         hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout, (int)mt,
                            chunk, pb);
         const long long nw = (long long)cout * L.ktot;
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + cout + 63) / 64)), dim3(256), 0,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + cout + kRedOut - 1) / kRedOut)),
+                           dim3(256), 0,
                            s, partial, pb,
                            splits, L.nrows, L.kpad, cout, L.ktot, cout, dw, db);
         const hipError_t e = hipGetLastError();
