@@ -378,10 +378,13 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvIn in, const bf16* __restrict
 // MFMA fragment is one 16-byte LDS read instead of eight 2-byte global
 // loads. Same grid, partial-sum layout and summation order per lane as
 // k_wgrad. Needs both input channel counts and cdz to be multiples of 8.
+// With pb, the workgroups of the first k-tile also sum the staged dz^T rows
+// into the bias partial pb[split][co] (in place of k_bias_partial).
 __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __restrict__ dz,
                                                    int cdz, int l, int mtot, int kpad,
                                                    int ktiles, int chunk,
-                                                   float* __restrict__ partial, int nrows) {
+                                                   float* __restrict__ partial, int nrows,
+                                                   float* __restrict__ pb) {
     __shared__ __align__(16) bf16 sa[16 * 32];     // [co][m]
     __shared__ __align__(16) bf16 sb[256 * 32];    // [k][m]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -408,6 +411,8 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
     floatx4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool bias = pb && kblk == 0;
+    float bacc = 0.f;
     for (int mc = mstart; mc < mend; mc += 32) {
         const int mm = mc + mloc;
         const bool mv = mm < mend;
@@ -436,6 +441,11 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
             for (int j = 0; j < 8; ++j) sb[(kr + j) * 32 + mloc] = v[j];
         }
         __syncthreads();
+        // the bias gradient: the first k-tile's workgroups sum the staged dz^T rows
+        if (bias && threadIdx.x < 16) {
+#pragma unroll
+            for (int m = 0; m < 32; ++m) bacc += (float)sa[threadIdx.x * 32 + m];
+        }
         const bf16x8 av = *reinterpret_cast<const bf16x8*>(sa + li * 32 + 8 * g);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -454,6 +464,8 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
         for (int r = 0; r < 4; ++r)
             partial[((size_t)split * nrows + row0 + 4 * g + r) * kpad + kc + li] = acc[nt][r];
     }
+    if (bias && threadIdx.x < 16 && row0 + threadIdx.x < cdz)
+        pb[(size_t)split * cdz + row0 + threadIdx.x] = bacc;
 }
 
 // pb[s][c] = sum over the voxels of split s of dz[m][c]: the 256 threads
@@ -1084,15 +1096,16 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
     wgrad_split(mt, splits, chunk);
     const int ktiles = (L.kpad + 255) / 256;
     const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-    if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0)
+    if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0) {
         hipLaunchKernelGGL(k_wgrad_lds, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
-                           (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows);
-    else
+                           (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows, n->pb);
+    } else {
         hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
                            (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows);
-    CL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, n->s, dz, L.coutE, (int)mt,
-                       chunk, n->pb);
+        CL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, n->s, dz, L.coutE,
+                           (int)mt, chunk, n->pb);
+    }
     CL_LAUNCH_CHECK();
     const long long nw = (long long)L.cout * L.ktot;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + L.cout + kRedOut - 1) / kRedOut)),
@@ -1535,14 +1548,15 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
     if (rc >= 0) {
         const int ktiles = (L.kpad + 255) / 256;
         const dim3 wgrid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-        if (kWgradLds && cin % 8 == 0 && cout % 8 == 0)
+        if (kWgradLds && cin % 8 == 0 && cout % 8 == 0) {
             hipLaunchKernelGGL(k_wgrad_lds, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16,
-                               cout, l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows);
-        else
+                               cout, l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows, pb);
+        } else {
             hipLaunchKernelGGL(k_wgrad, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16, cout,
                                l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows);
-        hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout, (int)mt,
-                           chunk, pb);
+            hipLaunchKernelGGL(k_bias_partial, dim3(splits), dim3(256), 0, s, S.dz16, cout,
+                               (int)mt, chunk, pb);
+        }
         const long long nw = (long long)cout * L.ktot;
         hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + cout + kRedOut - 1) / kRedOut)),
                            dim3(256), 0,
