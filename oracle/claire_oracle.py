@@ -473,16 +473,30 @@ def objective(grid, m0, m1, v, alpha, nt, p, beta=0.0):
 # ----------------------------------------------------------------------------
 # Gauss--Newton Hessian matvec (eqs. e:matvec, e:incstate, e:incadj; GN drop)
 # ----------------------------------------------------------------------------
-def incremental_state(st, vt):
+def incremental_state(st, vt, f_eval="grid"):
     """Incremental state m~(1) (eq. e:incstate) by SL with RK2 along the
-    characteristics of v: D m~/Dt = f, f^j = -grad m^j . v~ formed on the grid
-    and interpolated at the departure points."""
+    characteristics of v: D m~/Dt = f with f = -grad m . v~.
+
+    ``f_eval`` chooses how f is evaluated at the departure points (Section
+    2.5.2 allows both readings): "grid" forms the product f^j = -grad m^j . v~
+    on the grid and interpolates it (derivatives taken on the regular mesh,
+    the form the GPU path computes); "factors" interpolates grad m^j and v~
+    separately and multiplies at the departure point (f as a function of its
+    interpolated arguments). The two differ by interpolation error only: they
+    agree exactly when every departure point is a grid point."""
+    if f_eval not in ("grid", "factors"):
+        raise ValueError("f_eval must be 'grid' or 'factors'")
     nt, ht = st.nt, 1.0 / st.nt
     mt = np.zeros(st.grid.n)
+    if f_eval == "factors":
+        vt_y = interpolate(vt, st.d_plus)
     f_j = -np.sum(st.grad_m[0] * vt, axis=0)
     for j in range(nt):
         u_y = interpolate(mt, st.d_plus)
-        f0 = interpolate(f_j, st.d_plus)
+        if f_eval == "factors":
+            f0 = -np.sum(interpolate(st.grad_m[j], st.d_plus) * vt_y, axis=0)
+        else:
+            f0 = interpolate(f_j, st.d_plus)
         # f does not depend on m~, so the RK2 predictor does not enter f1
         f1 = -np.sum(st.grad_m[j + 1] * vt, axis=0)
         mt = u_y + 0.5 * ht * (f0 + f1)
@@ -502,11 +516,11 @@ def incremental_adjoint(st, mt_final):
     return lt
 
 
-def hessian_matvec(st, vt):
+def hessian_matvec(st, vt, f_eval="grid"):
     """H v~ = alpha L v~ + int_0^1 lambda~ grad m dt (eq. e:matvec, GN form),
-    trapezoidal rule in time."""
+    trapezoidal rule in time. ``f_eval``: see incremental_state."""
     vt = np.asarray(vt, dtype=np.float64)
-    lt = incremental_adjoint(st, incremental_state(st, vt))
+    lt = incremental_adjoint(st, incremental_state(st, vt, f_eval))
     c = trapezoid_weights(st.nt)
     data = sum(c[j] * lt[j] * st.grad_m[j] for j in range(st.nt + 1)) / st.nt
     if st.beta > 0.0:

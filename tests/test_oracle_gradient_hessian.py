@@ -225,3 +225,51 @@ def test_memory_lean_setup_matches_stored():
         assert isinstance(lean.grad_m, O.RecomputedGradients) and lean.lam is None
         assert np.array_equal(st.g, lean.g) and st.J == lean.J
         assert np.array_equal(O.hessian_matvec(st, vt), O.hessian_matvec(lean, vt))
+
+
+def _smooth_problem(n, nt=4):
+    """Images and velocities made of a few fixed Fourier modes: the same
+    functions at every n, so discretisation gaps can be followed under
+    refinement."""
+    g = O.Grid((n, n, n))
+    X = np.meshgrid(*[np.arange(k) * 2 * np.pi / k for k in g.n], indexing="ij")
+    m0 = np.sin(X[0]) * np.cos(X[1]) + 0.5 * np.sin(X[2] + X[0])
+    m1 = np.cos(X[0] + 0.3) * np.sin(X[1])
+    v = np.stack([0.3 * np.sin(X[1]), 0.2 * np.cos(X[2]), 0.25 * np.sin(X[0] + X[1])])
+    vt = np.stack([np.cos(X[2]), np.sin(X[0]) * np.sin(X[1]), 0.5 * np.cos(X[1] - X[2])])
+    return O.setup_velocity(g, m0, m1, v, 1e-2, nt, 1), vt
+
+
+def _f_eval_gap(st, vt):
+    a, b = O.incremental_state(st, vt), O.incremental_state(st, vt, "factors")
+    ha, hb = O.hessian_matvec(st, vt), O.hessian_matvec(st, vt, "factors")
+    return (np.abs(a - b).max() / np.abs(a).max(), np.abs(ha - hb).max() / np.abs(ha).max())
+
+
+def test_departure_f_variants_agree_on_whole_voxel_shifts():
+    # every departure point is a grid point: interpolation is a shift, and the
+    # shifted product equals the product of the shifted factors
+    n, nt = 8, 2
+    g = O.Grid((n, n, n))
+    shift = np.array([1, -1, 2])
+    v = np.stack([np.full(g.n, shift[a] * g.h[a] * nt) for a in range(3)])
+    st = O.setup_velocity(g, gaussian_blobs(g.n, 3, sigma=0.9), gaussian_blobs(g.n, 4, sigma=0.9),
+                          v, 1e-2, nt, 1)
+    vt = bandlimited_velocity(g.n, 5, 3, 1.0)
+    gap_mt, gap_hv = _f_eval_gap(st, vt)
+    assert gap_mt <= 1e-13 and gap_hv <= 1e-13
+    with pytest.raises(ValueError):
+        O.incremental_state(st, vt, "both")
+
+
+def test_departure_f_variants_gap_converges():
+    # Section 2.5.2 leaves open whether f is interpolated as a grid product or
+    # factor by factor; for smooth fields the two differ by the tricubic
+    # interpolation error, O(h^4): the gap must fall by well over 2^3 per
+    # halving of h (a variant that skipped interpolating a factor, or took
+    # the wrong time level, would not converge at all)
+    g32 = _f_eval_gap(*_smooth_problem(32))
+    g64 = _f_eval_gap(*_smooth_problem(64))
+    for coarse, fine in zip(g32, g64):
+        assert coarse / fine >= 10.0
+    assert max(g64) <= 2e-5

@@ -109,3 +109,43 @@ def test_flipped_incremental_adjoint_is_caught(monkeypatch):
     bad = _translation_error()
     monkeypatch.setattr(C, "incremental_adjoint", orig)
     assert good < 5e-3 and bad > 0.5
+
+
+def _factor_gap_ratio():
+    """Gap between the two readings of f at the departure points (grid
+    product, factors), smooth fields at 32^3 over 64^3."""
+    gaps = []
+    for n in (32, 64):
+        g = O.Grid((n, n, n))
+        X = np.meshgrid(*[np.arange(k) * 2 * np.pi / k for k in g.n], indexing="ij")
+        m0 = np.sin(X[0]) * np.cos(X[1]) + 0.5 * np.sin(X[2] + X[0])
+        v = np.stack([0.3 * np.sin(X[1]), 0.2 * np.cos(X[2]), 0.25 * np.sin(X[0] + X[1])])
+        vt = np.stack([np.cos(X[2]), np.sin(X[0]) * np.sin(X[1]), 0.5 * np.cos(X[1] - X[2])])
+        st = C.setup_velocity(g, m0, np.cos(X[0]), v, 1e-2, 4, 1)
+        a, b = C.incremental_state(st, vt), C.incremental_state(st, vt, "factors")
+        gaps.append(np.abs(a - b).max() / np.abs(a).max())
+    return gaps[0] / gaps[1]
+
+
+def test_uninterpolated_velocity_factor_is_caught(monkeypatch):
+    good = _factor_gap_ratio()
+    orig = C.incremental_state
+
+    def wrong(st, vt, f_eval="grid"):
+        if f_eval == "grid":
+            return orig(st, vt)
+        nt, ht = st.nt, 1.0 / st.nt
+        mt = np.zeros(st.grid.n)
+        for j in range(nt):
+            u_y = C.interpolate(mt, st.d_plus)
+            # v~ taken at the arrival point instead of the departure point
+            f0 = -np.sum(C.interpolate(st.grad_m[j], st.d_plus) * vt, axis=0)
+            f1 = -np.sum(st.grad_m[j + 1] * vt, axis=0)
+            mt = u_y + 0.5 * ht * (f0 + f1)
+        return mt
+
+    monkeypatch.setattr(C, "incremental_state", wrong)
+    bad = _factor_gap_ratio()
+    monkeypatch.setattr(C, "incremental_state", orig)
+    # the convergence pin asks for a ratio of at least 10
+    assert good >= 10.0 and bad < 10.0
