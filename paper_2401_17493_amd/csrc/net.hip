@@ -77,14 +77,28 @@ struct ConvOut {
     const float* bias;
 };
 
+// Reduction range of split z of gridDim.z over kpad (multiples of 32), and
+// this lane's first (tap, channel) pair k = t cin + ci in it.
+__device__ __forceinline__ void conv_krange(int kpad, int cin, int g, int& kc0, int& kc1, int& t,
+                                            int& ci) {
+    const int ks = kpad >> 5, per = (ks + (int)gridDim.z - 1) / (int)gridDim.z;
+    kc0 = min(ks, (int)blockIdx.z * per) << 5;
+    kc1 = min(ks, ((int)blockIdx.z + 1) * per) << 5;
+    const int k0 = kc0 + 8 * g;
+    t = k0 / cin;
+    ci = k0 - t * cin;
+}
+
 // Implicit-GEMM convolution: each wave computes 16 voxels x 64 output
 // channels (4 MFMA tiles), a workgroup 64 voxels; grid (ceil(mtot/64),
-// ceil(nrows/64)). wt: [nrows][kpad] bfloat16, zero beyond cout rows and
-// 27 cin columns; cin = ca + cb and both multiples of 8.
+// ceil(nrows/64), splits). wt: [nrows][kpad] bfloat16, zero beyond cout rows
+// and 27 cin columns; cin = ca + cb and both multiples of 8. With more than
+// one split (grids too small to fill the chip) split z sums its share of the
+// reduction into part[z][m][nrows] and k_conv_reduce applies the epilogue.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_conv(ConvIn in, const bf16* __restrict__ wt, int kpad,
                                               int nrows, int cout, int l, int mtot,
-                                              ConvOut out) {
+                                              ConvOut out, float* __restrict__ part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int mask = (1 << l) - 1;
@@ -94,12 +108,12 @@ __global__ __launch_bounds__(256) void k_conv(ConvIn in, const bf16* __restrict_
     const int m = mbase + li;
     const bool mval = m < mtot;
     const int i3 = m & mask, i2 = (m >> l) & mask, i1 = (m >> (2 * l)) & mask, bb = m >> (3 * l);
-    int t = 0, ci = 8 * g;
-    while (ci >= cin) { ci -= cin; ++t; }
+    int kc0, kc1, t, ci;
+    conv_krange(kpad, cin, g, kc0, kc1, t, ci);
     floatx4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < kpad; kc += 32) {
+    for (int kc = kc0; kc < kc1; kc += 32) {
         bf16x8 av = {};
         if (mval && t < 27) {
             const int o1 = t / 9 - 1, o2 = (t / 3) % 3 - 1, o3 = t % 3 - 1;
@@ -117,6 +131,20 @@ __global__ __launch_bounds__(256) void k_conv(ConvIn in, const bf16* __restrict_
         }
         ci += 32;
         while (ci >= cin) { ci -= cin; ++t; }
+    }
+    if (gridDim.z > 1) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int co = n0 + nt * 16 + li;
+            if (n0 + nt * 16 >= nrows) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int mo = mbase + 4 * g + r;
+                if (mo < mtot)
+                    part[((size_t)blockIdx.z * mtot + mo) * nrows + co] = acc[nt][r];
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -178,7 +206,7 @@ constexpr int kHaloMaxC = 144;                 // input channels the LDS tile ma
 template <int EPI>
 __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __restrict__ wt,
                                                    int kpad, int nrows, int cout, int l,
-                                                   ConvOut out) {
+                                                   ConvOut out, float* __restrict__ part) {
     extern __shared__ __align__(16) bf16 halo[];   // [216][cin]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
@@ -204,12 +232,12 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
     __syncthreads();
     // this lane's A row: brick voxel (wave, li / 4, li % 4)
     const int prow = wave * 36 + (li >> 2) * 6 + (li & 3);
-    int t = 0, ci = 8 * g;
-    while (ci >= cin) { ci -= cin; ++t; }
+    int kc0, kc1, t, ci;
+    conv_krange(kpad, cin, g, kc0, kc1, t, ci);
     floatx4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < kpad; kc += 32) {
+    for (int kc = kc0; kc < kc1; kc += 32) {
         bf16x8 av = {};
         if (t < 27) {
             const int pt = (t / 9) * 36 + ((t / 3) % 3) * 6 + t % 3;
@@ -228,6 +256,19 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
         while (ci >= cin) { ci -= cin; ++t; }
     }
     // results: rows 4 g + r of the wave's 16 voxels = brick voxel (wave, g, r)
+    if (gridDim.z > 1) {
+        const long long mtot = (long long)gridDim.x << 6;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int co = n0 + nt * 16 + li;
+            if (n0 + nt * 16 >= nrows) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[((size_t)blockIdx.z * mtot + vox(bb, o1 + wave, o2 + g, o3 + r, l)) * nrows +
+                     co] = acc[nt][r];
+        }
+        return;
+    }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int co = n0 + nt * 16 + li;
@@ -300,6 +341,21 @@ __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __re
         for (int r = 0; r < 4; ++r)
             conv_store<EPI>(out, cout, vox(bb, o1 + wave, o2 + mt, o3 + 4 * g + r, l), li,
                             acc[mt][r]);
+}
+
+// Sum of the reduction splits of a convolution in split order, then the
+// epilogue: y[m][co] for co < cout from part[z][m][nrows].
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv_reduce(const float* __restrict__ part, int nsplit,
+                                                     long long mtot, int nrows, int cout,
+                                                     ConvOut out) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= mtot * cout) return;
+    const long long mo = idx / cout;
+    const int co = (int)(idx - mo * cout);
+    float a = 0.f;
+    for (int z = 0; z < nsplit; ++z) a += part[((size_t)z * mtot + mo) * nrows + co];
+    conv_store<EPI>(out, cout, mo, co, a);
 }
 
 // Weight-gradient GEMM: partial[s][row][k] = sum over the voxels of split s
@@ -871,6 +927,18 @@ void wgrad_split(long long mtot, int& splits, int& chunk) {
     chunk = (int)ch;
 }
 
+// Reduction splits of a convolution whose 64 x 64 tiles alone would leave
+// most of the chip idle (the coarse levels): enough splits for about 768
+// workgroups, each keeping at least 8 of the kpad / 32 reduction steps.
+int conv_splits(long long mtot, int nrows, int kpad) {
+    const long long tiles = ((mtot + 63) / 64) * ((nrows + 63) / 64);
+    if (tiles >= 384) return 1;
+    long long sp = (768 + tiles - 1) / tiles;
+    const long long smax = (kpad / 32) / 8;
+    if (sp > smax) sp = smax;
+    return sp < 1 ? 1 : (int)sp;
+}
+
 int net_alloc(claire_net* n) {
     const int c1 = n->c[0], c2 = n->c[1], c3 = n->c[2], c4 = n->c[3];
     const int dims[kLayers][2] = {
@@ -948,6 +1016,15 @@ int net_alloc(claire_net* n) {
         if (need > n->partial_cap) n->partial_cap = need;
         const long long needb = (long long)splits * n->L[i].coutE;
         if (needb > n->pb_cap) n->pb_cap = needb;
+        // the same buffer holds the reduction splits of the coarse-level
+        // convolutions (forward and backward data), which run between
+        // weight gradients on the same stream
+        const NetLayer& L = n->L[i];
+        const long long mt = ml[lvl[i]];
+        const long long needf = (long long)conv_splits(mt, L.nrows, L.kpad) * mt * L.nrows;
+        const long long needd = (long long)conv_splits(mt, L.nrowsT, L.kpadT) * mt * L.nrowsT;
+        if (needf > n->partial_cap) n->partial_cap = needf;
+        if (needd > n->partial_cap) n->partial_cap = needd;
     }
     CL_TRY(dalloc(&n->partial, n->partial_cap));
     CL_TRY(dalloc(&n->pb, n->pb_cap));
@@ -1014,12 +1091,17 @@ constexpr bool kWgradLds = CLAIRE_WGRAD_LDS;
 
 template <int EPI>
 int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
-         const ConvOut& out, hipStream_t s) {
+         const ConvOut& out, hipStream_t s, float* part = nullptr, long long part_cap = 0) {
     const int cin = in.ca + in.cb;
-    const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64));
     // the halo kernels tile the grid by 4x4x4 or 4x4x16 bricks (mtot = batch 8^l)
-    if (CLAIRE_CONV_NARROW && nrows == 16 && l >= 4 && cin <= kNarrowMaxC && (cin & 7) == 0 &&
-        (mtot & 255) == 0) {
+    const bool narrow = CLAIRE_CONV_NARROW && nrows == 16 && l >= 4 && cin <= kNarrowMaxC &&
+                        (cin & 7) == 0 && (mtot & 255) == 0;
+    // reduction splits: k_conv and k_conv_halo only
+    int splits = part && !narrow ? conv_splits(mtot, nrows, kpad) : 1;
+    if ((long long)splits * mtot * nrows > part_cap) splits = 1;
+    const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64),
+                    (unsigned)splits);
+    if (narrow) {
         const size_t lds = sizeof(bf16) * kNarrowPos * cin;
         hipLaunchKernelGGL(k_conv_narrow<EPI>, dim3((unsigned)(mtot / 256)), dim3(256), lds, s,
                            in, wt, kpad, cout, l, out);
@@ -1027,12 +1109,17 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
                (mtot & 63) == 0) {
         const size_t lds = sizeof(bf16) * kHaloPos * cin;
         hipLaunchKernelGGL(k_conv_halo<EPI>, grid, dim3(256), lds, s, in, wt, kpad, nrows, cout,
-                           l, out);
+                           l, out, part);
     } else {
         hipLaunchKernelGGL(k_conv<EPI>, grid, dim3(256), 0, s, in, wt, kpad, nrows, cout, l,
-                           (int)mtot, out);
+                           (int)mtot, out, part);
     }
     CL_LAUNCH_CHECK();
+    if (splits > 1) {
+        hipLaunchKernelGGL(k_conv_reduce<EPI>, dim3(nblk(mtot * cout)), dim3(256), 0, s, part,
+                           splits, mtot, nrows, cout, out);
+        CL_LAUNCH_CHECK();
+    }
     return 0;
 }
 
@@ -1041,6 +1128,11 @@ ConvIn cat_up(const bf16* up, int cu, const bf16* skip, int cs) {
     return ConvIn{up, cu, 1, skip, cs};
 }
 
+// Split buffer for forward convolutions: batches of one (the warm start's
+// inference) keep the single-pass reduction, so the initial guess the solver
+// receives does not change with the training-side splitting.
+float* fwd_part(claire_net* n, int batch) { return batch > 1 ? n->partial : nullptr; }
+
 // forward layer with LeakyReLU into y (bfloat16)
 int fwd(claire_net* n, int li, const ConvIn& in, int level, int batch, bf16* y) {
     const NetLayer& L = n->L[li];
@@ -1048,7 +1140,8 @@ int fwd(claire_net* n, int li, const ConvIn& in, int level, int batch, bf16* y) 
     o.y16 = y;
     o.bias = n->p + L.off + (long long)L.cout * L.ktot;
     return conv<EPI_ACT>(in, L.wt, L.kpad, L.nrows, L.cout, n->l - level,
-                         vox_level(n, level, batch), o, n->s);
+                         vox_level(n, level, batch), o, n->s, fwd_part(n, batch),
+                         n->partial_cap);
 }
 
 int pool(claire_net* n, const bf16* x, int C, int level_out, int batch, bf16* y) {
@@ -1085,7 +1178,8 @@ int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
     ConvOut o{};
     o.y32 = n->vout;
     o.bias = n->p + H.off + (long long)H.cout * H.ktot;
-    return conv<EPI_LINEAR>(one(n->d1, c1), H.wt, H.kpad, H.nrows, H.cout, n->l, mt, o, n->s);
+    return conv<EPI_LINEAR>(one(n->d1, c1), H.wt, H.kpad, H.nrows, H.cout, n->l, mt, o, n->s,
+                            fwd_part(n, batch), n->partial_cap);
 }
 
 // weight and bias gradient of layer li from its input view and dz
@@ -1125,7 +1219,7 @@ int dgrad_act(claire_net* n, int li, const bf16* dz, const bf16* yprev, int leve
     o.y16 = dz_prev;
     o.yprev = yprev;
     return conv<EPI_DGRAD_ACT>(one(dz, L.coutE), L.wtT, L.kpadT, L.nrowsT, L.cin, n->l - level,
-                               vox_level(n, level, batch), o, n->s);
+                               vox_level(n, level, batch), o, n->s, n->partial, n->partial_cap);
 }
 
 // backward data into float32, channels < csplit to a, the rest to b
@@ -1137,7 +1231,7 @@ int dgrad_raw(claire_net* n, int li, const bf16* dz, int level, int batch, int c
     o.y32b = b;
     o.csplit = csplit;
     return conv<EPI_DGRAD_RAW>(one(dz, L.coutE), L.wtT, L.kpadT, L.nrowsT, L.cin, n->l - level,
-                               vox_level(n, level, batch), o, n->s);
+                               vox_level(n, level, batch), o, n->s, n->partial, n->partial_cap);
 }
 
 int up_adjoint(claire_net* n, const float* dxa, const bf16* y, int C, int level_c, int batch,
