@@ -101,7 +101,8 @@ int claire_resample(const float* src, int n_src, float* dst, int n_dst, int ncom
  * [batch][R^3][cin] float32 (rounded to bfloat16 on the way in), w
  * [cout][27][cin], b [cout] float32 (w rounded to bfloat16), y
  * [batch][R^3][cout] float32 = conv (act = 0) or LeakyReLU(conv) (act = 1),
- * not rounded. cin a multiple of 8. */
+ * not rounded. cin a multiple of 8. The network's kernels for the shape run,
+ * reduction splits of small grids included. */
 int claire_conv3d(const float* x, const float* w, const float* b, int batch, int res,
                   int cin, int cout, int act, float* y, void* stream);
 

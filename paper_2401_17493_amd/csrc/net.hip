@@ -279,15 +279,18 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
     }
 }
 
-// Narrow layers (at most 16 output columns, e.g. the 16-channel layers at the
-// network's finest level): a workgroup owns a 4x4x16 voxel brick; wave w takes
-// its x1 plane w as four rows of 16 x3 voxels, four MFMA tiles along the
-// voxels that share each weight fragment, so one 16-byte weight load feeds
-// four MFMAs instead of one. The 6x6x18 neighbourhood of all input channels is
-// staged in LDS once. Same fragments and summation order as k_conv_halo.
+// Narrow layers (at most 16 x NG output columns, e.g. the 16-channel layers at
+// the network's finest level): a workgroup owns a 4x4x16 voxel brick; wave w
+// takes its x1 plane w as four rows of 16 x3 voxels, four MFMA tiles along
+// the voxels that share each weight fragment, so one 16-byte weight load
+// feeds four MFMAs instead of one, and each A fragment read from LDS feeds
+// the NG column groups. The 6x6x18 neighbourhood of all input channels is
+// staged in LDS once. Same fragments and summation order per output as
+// k_conv_halo.
 constexpr int kNarrowPos = 6 * 6 * 18;
 constexpr int kNarrowMaxC = 48;                // input channels the LDS tile may hold (62 KB)
-template <int EPI>
+constexpr int kNarrowMaxNG = 4;                // column groups of 16
+template <int EPI, int NG>
 __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __restrict__ wt,
                                                      int kpad, int cout, int l, ConvOut out) {
     extern __shared__ __align__(16) bf16 halo[];   // [648][cin]
@@ -317,30 +320,43 @@ __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __re
     // this lane's A rows: voxels (wave, mt, li) of the brick, mt = 0..3
     int t = 0, ci = 8 * g;
     while (ci >= cin) { ci -= cin; ++t; }
-    floatx4 acc[4];
+    floatx4 acc[NG][4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[gi][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < kpad; kc += 32) {
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wt + (size_t)li * kpad + kc + 8 * g);
+        bf16x8 bv[NG];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi)
+            bv[gi] = *reinterpret_cast<const bf16x8*>(wt + (size_t)(gi * 16 + li) * kpad + kc +
+                                                      8 * g);
         const int pt = t < 27 ? (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3 : 0;
         const bf16* base = halo + (wave * 108 + li + pt) * cin + ci;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             bf16x8 av = {};
             if (t < 27) av = *reinterpret_cast<const bf16x8*>(base + mt * 18 * cin);
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mt], 0, 0, 0);
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi)
+                acc[gi][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[gi], acc[gi][mt], 0,
+                                                                      0, 0);
         }
         ci += 32;
         while (ci >= cin) { ci -= cin; ++t; }
     }
-    // results: rows 4 g + r of tile mt = brick voxel (wave, mt, 4 g + r), column li
-    if (li >= cout) return;
+    // results: rows 4 g + r of tile mt = brick voxel (wave, mt, 4 g + r), column 16 gi + li
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int gi = 0; gi < NG; ++gi) {
+        const int co = gi * 16 + li;
+        if (co >= cout) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            conv_store<EPI>(out, cout, vox(bb, o1 + wave, o2 + mt, o3 + 4 * g + r, l), li,
-                            acc[mt][r]);
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                conv_store<EPI>(out, cout, vox(bb, o1 + wave, o2 + mt, o3 + 4 * g + r, l), co,
+                                acc[gi][mt][r]);
+    }
 }
 
 // Sum of the reduction splits of a convolution in split order, then the
@@ -1093,9 +1109,13 @@ template <int EPI>
 int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
          const ConvOut& out, hipStream_t s, float* part = nullptr, long long part_cap = 0) {
     const int cin = in.ca + in.cb;
-    // the halo kernels tile the grid by 4x4x4 or 4x4x16 bricks (mtot = batch 8^l)
-    const bool narrow = CLAIRE_CONV_NARROW && nrows == 16 && l >= 4 && cin <= kNarrowMaxC &&
-                        (cin & 7) == 0 && (mtot & 255) == 0;
+    // the halo kernels tile the grid by 4x4x4 or 4x4x16 bricks (mtot = batch 8^l);
+    // the narrow kernel takes up to 4 column groups where its 256-voxel bricks
+    // still give at least 256 workgroups
+    const int ng = nrows / 16;
+    const bool narrow = CLAIRE_CONV_NARROW && nrows <= 16 * kNarrowMaxNG && l >= 4 &&
+                        cin <= kNarrowMaxC && (cin & 7) == 0 && (mtot & 255) == 0 &&
+                        (ng == 1 || mtot >= 256LL * 256);
     // reduction splits: k_conv and k_conv_halo only
     int splits = part && !narrow ? conv_splits(mtot, nrows, kpad) : 1;
     if ((long long)splits * mtot * nrows > part_cap) splits = 1;
@@ -1103,8 +1123,19 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
                     (unsigned)splits);
     if (narrow) {
         const size_t lds = sizeof(bf16) * kNarrowPos * cin;
-        hipLaunchKernelGGL(k_conv_narrow<EPI>, dim3((unsigned)(mtot / 256)), dim3(256), lds, s,
-                           in, wt, kpad, cout, l, out);
+        const dim3 ngrid((unsigned)(mtot / 256));
+        if (ng == 1)
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 1>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
+        else if (ng == 2)
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 2>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
+        else if (ng == 3)
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 3>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
+        else
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 4>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
     } else if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
                (mtot & 63) == 0) {
         const size_t lds = sizeof(bf16) * kHaloPos * cin;
@@ -1600,15 +1631,21 @@ int claire_conv3d(const float* x, const float* w, const float* b, int batch, int
     const long long mt = (long long)batch * res * res * res;
     const NetLayer L = layer_geometry(cin, cout);
     LayerScratch S;
+    float* part = nullptr;
+    const long long part_cap = (long long)conv_splits(mt, L.nrows, L.kpad) * mt * L.nrows;
     int rc = layer_setup(S, L, x, w, nullptr, mt, s);
+    if (rc >= 0) rc = dalloc(&part, part_cap);
     if (rc >= 0) {
         ConvOut o{};
         o.bias = b;
         o.y32 = y;
-        rc = act ? conv<EPI_ACT32>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt, o, s)
-                 : conv<EPI_LINEAR>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt, o, s);
+        rc = act ? conv<EPI_ACT32>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt, o,
+                                   s, part, part_cap)
+                 : conv<EPI_LINEAR>(one(S.x16, cin), S.wt, L.kpad, L.nrows, cout, lg2(res), mt,
+                                    o, s, part, part_cap);
     }
     S.release(s);
+    dfree(part);
     return rc < 0 ? rc : 0;
 }
 
@@ -1630,14 +1667,20 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
     float *partial = nullptr, *pb = nullptr;
     int splits, chunk;
     wgrad_split(mt, splits, chunk);
+    // one buffer for the data gradient's reduction splits and, after it on
+    // the same stream, the weight gradient's partial sums
+    long long part_cap = (long long)splits * L.nrows * L.kpad;
+    const long long dcap = (long long)conv_splits(mt, L.nrowsT, L.kpadT) * mt * L.nrowsT;
+    if (dcap > part_cap) part_cap = dcap;
     int rc = layer_setup(S, L, x, w, dz, mt, s);
-    if (rc >= 0) rc = dalloc(&partial, (long long)splits * L.nrows * L.kpad);
+    if (rc >= 0) rc = dalloc(&partial, part_cap);
     if (rc >= 0) rc = dalloc(&pb, (long long)splits * L.coutE);
     if (rc >= 0) {
         ConvOut o{};
         o.y32 = dx;
         o.csplit = cin;
-        rc = conv<EPI_DGRAD_RAW>(one(S.dz16, cout), S.wtT, L.kpadT, L.nrowsT, cin, l, mt, o, s);
+        rc = conv<EPI_DGRAD_RAW>(one(S.dz16, cout), S.wtT, L.kpadT, L.nrowsT, cin, l, mt, o, s,
+                                 partial, part_cap);
     }
     if (rc >= 0) {
         const int ktiles = (L.kpad + 255) / 256;

@@ -88,13 +88,36 @@ def test_conv3d_backward(WS, B, R, cin, cout):
 # (bottleneck), the decoder concatenations 192 -> 64 and 96 -> 32, whose
 # output columns span two or more 64-wide blocks and whose backward-data
 # GEMM has more than 64 rows; and the weight gradient at B = 4, R = 64, where
-# the voxel reduction is split 1024 ways (the cap).
+# the voxel reduction is split 1024 ways (the cap). At R = 8 and 4 the
+# convolutions have too few 64 x 64 tiles to fill the chip and split their
+# reduction (k_conv_halo, and k_conv for the 192-channel input).
 PRODUCTION = [(1, 8, 128, 128), (1, 8, 192, 64), (2, 8, 96, 32), (1, 4, 48, 16)]
 
 
 @pytest.mark.parametrize("B,R,cin,cout", PRODUCTION)
 def test_conv3d_production_widths(WS, B, R, cin, cout):
     r = np.random.default_rng(400 + R + cin + cout)
+    x = f32(r.standard_normal((B, R, R, R, cin)))
+    w = f32(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    b = f32(r.standard_normal(cout))
+    dz = f32(r.standard_normal((B, R, R, R, cout)))
+    y = host(WS.conv3d(dev(x), dev(w), dev(b), act=True))
+    ref = W.leaky(W.conv3d(W.bf16(x), W.bf16(w), b))
+    dx, dw, db = (host(t) for t in WS.conv3d_backward(dev(x), dev(w), dev(dz)))
+    rdx, rdw, rdb = W.conv3d_backward(W.bf16(x), W.bf16(w), W.bf16(dz))
+    errs = rel(y, ref), rel(dx, rdx), rel(dw, rdw), rel(db, rdb)
+    print("conv3d B%d R%d %d->%d: y %.2e dx %.2e dw %.2e db %.2e" % ((B, R, cin, cout) + errs))
+    assert max(errs) <= 2e-5
+
+
+# Two to four 16-column groups in the narrow-layer kernel (at least 256
+# bricks of 4x4x16 voxels: B R^3 >= 65536): forward 16 -> 48, 32 -> 32,
+# 16 -> 64, and the data gradient of 48 -> 16 (48 output columns), the
+# shape of the finest decoder layer's backward pass.
+@pytest.mark.parametrize("B,R,cin,cout", [(2, 32, 16, 48), (2, 32, 32, 32), (2, 32, 16, 64),
+                                          (2, 32, 48, 16)])
+def test_conv3d_column_groups(WS, B, R, cin, cout):
+    r = np.random.default_rng(600 + cin + cout)
     x = f32(r.standard_normal((B, R, R, R, cin)))
     w = f32(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
     b = f32(r.standard_normal(cout))
