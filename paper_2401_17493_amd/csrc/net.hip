@@ -540,6 +540,132 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
         pb[(size_t)split * cdz + row0 + threadIdx.x] = bacc;
 }
 
+// Weight gradient of a layer with at most 16 outputs on 4x4x16 voxel bricks
+// (the finest level's layers). Split s takes bricks [s bps, (s + 1) bps).
+// Per brick, dz^T (16 outputs x 256 voxels) and, per 16-channel tile of the
+// input, its 6x6x18 neighbourhood transposed to channel planes are staged in
+// LDS; the neighbourhood is kept in three copies shifted by one x3 column, so
+// the 8 consecutive x3 voxels of every tap's B fragment are one aligned
+// 16-byte read. Every staged value then feeds all 27 taps instead of being
+// re-staged per tap as an im2col block. Wave w accumulates taps w, w + 4, ...
+// for all channel tiles over all its bricks; wave 0 also sums dz^T against a
+// fragment of ones (the bias gradient). Partial-sum layout as k_wgrad:
+// partial[s][co][t cin + ci]. Needs cin <= 16 CT, cin and cdz multiples of 8,
+// cdz <= 16 and l >= 4.
+constexpr int kWbPlane = 6 * 6 * 16 + 8;      // bf16 per channel plane of a shifted copy
+constexpr int kWbRow = 256 + 8;               // bf16 per dz^T row
+template <int CT>
+__global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __restrict__ dz,
+                                                     int cdz, int l, int nbricks, int bps,
+                                                     int kpad, float* __restrict__ partial,
+                                                     float* __restrict__ pb) {
+    __shared__ __align__(16) bf16 xs[3 * 16 * kWbPlane];   // [s3][c][a6 6 + b6][16]
+    __shared__ __align__(16) bf16 dzt[16 * kWbRow];        // [co][a 64 + b 16 + j]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int mask = (1 << l) - 1;
+    const int lb = l - 2, lb3 = l - 4;
+    const int cin = in.ca + in.cb;
+    const int split = blockIdx.x;
+    const int b0 = split * bps, b1 = min(nbricks, b0 + bps);
+    // rows cdz..15 of dz^T stay zero
+    for (int e = threadIdx.x; e < 16 * kWbRow; e += 256) dzt[e] = (bf16)0.f;
+    floatx4 acc[7][CT], accb = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ti = 0; ti < 7; ++ti)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ti][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+    // this lane's voxels in chunk c (32 voxels = rows (a, b0c), (a, b0c + 1)):
+    // a = c / 2, b = 2 (c % 2) + g / 2, j = 8 (g % 2) .. + 7
+    const int bg = g >> 1, jg = 8 * (g & 1);
+    for (int br = b0; br < b1; ++br) {
+        int bid = br;
+        const int o3 = (bid & ((1 << lb3) - 1)) << 4;
+        bid >>= lb3;
+        const int o2 = (bid & ((1 << lb) - 1)) << 2;
+        bid >>= lb;
+        const int o1 = (bid & ((1 << lb) - 1)) << 2;
+        const int bb = bid >> lb;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            __syncthreads();   // the previous tile's fragments have been read
+            if (ct == 0) {
+                // dz^T of the brick: voxel v = a 64 + b 16 + j, 8 channels per item
+                for (int e = threadIdx.x; e < 256 * (cdz >> 3); e += 256) {
+                    const int v = e & 255, cg = e >> 8;
+                    const int a = v >> 6, b = (v >> 4) & 3, j = v & 15;
+                    const bf16x8 d = *reinterpret_cast<const bf16x8*>(
+                        dz + vox(bb, o1 + a, o2 + b, o3 + j, l) * cdz + 8 * cg);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) dzt[(8 * cg + i) * kWbRow + v] = d[i];
+                }
+            }
+            // the neighbourhood of channels 16 ct .. 16 ct + 15: position
+            // (a6, b6, jj) is voxel o + (a6, b6, jj) - 1, stored at column
+            // jj - s3 of copy s3 (0 <= jj - s3 < 16)
+            for (int e = threadIdx.x; e < 648 * 2; e += 256) {
+                const int p = e >> 1, cg = e & 1;
+                const int a6 = p / 108, b6 = (p / 18) % 6, jj = p % 18;
+                const int c0 = 16 * ct + 8 * cg;
+                bf16x8 v = {};
+                if (c0 < cin)
+                    v = *reinterpret_cast<const bf16x8*>(
+                        in_ptr(in, l, bb, (o1 + a6 - 1) & mask, (o2 + b6 - 1) & mask,
+                               (o3 + jj - 1) & mask, c0));
+#pragma unroll
+                for (int s3 = 0; s3 < 3; ++s3) {
+                    const int j = jj - s3;
+                    if (j < 0 || j > 15) continue;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        xs[(s3 * 16 + 8 * cg + i) * kWbPlane + (a6 * 6 + b6) * 16 + j] = v[i];
+                }
+            }
+            __syncthreads();
+            for (int c = 0; c < 8; ++c) {
+                const int a = c >> 1, b = 2 * (c & 1) + bg;
+                const bf16x8 av =
+                    *reinterpret_cast<const bf16x8*>(dzt + li * kWbRow + a * 64 + b * 16 + jg);
+                if (ct == 0 && wave == 0)
+                    accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb, 0, 0, 0);
+#pragma unroll
+                for (int ti = 0; ti < 7; ++ti) {
+                    const int t = wave + 4 * ti;
+                    if (t < 27) {
+                        const int s3 = t % 3, d1 = t / 9, d2 = (t / 3) % 3;
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(
+                            xs + (s3 * 16 + li) * kWbPlane + ((a + d1) * 6 + b + d2) * 16 + jg);
+                        acc[ti][ct] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ti][ct], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // D[co = 4 g + r][ci = li] of tap t, channel tile ct
+#pragma unroll
+    for (int ti = 0; ti < 7; ++ti) {
+        const int t = wave + 4 * ti;
+        if (t >= 27) continue;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int ci = 16 * ct + li;
+            if (ci >= cin) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                partial[((size_t)split * 16 + 4 * g + r) * kpad + t * cin + ci] = acc[ti][ct][r];
+        }
+    }
+    if (pb && wave == 0 && li == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (4 * g + r < cdz) pb[(size_t)split * cdz + 4 * g + r] = accb[r];
+    }
+}
+
 // pb[s][c] = sum over the voxels of split s of dz[m][c]: the 256 threads
 // form (voxel lane, channel) pairs, channels fastest (coalesced rows), and
 // the voxel lanes are folded in a fixed tree.
@@ -1213,6 +1339,32 @@ int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
                             fwd_part(n, batch), n->partial_cap);
 }
 
+#ifndef CLAIRE_WGRAD_BRICK
+#define CLAIRE_WGRAD_BRICK 1
+#endif
+
+// Launches k_wgrad_brick when the layer fits it (at most 16 outputs, at most
+// 48 input channels, x3 extent >= 16, whole bricks per split); false if not.
+bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt, int chunk,
+                 int splits, int nrows, int kpad, float* partial, float* pb, hipStream_t s) {
+    const int cin = in.ca + in.cb;
+    if (!CLAIRE_WGRAD_BRICK || nrows != 16 || cdz > 16 || (cdz & 7) || (in.ca & 7) ||
+        (in.cb & 7) || cin > 48 || l < 4 || (mt & 255) || (chunk & 255))
+        return false;
+    const int nbricks = (int)(mt / 256), bps = chunk / 256;
+    const dim3 grid((unsigned)splits), block(256);
+    if (cin <= 16)
+        hipLaunchKernelGGL(k_wgrad_brick<1>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
+                           kpad, partial, pb);
+    else if (cin <= 32)
+        hipLaunchKernelGGL(k_wgrad_brick<2>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
+                           kpad, partial, pb);
+    else
+        hipLaunchKernelGGL(k_wgrad_brick<3>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
+                           kpad, partial, pb);
+    return true;
+}
+
 // weight and bias gradient of layer li from its input view and dz
 int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, int batch) {
     const NetLayer& L = n->L[li];
@@ -1221,7 +1373,9 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
     wgrad_split(mt, splits, chunk);
     const int ktiles = (L.kpad + 255) / 256;
     const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-    if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0) {
+    if (wgrad_brick(in, dz, L.coutE, n->l - level, mt, chunk, splits, L.nrows, L.kpad,
+                    n->partial, n->pb, n->s)) {
+    } else if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0) {
         hipLaunchKernelGGL(k_wgrad_lds, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
                            (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows, n->pb);
     } else {
@@ -1685,7 +1839,9 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
     if (rc >= 0) {
         const int ktiles = (L.kpad + 255) / 256;
         const dim3 wgrid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-        if (kWgradLds && cin % 8 == 0 && cout % 8 == 0) {
+        if (wgrad_brick(one(S.x16, cin), S.dz16, cout, l, mt, chunk, splits, L.nrows, L.kpad,
+                        partial, pb, s)) {
+        } else if (kWgradLds && cin % 8 == 0 && cout % 8 == 0) {
             hipLaunchKernelGGL(k_wgrad_lds, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16,
                                cout, l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows, pb);
         } else {

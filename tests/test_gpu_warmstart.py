@@ -70,8 +70,11 @@ def test_conv3d_forward(WS, B, R, cin, cout, act):
     assert err <= 2e-5
 
 
+# (1, 16, 24, 8), (2, 16, 16, 16) and (2, 16, 32, 16) take the brick-staged
+# weight gradient (at most 16 outputs, x3 extent >= 16) with one partly
+# filled, one and two 16-channel tiles
 @pytest.mark.parametrize("B,R,cin,cout", [(2, 8, 8, 16), (1, 16, 24, 8), (2, 4, 48, 40),
-                                          (1, 2, 16, 8), (2, 16, 16, 16)])
+                                          (1, 2, 16, 8), (2, 16, 16, 16), (2, 16, 32, 16)])
 def test_conv3d_backward(WS, B, R, cin, cout):
     r = np.random.default_rng(200 + R + cin + cout)
     x = f32(r.standard_normal((B, R, R, R, cin)))
