@@ -1345,13 +1345,20 @@ int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
 
 // Launches k_wgrad_brick when the layer fits it (at most 16 outputs, at most
 // 48 input channels, x3 extent >= 16, whole bricks per split); false if not.
-bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt, int chunk,
-                 int splits, int nrows, int kpad, float* partial, float* pb, hipStream_t s) {
+constexpr int kBrickSplits = 512;   // two workgroups per CU in one round
+bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt, int& splits,
+                 int nrows, int kpad, float* partial, float* pb, hipStream_t s) {
     const int cin = in.ca + in.cb;
     if (!CLAIRE_WGRAD_BRICK || nrows != 16 || cdz > 16 || (cdz & 7) || (in.ca & 7) ||
-        (in.cb & 7) || cin > 48 || l < 4 || (mt & 255) || (chunk & 255))
+        (in.cb & 7) || cin > 48 || l < 4 || (mt & 255))
         return false;
-    const int nbricks = (int)(mt / 256), bps = chunk / 256;
+    // bricks per split: at most kBrickSplits splits (fewer partial sums to
+    // write and reduce), and no more than the partial buffer was sized for
+    const int nbricks = (int)(mt / 256);
+    int bps = (nbricks + kBrickSplits - 1) / kBrickSplits;
+    const int bmin = (nbricks + splits - 1) / splits;
+    if (bps < bmin) bps = bmin;
+    splits = (nbricks + bps - 1) / bps;
     const dim3 grid((unsigned)splits), block(256);
     if (cin <= 16)
         hipLaunchKernelGGL(k_wgrad_brick<1>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
@@ -1373,8 +1380,8 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
     wgrad_split(mt, splits, chunk);
     const int ktiles = (L.kpad + 255) / 256;
     const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-    if (wgrad_brick(in, dz, L.coutE, n->l - level, mt, chunk, splits, L.nrows, L.kpad,
-                    n->partial, n->pb, n->s)) {
+    if (wgrad_brick(in, dz, L.coutE, n->l - level, mt, splits, L.nrows, L.kpad, n->partial,
+                    n->pb, n->s)) {
     } else if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0) {
         hipLaunchKernelGGL(k_wgrad_lds, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
                            (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows, n->pb);
@@ -1839,7 +1846,7 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
     if (rc >= 0) {
         const int ktiles = (L.kpad + 255) / 256;
         const dim3 wgrid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
-        if (wgrad_brick(one(S.x16, cin), S.dz16, cout, l, mt, chunk, splits, L.nrows, L.kpad,
+        if (wgrad_brick(one(S.x16, cin), S.dz16, cout, l, mt, splits, L.nrows, L.kpad,
                         partial, pb, s)) {
         } else if (kWgradLds && cin % 8 == 0 && cout % 8 == 0) {
             hipLaunchKernelGGL(k_wgrad_lds, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16,
