@@ -540,8 +540,9 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
         pb[(size_t)split * cdz + row0 + threadIdx.x] = bacc;
 }
 
-// Weight gradient of a layer with at most 16 outputs on 4x4x16 voxel bricks
-// (the finest level's layers). Split s takes bricks [s bps, (s + 1) bps).
+// Weight gradient on 4x4x16 voxel bricks for up to 48 input channels; a
+// workgroup takes the 16 output rows 16 blockIdx.y .. + 15 of dz's cdz
+// (nrows = 16 gridDim.y). Split s takes bricks [s bps, (s + 1) bps).
 // Per brick, dz^T (16 outputs x 256 voxels) and, per 16-channel tile of the
 // input, its 6x6x18 neighbourhood transposed to channel planes are staged in
 // LDS; the neighbourhood is kept in three copies shifted by one x3 column, so
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
 // for all channel tiles over all its bricks; wave 0 also sums dz^T against a
 // fragment of ones (the bias gradient). Partial-sum layout as k_wgrad:
 // partial[s][co][t cin + ci]. Needs cin <= 16 CT, cin and cdz multiples of 8,
-// cdz <= 16 and l >= 4.
+// cdz <= nrows and l >= 4.
 constexpr int kWbPlane = 6 * 6 * 16 + 8;      // bf16 per channel plane of a shifted copy
 constexpr int kWbRow = 256 + 8;               // bf16 per dz^T row
 template <int CT>
@@ -568,7 +569,9 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
     const int cin = in.ca + in.cb;
     const int split = blockIdx.x;
     const int b0 = split * bps, b1 = min(nbricks, b0 + bps);
-    // rows cdz..15 of dz^T stay zero
+    const int row0 = 16 * blockIdx.y, nrows = 16 * gridDim.y;
+    const int rows = min(16, cdz - row0);       // valid rows of this tile, a multiple of 8
+    // rows beyond cdz of dz^T stay zero
     for (int e = threadIdx.x; e < 16 * kWbRow; e += 256) dzt[e] = (bf16)0.f;
     floatx4 acc[7][CT], accb = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -594,11 +597,11 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
             __syncthreads();   // the previous tile's fragments have been read
             if (ct == 0) {
                 // dz^T of the brick: voxel v = a 64 + b 16 + j, 8 channels per item
-                for (int e = threadIdx.x; e < 256 * (cdz >> 3); e += 256) {
+                for (int e = threadIdx.x; e < 256 * (rows >> 3); e += 256) {
                     const int v = e & 255, cg = e >> 8;
                     const int a = v >> 6, b = (v >> 4) & 3, j = v & 15;
                     const bf16x8 d = *reinterpret_cast<const bf16x8*>(
-                        dz + vox(bb, o1 + a, o2 + b, o3 + j, l) * cdz + 8 * cg);
+                        dz + vox(bb, o1 + a, o2 + b, o3 + j, l) * cdz + row0 + 8 * cg);
 #pragma unroll
                     for (int i = 0; i < 8; ++i) dzt[(8 * cg + i) * kWbRow + v] = d[i];
                 }
@@ -656,13 +659,14 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
             if (ci >= cin) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                partial[((size_t)split * 16 + 4 * g + r) * kpad + t * cin + ci] = acc[ti][ct][r];
+                partial[((size_t)split * nrows + row0 + 4 * g + r) * kpad + t * cin + ci] =
+                    acc[ti][ct][r];
         }
     }
     if (pb && wave == 0 && li == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (4 * g + r < cdz) pb[(size_t)split * cdz + 4 * g + r] = accb[r];
+            if (4 * g + r < rows) pb[(size_t)split * cdz + row0 + 4 * g + r] = accb[r];
     }
 }
 
@@ -1343,14 +1347,14 @@ int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
 #define CLAIRE_WGRAD_BRICK 1
 #endif
 
-// Launches k_wgrad_brick when the layer fits it (at most 16 outputs, at most
-// 48 input channels, x3 extent >= 16, whole bricks per split); false if not.
+// Launches k_wgrad_brick when the layer fits it (at most 64 outputs, at most
+// 48 input channels, x3 extent >= 16); false if not.
 constexpr int kBrickSplits = 512;   // two workgroups per CU in one round
 bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt, int& splits,
                  int nrows, int kpad, float* partial, float* pb, hipStream_t s) {
     const int cin = in.ca + in.cb;
-    if (!CLAIRE_WGRAD_BRICK || nrows != 16 || cdz > 16 || (cdz & 7) || (in.ca & 7) ||
-        (in.cb & 7) || cin > 48 || l < 4 || (mt & 255))
+    if (!CLAIRE_WGRAD_BRICK || nrows > 64 || (nrows & 15) || cdz > nrows || (cdz & 7) ||
+        (in.ca & 7) || (in.cb & 7) || cin > 48 || l < 4 || (mt & 255))
         return false;
     // bricks per split: at most kBrickSplits splits (fewer partial sums to
     // write and reduce), and no more than the partial buffer was sized for
@@ -1359,7 +1363,7 @@ bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt,
     const int bmin = (nbricks + splits - 1) / splits;
     if (bps < bmin) bps = bmin;
     splits = (nbricks + bps - 1) / bps;
-    const dim3 grid((unsigned)splits), block(256);
+    const dim3 grid((unsigned)splits, (unsigned)(nrows / 16)), block(256);
     if (cin <= 16)
         hipLaunchKernelGGL(k_wgrad_brick<1>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
                            kpad, partial, pb);
