@@ -540,9 +540,10 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
         pb[(size_t)split * cdz + row0 + threadIdx.x] = bacc;
 }
 
-// Weight gradient on 4x4x16 voxel bricks for up to 48 input channels; a
-// workgroup takes the 16 output rows 16 blockIdx.y .. + 15 of dz's cdz
-// (nrows = 16 gridDim.y). Split s takes bricks [s bps, (s + 1) bps).
+// Weight gradient on 4x4x16 voxel bricks; a workgroup takes the 16 output
+// rows 16 blockIdx.y .. + 15 of dz's cdz (nrows = 16 gridDim.y) and the CT
+// 16-channel tiles from 16 CT blockIdx.z of the input. Split s takes bricks
+// [s bps, (s + 1) bps).
 // Per brick, dz^T (16 outputs x 256 voxels) and, per 16-channel tile of the
 // input, its 6x6x18 neighbourhood transposed to channel planes are staged in
 // LDS; the neighbourhood is kept in three copies shifted by one x3 column, so
@@ -551,8 +552,8 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(ConvIn in, const bf16* __rest
 // re-staged per tap as an im2col block. Wave w accumulates taps w, w + 4, ...
 // for all channel tiles over all its bricks; wave 0 also sums dz^T against a
 // fragment of ones (the bias gradient). Partial-sum layout as k_wgrad:
-// partial[s][co][t cin + ci]. Needs cin <= 16 CT, cin and cdz multiples of 8,
-// cdz <= nrows and l >= 4.
+// partial[s][co][t cin + ci]. Needs cin <= 16 CT gridDim.z, cin and cdz
+// multiples of 8, cdz <= nrows and l >= 4.
 constexpr int kWbPlane = 6 * 6 * 16 + 8;      // bf16 per channel plane of a shifted copy
 constexpr int kWbRow = 256 + 8;               // bf16 per dz^T row
 template <int CT>
@@ -606,13 +607,13 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
                     for (int i = 0; i < 8; ++i) dzt[(8 * cg + i) * kWbRow + v] = d[i];
                 }
             }
-            // the neighbourhood of channels 16 ct .. 16 ct + 15: position
+            // the neighbourhood of channels 16 (CT z + ct) + 0..15: position
             // (a6, b6, jj) is voxel o + (a6, b6, jj) - 1, stored at column
             // jj - s3 of copy s3 (0 <= jj - s3 < 16)
             for (int e = threadIdx.x; e < 648 * 2; e += 256) {
                 const int p = e >> 1, cg = e & 1;
                 const int a6 = p / 108, b6 = (p / 18) % 6, jj = p % 18;
-                const int c0 = 16 * ct + 8 * cg;
+                const int c0 = 16 * (CT * (int)blockIdx.z + ct) + 8 * cg;
                 bf16x8 v = {};
                 if (c0 < cin)
                     v = *reinterpret_cast<const bf16x8*>(
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
         if (t >= 27) continue;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            const int ci = 16 * ct + li;
+            const int ci = 16 * (CT * (int)blockIdx.z + ct) + li;
             if (ci >= cin) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(256) void k_wgrad_brick(ConvIn in, const bf16* __re
                     acc[ti][ct][r];
         }
     }
-    if (pb && wave == 0 && li == 0) {
+    if (pb && blockIdx.z == 0 && wave == 0 && li == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (4 * g + r < rows) pb[(size_t)split * cdz + row0 + 4 * g + r] = accb[r];
@@ -1348,26 +1349,34 @@ int net_forward(claire_net* n, const float* m0, const float* m1, int batch) {
 #endif
 
 // Launches k_wgrad_brick when the layer fits it (at most 64 outputs, at most
-// 48 input channels, x3 extent >= 16); false if not.
-constexpr int kBrickSplits = 512;   // two workgroups per CU in one round
+// 192 input channels, x3 extent >= 16); false if not.
+constexpr int kBrickWgs = 512;   // two workgroups per CU in one round
 bool wgrad_brick(const ConvIn& in, const bf16* dz, int cdz, int l, long long mt, int& splits,
-                 int nrows, int kpad, float* partial, float* pb, hipStream_t s) {
+                 int nrows, int kpad, float* partial, long long part_cap, float* pb,
+                 long long pb_cap, hipStream_t s) {
     const int cin = in.ca + in.cb;
     if (!CLAIRE_WGRAD_BRICK || nrows > 64 || (nrows & 15) || cdz > nrows || (cdz & 7) ||
-        (in.ca & 7) || (in.cb & 7) || cin > 48 || l < 4 || (mt & 255))
+        (in.ca & 7) || (in.cb & 7) || cin > 192 || l < 4 || (mt & 255))
         return false;
-    // bricks per split: at most kBrickSplits splits (fewer partial sums to
-    // write and reduce), and no more than the partial buffer was sized for
+    // channel tiles of 16, in groups of at most 3 per workgroup (the
+    // accumulators of 7 taps x 3 tiles)
+    const int tiles = (cin + 15) / 16, groups = (tiles + 2) / 3;
+    const int ct = (tiles + groups - 1) / groups;
+    // bricks per split: about kBrickWgs workgroups over splits, row tiles and
+    // channel groups (fewer splits, fewer partial sums to write and reduce),
+    // and no more splits than the partial buffers hold
     const int nbricks = (int)(mt / 256);
-    int bps = (nbricks + kBrickSplits - 1) / kBrickSplits;
-    const int bmin = (nbricks + splits - 1) / splits;
-    if (bps < bmin) bps = bmin;
-    splits = (nbricks + bps - 1) / bps;
-    const dim3 grid((unsigned)splits, (unsigned)(nrows / 16)), block(256);
-    if (cin <= 16)
+    int want = kBrickWgs / ((nrows / 16) * groups);
+    if (want < 1) want = 1;
+    int bps = (nbricks + want - 1) / want;
+    auto nsplit = [&](int b) { return (long long)((nbricks + b - 1) / b); };
+    while (nsplit(bps) * nrows * kpad > part_cap || nsplit(bps) * cdz > pb_cap) ++bps;
+    splits = (int)nsplit(bps);
+    const dim3 grid((unsigned)splits, (unsigned)(nrows / 16), (unsigned)groups), block(256);
+    if (ct == 1)
         hipLaunchKernelGGL(k_wgrad_brick<1>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
                            kpad, partial, pb);
-    else if (cin <= 32)
+    else if (ct == 2)
         hipLaunchKernelGGL(k_wgrad_brick<2>, grid, block, 0, s, in, dz, cdz, l, nbricks, bps,
                            kpad, partial, pb);
     else
@@ -1385,7 +1394,7 @@ int wgrad(claire_net* n, int li, const ConvIn& in, const bf16* dz, int level, in
     const int ktiles = (L.kpad + 255) / 256;
     const dim3 grid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
     if (wgrad_brick(in, dz, L.coutE, n->l - level, mt, splits, L.nrows, L.kpad, n->partial,
-                    n->pb, n->s)) {
+                    n->partial_cap, n->pb, n->pb_cap, n->s)) {
     } else if (kWgradLds && in.ca % 8 == 0 && in.cb % 8 == 0 && L.coutE % 8 == 0) {
         hipLaunchKernelGGL(k_wgrad_lds, grid, dim3(256), 0, n->s, in, dz, L.coutE, n->l - level,
                            (int)mt, L.kpad, ktiles, chunk, n->partial, L.nrows, n->pb);
@@ -1851,7 +1860,7 @@ int claire_conv3d_backward(const float* x, const float* w, const float* dz, int 
         const int ktiles = (L.kpad + 255) / 256;
         const dim3 wgrid((unsigned)((L.nrows / 16) * ktiles), (unsigned)splits);
         if (wgrad_brick(one(S.x16, cin), S.dz16, cout, l, mt, splits, L.nrows, L.kpad,
-                        partial, pb, s)) {
+                        partial, part_cap, pb, (long long)splits * L.coutE, s)) {
         } else if (kWgradLds && cin % 8 == 0 && cout % 8 == 0) {
             hipLaunchKernelGGL(k_wgrad_lds, wgrid, dim3(256), 0, s, one(S.x16, cin), S.dz16,
                                cout, l, (int)mt, L.kpad, ktiles, chunk, partial, L.nrows, pb);

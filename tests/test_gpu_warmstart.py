@@ -134,6 +134,22 @@ def test_conv3d_column_groups(WS, B, R, cin, cout):
     assert max(errs) <= 2e-5
 
 
+# Weight gradients of wide inputs on 16^3 bricks: the input's 16-channel
+# tiles are dealt to 2 or 4 workgroup groups of at most three (64 -> 64,
+# 96 -> 32, 192 -> 64), with 2 and 4 tiles of 16 output rows.
+@pytest.mark.parametrize("B,R,cin,cout", [(4, 16, 64, 64), (2, 16, 96, 32), (2, 16, 192, 64)])
+def test_conv3d_backward_channel_groups(WS, B, R, cin, cout):
+    r = np.random.default_rng(700 + cin + cout)
+    x = f32(r.standard_normal((B, R, R, R, cin)))
+    w = f32(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    dz = f32(r.standard_normal((B, R, R, R, cout)))
+    dx, dw, db = (host(t) for t in WS.conv3d_backward(dev(x), dev(w), dev(dz)))
+    rdx, rdw, rdb = W.conv3d_backward(W.bf16(x), W.bf16(w), W.bf16(dz))
+    errs = rel(dx, rdx), rel(dw, rdw), rel(db, rdb)
+    print("conv3d backward B%d R%d %d->%d: dx %.2e dw %.2e db %.2e" % ((B, R, cin, cout) + errs))
+    assert max(errs) <= 2e-5
+
+
 def test_wgrad_split_cap(WS):
     # B R^3 = 4 * 64^3 voxels: 2048 chunks of 512 would be needed, the split
     # count is capped at 1024 (chunks of 1024 voxels)
