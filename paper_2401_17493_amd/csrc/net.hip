@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
     }
 }
 
-// Narrow layers (at most 16 x NG output columns, e.g. the 16-channel layers at
+// Narrow layers (at most 16 x NG output columns, NG <= 6, e.g. the 16-channel layers at
 // the network's finest level): a workgroup owns a 4x4x16 voxel brick; wave w
 // takes its x1 plane w as four rows of 16 x3 voxels, four MFMA tiles along
 // the voxels that share each weight fragment, so one 16-byte weight load
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
 // k_conv_halo.
 constexpr int kNarrowPos = 6 * 6 * 18;
 constexpr int kNarrowMaxC = 48;                // input channels the LDS tile may hold (62 KB)
-constexpr int kNarrowMaxNG = 4;                // column groups of 16
+constexpr int kNarrowMaxNG = 6;                // column groups of 16
 template <int EPI, int NG>
 __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __restrict__ wt,
                                                      int kpad, int cout, int l, ConvOut out) {
@@ -1241,7 +1241,7 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
          const ConvOut& out, hipStream_t s, float* part = nullptr, long long part_cap = 0) {
     const int cin = in.ca + in.cb;
     // the halo kernels tile the grid by 4x4x4 or 4x4x16 bricks (mtot = batch 8^l);
-    // the narrow kernel takes up to 4 column groups where its 256-voxel bricks
+    // the narrow kernel takes up to 6 column groups where its 256-voxel bricks
     // still give at least 256 workgroups
     const int ng = nrows / 16;
     const bool narrow = CLAIRE_CONV_NARROW && nrows <= 16 * kNarrowMaxNG && l >= 4 &&
@@ -1264,8 +1264,14 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
         else if (ng == 3)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 3>), ngrid, dim3(256), lds, s, in, wt, kpad,
                                cout, l, out);
-        else
+        else if (ng == 4)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 4>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
+        else if (ng == 5)
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 5>), ngrid, dim3(256), lds, s, in, wt, kpad,
+                               cout, l, out);
+        else
+            hipLaunchKernelGGL((k_conv_narrow<EPI, 6>), ngrid, dim3(256), lds, s, in, wt, kpad,
                                cout, l, out);
     } else if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
                (mtot & 63) == 0) {

@@ -113,12 +113,13 @@ def test_conv3d_production_widths(WS, B, R, cin, cout):
     assert max(errs) <= 2e-5
 
 
-# Two to four 16-column groups in the narrow-layer kernel (at least 256
+# Two to six 16-column groups in the narrow-layer kernel (at least 256
 # bricks of 4x4x16 voxels: B R^3 >= 65536): forward 16 -> 48, 32 -> 32,
-# 16 -> 64, and the data gradient of 48 -> 16 (48 output columns), the
-# shape of the finest decoder layer's backward pass.
+# 16 -> 64, 32 -> 96, and the data gradients of 48 -> 16 and 96 -> 32 (48
+# and 96 output columns), the shapes of the two finest decoder layers'
+# backward passes.
 @pytest.mark.parametrize("B,R,cin,cout", [(2, 32, 16, 48), (2, 32, 32, 32), (2, 32, 16, 64),
-                                          (2, 32, 48, 16)])
+                                          (2, 32, 48, 16), (2, 32, 32, 96), (2, 32, 96, 32)])
 def test_conv3d_column_groups(WS, B, R, cin, cout):
     r = np.random.default_rng(600 + cin + cout)
     x = f32(r.standard_normal((B, R, R, R, cin)))
