@@ -288,12 +288,12 @@ __global__ __launch_bounds__(256) void k_conv_halo(ConvIn in, const bf16* __rest
 // staged in LDS once. Same fragments and summation order per output as
 // k_conv_halo.
 constexpr int kNarrowPos = 6 * 6 * 18;
-constexpr int kNarrowMaxC = 48;                // input channels the LDS tile may hold (62 KB)
+constexpr int kNarrowMaxC = 48;                // input channels staged at a time (62 KB)
 constexpr int kNarrowMaxNG = 6;                // column groups of 16
 template <int EPI, int NG>
 __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __restrict__ wt,
                                                      int kpad, int cout, int l, ConvOut out) {
-    extern __shared__ __align__(16) bf16 halo[];   // [648][cin]
+    extern __shared__ __align__(16) bf16 halo[];   // [648][cst]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int mask = (1 << l) - 1;
@@ -306,44 +306,55 @@ __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __re
     const int o1 = (bid & ((1 << lb) - 1)) << 2;
     const int bb = bid >> lb;
     const int cin = in.ca + in.cb;
-    const int c8 = cin >> 3;                       // 16-byte channel groups per voxel
-    // stage the neighbourhood: position p = (a, b, c) in 6 x 6 x 18, voxel o + (a, b, c) - 1
-    for (int e = threadIdx.x; e < kNarrowPos * c8; e += 256) {
-        const int p = e / c8, cg = e - p * c8;
-        const int a = p / 108, b = (p / 18) % 6, c = p % 18;
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(
-            in_ptr(in, l, bb, (o1 + a - 1) & mask, (o2 + b - 1) & mask, (o3 + c - 1) & mask,
-                   8 * cg));
-        *reinterpret_cast<bf16x8*>(halo + p * cin + 8 * cg) = v;
-    }
-    __syncthreads();
-    // this lane's A rows: voxels (wave, mt, li) of the brick, mt = 0..3
-    int t = 0, ci = 8 * g;
-    while (ci >= cin) { ci -= cin; ++t; }
+    // channels staged at a time: all of them, or chunks of kNarrowMaxC (then
+    // the reduction runs chunk by chunk, each over its taps and channels)
+    const int cst = cin <= kNarrowMaxC ? cin : kNarrowMaxC;
+    const int c8 = cst >> 3;                       // 16-byte channel groups per voxel
+    const int ksc = (27 * cst + 31) & ~31;         // reduction steps of a chunk x 32
     floatx4 acc[NG][4];
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[gi][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < kpad; kc += 32) {
-        bf16x8 bv[NG];
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi)
-            bv[gi] = *reinterpret_cast<const bf16x8*>(wt + (size_t)(gi * 16 + li) * kpad + kc +
-                                                      8 * g);
-        const int pt = t < 27 ? (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3 : 0;
-        const bf16* base = halo + (wave * 108 + li + pt) * cin + ci;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            bf16x8 av = {};
-            if (t < 27) av = *reinterpret_cast<const bf16x8*>(base + mt * 18 * cin);
-#pragma unroll
-            for (int gi = 0; gi < NG; ++gi)
-                acc[gi][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[gi], acc[gi][mt], 0,
-                                                                      0, 0);
+    for (int q0 = 0; q0 < cin; q0 += cst) {
+        if (q0) __syncthreads();   // the previous chunk's fragments have been read
+        // stage the neighbourhood: position p = (a, b, c) in 6 x 6 x 18, voxel
+        // o + (a, b, c) - 1, channels q0 .. q0 + cst - 1
+        for (int e = threadIdx.x; e < kNarrowPos * c8; e += 256) {
+            const int p = e / c8, cg = e - p * c8;
+            const int a = p / 108, b = (p / 18) % 6, c = p % 18;
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+                in_ptr(in, l, bb, (o1 + a - 1) & mask, (o2 + b - 1) & mask,
+                       (o3 + c - 1) & mask, q0 + 8 * cg));
+            *reinterpret_cast<bf16x8*>(halo + p * cst + 8 * cg) = v;
         }
-        ci += 32;
-        while (ci >= cin) { ci -= cin; ++t; }
+        __syncthreads();
+        // this lane's A rows: voxels (wave, mt, li) of the brick, mt = 0..3
+        int t = 0, ci = 8 * g;
+        while (ci >= cst) { ci -= cst; ++t; }
+        for (int kc = 0; kc < ksc; kc += 32) {
+            bf16x8 bv[NG];
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                bv[gi] = bf16x8{};
+                if (t < 27)
+                    bv[gi] = *reinterpret_cast<const bf16x8*>(
+                        wt + (size_t)(gi * 16 + li) * kpad + t * cin + q0 + ci);
+            }
+            const int pt = t < 27 ? (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3 : 0;
+            const bf16* base = halo + (wave * 108 + li + pt) * cst + ci;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                bf16x8 av = {};
+                if (t < 27) av = *reinterpret_cast<const bf16x8*>(base + mt * 18 * cst);
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi)
+                    acc[gi][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[gi],
+                                                                          acc[gi][mt], 0, 0, 0);
+            }
+            ci += 32;
+            while (ci >= cst) { ci -= cst; ++t; }
+        }
     }
     // results: rows 4 g + r of tile mt = brick voxel (wave, mt, 4 g + r), column 16 gi + li
 #pragma unroll
@@ -1245,15 +1256,15 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
     // still give at least 256 workgroups
     const int ng = nrows / 16;
     const bool narrow = CLAIRE_CONV_NARROW && nrows <= 16 * kNarrowMaxNG && l >= 4 &&
-                        cin <= kNarrowMaxC && (cin & 7) == 0 && (mtot & 255) == 0 &&
-                        (ng == 1 || mtot >= 256LL * 256);
+                        (cin <= kNarrowMaxC || cin % kNarrowMaxC == 0) && (cin & 7) == 0 &&
+                        (mtot & 255) == 0 && (ng == 1 || mtot >= 256LL * 256);
     // reduction splits: k_conv and k_conv_halo only
     int splits = part && !narrow ? conv_splits(mtot, nrows, kpad) : 1;
     if ((long long)splits * mtot * nrows > part_cap) splits = 1;
     const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64),
                     (unsigned)splits);
     if (narrow) {
-        const size_t lds = sizeof(bf16) * kNarrowPos * cin;
+        const size_t lds = sizeof(bf16) * kNarrowPos * (cin <= kNarrowMaxC ? cin : kNarrowMaxC);
         const dim3 ngrid((unsigned)(mtot / 256));
         if (ng == 1)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 1>), ngrid, dim3(256), lds, s, in, wt, kpad,
