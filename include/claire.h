@@ -81,9 +81,11 @@ typedef struct claire_opts {
                                    (Section 2.6). NULL: the single alpha argument. */
     int n_levels;               /* length of alpha_levels */
     int compute_det;            /* 1: report det F(1) statistics at the end */
-    int tol_from_zero;          /* 1: g_0 of the gtol test is the gradient at v = 0 (one
-                                   extra state + adjoint solve per level) instead of the
-                                   gradient at the initial guess, so a warm-started solve
+    int tol_from_zero;          /* 1: g_0 of the gtol test is the gradient at v = 0 instead
+                                   of the gradient at the initial guess (the plain model
+                                   forms it without transport solves: the state is m0 and
+                                   the adjoint m1 - m0 at all times; with beta > 0 one
+                                   extra state + adjoint solve per level), so a warm-started solve
                                    stops at the same gradient norm as one from v = 0; an
                                    initial guess whose objective is not finite or exceeds
                                    J(v = 0) is then replaced by v = 0 (first level) */
