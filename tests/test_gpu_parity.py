@@ -296,6 +296,9 @@ def test_initial_guess_fallback(C):
             assert st["status"] == 0 and st["initial_rejected"] == 1
             assert torch.equal(v, v_cold)
             assert (st["gn_iters"], st["matvecs"]) == (s_cold["gn_iters"], s_cold["matvecs"])
+            # ||g(v = 0)||_inf formed without transport solves equals the
+            # cold solve's first setup bit for bit
+            assert st["rel_grad"] == s_cold["rel_grad"]
         # near the solution (as a trained network's prediction is): kept
         v, st = ctx.solve(0.8 * v_cold, tol_from_zero=1)
         assert st["status"] == 0 and st["initial_rejected"] == 0
