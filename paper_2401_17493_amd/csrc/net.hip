@@ -292,7 +292,8 @@ constexpr int kNarrowMaxC = 48;                // input channels staged at a tim
 constexpr int kNarrowMaxNG = 6;                // column groups of 16
 template <int EPI, int NG>
 __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __restrict__ wt,
-                                                     int kpad, int cout, int l, ConvOut out) {
+                                                     int kpad, int cout, int l, ConvOut out,
+                                                     int cst) {
     extern __shared__ __align__(16) bf16 halo[];   // [648][cst]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
@@ -306,9 +307,9 @@ __global__ __launch_bounds__(256) void k_conv_narrow(ConvIn in, const bf16* __re
     const int o1 = (bid & ((1 << lb) - 1)) << 2;
     const int bb = bid >> lb;
     const int cin = in.ca + in.cb;
-    // channels staged at a time: all of them, or chunks of kNarrowMaxC (then
-    // the reduction runs chunk by chunk, each over its taps and channels)
-    const int cst = cin <= kNarrowMaxC ? cin : kNarrowMaxC;
+    // cst channels are staged at a time (a divisor of cin, a multiple of 8);
+    // with cst < cin the reduction runs chunk by chunk, each over its taps
+    // and channels
     const int c8 = cst >> 3;                       // 16-byte channel groups per voxel
     const int ksc = (27 * cst + 31) & ~31;         // reduction steps of a chunk x 32
     floatx4 acc[NG][4];
@@ -1247,6 +1248,10 @@ int reset_adam(claire_net* n) {
 #endif
 constexpr bool kWgradLds = CLAIRE_WGRAD_LDS;
 
+#ifndef CLAIRE_NARROW_SMALL_CHUNK
+#define CLAIRE_NARROW_SMALL_CHUNK 1
+#endif
+
 template <int EPI>
 int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l, long long mtot,
          const ConvOut& out, hipStream_t s, float* part = nullptr, long long part_cap = 0) {
@@ -1264,26 +1269,32 @@ int conv(const ConvIn& in, const bf16* wt, int kpad, int nrows, int cout, int l,
     const dim3 grid((unsigned)((mtot + 63) / 64), (unsigned)((nrows + 63) / 64),
                     (unsigned)splits);
     if (narrow) {
-        const size_t lds = sizeof(bf16) * kNarrowPos * (cin <= kNarrowMaxC ? cin : kNarrowMaxC);
+        // staged chunk: all channels up to kNarrowMaxC, else kNarrowMaxC; where
+        // the summation order may change (part given: batches above one),
+        // 24 or 16 channels, for more workgroups per CU
+        int cst = cin <= kNarrowMaxC ? cin : kNarrowMaxC;
+        if (part && CLAIRE_NARROW_SMALL_CHUNK)
+            cst = (cin % 24 == 0) ? 24 : (cin % 16 == 0 ? 16 : cst);
+        const size_t lds = sizeof(bf16) * kNarrowPos * cst;
         const dim3 ngrid((unsigned)(mtot / 256));
         if (ng == 1)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 1>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
         else if (ng == 2)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 2>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
         else if (ng == 3)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 3>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
         else if (ng == 4)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 4>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
         else if (ng == 5)
             hipLaunchKernelGGL((k_conv_narrow<EPI, 5>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
         else
             hipLaunchKernelGGL((k_conv_narrow<EPI, 6>), ngrid, dim3(256), lds, s, in, wt, kpad,
-                               cout, l, out);
+                               cout, l, out, cst);
     } else if (CLAIRE_CONV_HALO && l >= 2 && cin <= kHaloMaxC && (cin & 7) == 0 &&
                (mtot & 63) == 0) {
         const size_t lds = sizeof(bf16) * kHaloPos * cin;
