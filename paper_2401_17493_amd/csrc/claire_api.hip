@@ -393,13 +393,80 @@ int join_reg(claire_ctx* c) {
     return 0;
 }
 
+// PCG direction update (v~ += kappa s, s = z + mu s, as k_pcg_direction)
+// fused with the first incremental-state source of the next matvec,
+// w0 = -(h_t/2) grad m^0 . s for the new s (as k_inc_first forms it: the
+// product of component 1, then components 0 and 2 by fused multiply-adds,
+// the order the compiler gives that kernel), so the matvec need not read s
+// for it again. Four voxels per thread (n a multiple of 4); a no-op on a
+// bad curvature.
+namespace {
+constexpr int kDirThreads = 256;
+__device__ __forceinline__ float4 load4(const float* p) {
+    return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ float4 load4(const __half* p) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    const __half2 a = *reinterpret_cast<const __half2*>(&u.x);
+    const __half2 b = *reinterpret_cast<const __half2*>(&u.y);
+    return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
+}
+__device__ __forceinline__ float w0_of(float g0, float g1, float g2, float s0, float s1,
+                                       float s2, float half_ht) {
+    return -half_ht * fmaf(g2, s2, fmaf(g0, s0, g1 * s1));
+}
+template <typename GT>
+__global__ __launch_bounds__(kDirThreads) void k_pcg_direction_w0(
+    const float* __restrict__ z, float* __restrict__ sd, float* __restrict__ vt,
+    const GT* __restrict__ gm0, float* __restrict__ w0, long long n, float half_ht, PcgDev pd) {
+    if (!pcg_curv_ok(pd)) return;   // uniform over the grid
+    const float kappa = (float)(pd.sc[pd.rz] / pd.sc[pd.shs]);
+    const float mu = (float)(pd.sc[pd.rz_new] / pd.sc[pd.rz]);
+    const long long stride = (long long)gridDim.x * kDirThreads * 4;
+    for (long long i = ((long long)blockIdx.x * kDirThreads + threadIdx.x) * 4; i < n;
+         i += stride) {
+        float4 sn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float4 zz = load4(z + a * n + i);
+            float4 v = load4(sd + a * n + i), t = load4(vt + a * n + i);
+            t.x = fmaf(kappa, v.x, t.x); t.y = fmaf(kappa, v.y, t.y);
+            t.z = fmaf(kappa, v.z, t.z); t.w = fmaf(kappa, v.w, t.w);
+            v.x = fmaf(mu, v.x, zz.x); v.y = fmaf(mu, v.y, zz.y);
+            v.z = fmaf(mu, v.z, zz.z); v.w = fmaf(mu, v.w, zz.w);
+            *reinterpret_cast<float4*>(vt + a * n + i) = t;
+            *reinterpret_cast<float4*>(sd + a * n + i) = v;
+            sn[a] = v;
+        }
+        const float4 g0 = load4(gm0 + i), g1 = load4(gm0 + n + i), g2 = load4(gm0 + 2 * n + i);
+        float4 w;
+        w.x = w0_of(g0.x, g1.x, g2.x, sn[0].x, sn[1].x, sn[2].x, half_ht);
+        w.y = w0_of(g0.y, g1.y, g2.y, sn[0].y, sn[1].y, sn[2].y, half_ht);
+        w.z = w0_of(g0.z, g1.z, g2.z, sn[0].z, sn[1].z, sn[2].z, half_ht);
+        w.w = w0_of(g0.w, g1.w, g2.w, sn[0].w, sn[1].w, sn[2].w, half_ht);
+        *reinterpret_cast<float4*>(w0 + i) = w;
+    }
+}
+}  // namespace
+
+template <typename GT>
+int launch_pcg_direction_w0(claire_ctx* c, const GT* gm0, const PcgDev& pd) {
+    const long long n = c->g.n;
+    long long nb = (n / 4 + kDirThreads - 1) / kDirThreads;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_pcg_direction_w0<GT>, dim3((unsigned)nb), dim3(kDirThreads), 0, c->s,
+                       c->z, c->sd, c->vt, gm0, c->w0, n, (float)(0.5 / c->nt), pd);
+    CL_LAUNCH_CHECK();
+    return 0;
+}
+
 // GT: storage of grad m^j read by the matvec (float; __half in the mixed
 // path, whose only difference is these 16-bit reads -- the sources
 // f^j = -grad m^j . v~, the fields m~, lam~, A and the displacements stay
 // float32, R23).
 template <typename GT>
 int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
-                 const float* reg_part, int dot_slot, const PcgDev* als_pd) {
+                 const float* reg_part, int dot_slot, const PcgDev* als_pd, bool w0_ready) {
     const Geo& g = c->g;
     const long long n = g.n;
     const int nt = c->nt;
@@ -407,7 +474,8 @@ int matvec_steps(claire_ctx* c, const GT* gm, const float* vt, float* out,
     const bool fork = !reg_part;
     if (fork) CL_TRY(fork_reg(c, vt));
     // incremental state, forward in time; the last step writes lambda~^nt = -m~^nt
-    CL_TRY(launch_inc_state_first(g, gm, vt, c->w0, ht, c->s));
+    // (w0 may have been formed with the direction update that produced vt)
+    if (!w0_ready) CL_TRY(launch_inc_state_first(g, gm, vt, c->w0, ht, c->s));
     float* src = c->w0;
     float* nxt = c->w1;
     for (int j = 0; j < nt; ++j) {
@@ -459,13 +527,14 @@ int finish_ni_matvec(claire_ctx* c, const float* vt, float* out, const float* re
 // recursion in reg_part (= c->als) with the device scalars of the previous
 // iteration and the residual c->r
 int run_matvec(claire_ctx* c, const float* vt, float* out, const float* reg_part = nullptr,
-               int dot_slot = -1, const PcgDev* als_pd = nullptr) {
+               int dot_slot = -1, const PcgDev* als_pd = nullptr, bool w0_ready = false) {
     if (als_pd && (c->beta > 0.0 || reg_part != c->als || dot_slot < 0)) {
         set_error("the als update rides only on the plain model's PCG matvec");
         return CLAIRE_EINVAL;
     }
-    if (c->precision == 1) return matvec_steps(c, c->gm16, vt, out, reg_part, dot_slot, als_pd);
-    return matvec_steps(c, c->gm, vt, out, reg_part, dot_slot, als_pd);
+    if (c->precision == 1)
+        return matvec_steps(c, c->gm16, vt, out, reg_part, dot_slot, als_pd, w0_ready);
+    return matvec_steps(c, c->gm, vt, out, reg_part, dot_slot, als_pd, w0_ready);
 }
 
 // Objective of a trial velocity held in c->v: backtrace, state, mismatch.
@@ -576,12 +645,18 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
     // plain model, (alpha L)^{-1}: the als update of each direction after the
     // first rides on the next matvec's assembly
     const bool als_fused = !two && !(c->beta > 0.0);
+    // the direction update also forms the next matvec's first source w0
+    auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    const bool w0_fused = (n & 3) == 0 && a16(c->z) && a16(c->sd) && a16(c->vt) &&
+                          a16(c->w0) && a16(c->gm) && (c->precision != 1 || a16(c->gm16));
+    bool w0_ready = false;
     PcgDev prev;
     bool have_prev = false;
     while (res.its < limit) {
         // <s, Hs> -> slot 0
         CL_TRY(run_matvec(c, c->sd, c->hs, two ? nullptr : c->als, 0,
-                          als_fused && have_prev ? &prev : nullptr));
+                          als_fused && have_prev ? &prev : nullptr, w0_ready));
+        w0_ready = false;
         ++res.its;
         if (res.its == limit) {
             // last matvec: r -= kappa Hs and v~ += kappa s, no preconditioner
@@ -609,7 +684,13 @@ int run_pcg(claire_ctx* c, const claire_opts& o, PcgResult& res) {
         CL_HIP(hipEventRecord(c->ev_pcg, s));
         // v~ += kappa s, s = z + mu s, als: needed unless the test below stops
         // the solve, and v~ is right in that case too
-        CL_TRY(launch_pcg_direction_dev(c->z, c->sd, c->vt, pd, n3, s));
+        if (w0_fused) {
+            CL_TRY(c->precision == 1 ? launch_pcg_direction_w0(c, c->gm16, pd)
+                                     : launch_pcg_direction_w0(c, c->gm, pd));
+            w0_ready = true;
+        } else {
+            CL_TRY(launch_pcg_direction_dev(c->z, c->sd, c->vt, pd, n3, s));
+        }
         if (!two && !als_fused) CL_TRY(launch_als_update_dev(c->r, c->als, pd, n, s));
         CL_HIP(hipEventSynchronize(c->ev_pcg));
         const int st = curvature_stop(c->red.host[0]);
